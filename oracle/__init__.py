@@ -1,0 +1,161 @@
+"""CPU oracle for the avalanche overlay hot path -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of ``bench.py`` may import this
+package. The product package (``paper_2506_23364_amd``) never imports it and shares no code with it.
+
+Two twins of one plain C source (``avl_oracle.c``): the FP32 oracle, which the GPU path must match
+bit-exactly on integer outputs, and the FP64 twin, which states the FP32 error. Both are loaded through
+ctypes from ``liboracle_f32.so`` / ``liboracle_f64.so`` next to this file (built by ``build.py``).
+
+Parity status of each function is recorded in the design notes; every function here is pinned by a
+test in ``tests/test_oracle_*.py`` against something other than itself (rocRAND's Philox, numpy's
+gradient and flatnonzero, closed forms of the friction law, scipy's bilinear interpolant, invariants).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import build as _build
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+
+END_LIMIT, END_EXIT, END_STOP = 0, 1, 2
+
+
+class OracleParams(ctypes.Structure):
+    _fields_ = [
+        ("mu", ctypes.c_float), ("xi", ctypes.c_float), ("flow_height", ctypes.c_float),
+        ("persistence", ctypes.c_float), ("randomness", ctypes.c_float), ("step_cells", ctypes.c_float),
+        ("tan_alpha", ctypes.c_float), ("flags", ctypes.c_uint32),
+    ]
+
+
+def make_params(mu=0.2, xi=2000.0, flow_height=1.0, persistence=0.9, randomness=0.16, step_cells=1.0,
+                tan_alpha=-1.0) -> OracleParams:
+    return OracleParams(mu, xi, flow_height, persistence, randomness, step_cells, tan_alpha, 0)
+
+
+_libs: dict = {}
+
+
+def _lib(prec: str):
+    if prec not in _libs:
+        path = os.path.join(_HERE, f"liboracle_{prec}.so")
+        if not os.path.exists(path):
+            _build.build()
+        lib = ctypes.CDLL(path)
+        _libs[prec] = lib
+    return _libs[prec]
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _real(prec: str):
+    return np.float32 if prec == "f32" else np.float64
+
+
+def philox(ctr, key, prec: str = "f32") -> np.ndarray:
+    """Philox4x32-10 block for a 4-word counter and 2-word key."""
+    c = np.asarray(ctr, dtype=np.uint32).copy()
+    k = np.asarray(key, dtype=np.uint32).copy()
+    out = np.zeros(4, dtype=np.uint32)
+    getattr(_lib(prec), f"oracle_philox4x32_10_{prec}")(_ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
+def normals(dem: np.ndarray, cell_size: float, prec: str = "f32") -> np.ndarray:
+    dem = np.ascontiguousarray(dem, dtype=np.float32)
+    h, w = dem.shape
+    out = np.zeros((h, w, 4), dtype=_real(prec))
+    getattr(_lib(prec), f"oracle_normals_{prec}")(_ptr(dem), ctypes.c_int(h), ctypes.c_int(w),
+                                                  ctypes.c_float(cell_size), _ptr(out))
+    return out
+
+
+def release_mask(nrm: np.ndarray, dem: np.ndarray, smin: float, smax: float, zmin: float, zmax: float,
+                 prec: str = "f32") -> np.ndarray:
+    nrm = np.ascontiguousarray(nrm, dtype=_real(prec))
+    dem = np.ascontiguousarray(dem, dtype=np.float32)
+    h, w = dem.shape
+    out = np.zeros((h, w), dtype=np.uint8)
+    getattr(_lib(prec), f"oracle_release_mask_{prec}")(
+        _ptr(nrm), _ptr(dem), ctypes.c_int(h), ctypes.c_int(w), ctypes.c_float(smin), ctypes.c_float(smax),
+        ctypes.c_float(zmin), ctypes.c_float(zmax), _ptr(out))
+    return out
+
+
+def compact(mask: np.ndarray) -> np.ndarray:
+    mask = np.ascontiguousarray(mask, dtype=np.uint8)
+    h, w = mask.shape
+    out = np.zeros(h * w, dtype=np.int32)
+    fn = _lib("f32").oracle_compact_f32
+    fn.restype = ctypes.c_int64
+    n = fn(_ptr(mask), ctypes.c_int(h), ctypes.c_int(w), _ptr(out))
+    return out[:n].copy()
+
+
+@dataclass
+class RunResult:
+    counts: np.ndarray
+    vmax: np.ndarray
+    steps: int
+    n_exit: int
+    n_stop: int
+    n_limit: int
+
+
+def trajectories(dem: np.ndarray, mask: np.ndarray, cell_size: float, params: OracleParams,
+                 particles_per_cell: int, step_limit: int, seed: int, run: int = 0,
+                 prec: str = "f32") -> RunResult:
+    dem = np.ascontiguousarray(dem, dtype=np.float32)
+    mask = np.ascontiguousarray(mask, dtype=np.uint8)
+    h, w = dem.shape
+    assert mask.shape == (h, w)
+    counts = np.zeros((h, w), dtype=np.uint32)
+    vmax = np.zeros((h, w), dtype=_real(prec))
+    stats = np.zeros(4, dtype=np.uint64)
+    getattr(_lib(prec), f"oracle_trajectories_{prec}")(
+        _ptr(dem), _ptr(mask), ctypes.c_int(h), ctypes.c_int(w), ctypes.c_float(cell_size),
+        ctypes.byref(params), ctypes.c_uint32(particles_per_cell), ctypes.c_uint32(step_limit),
+        ctypes.c_uint64(seed), ctypes.c_uint32(run), _ptr(counts), _ptr(vmax), _ptr(stats))
+    return RunResult(counts, vmax, int(stats[0]), int(stats[1]), int(stats[2]), int(stats[3]))
+
+
+@dataclass
+class Trace:
+    rows: np.ndarray  # (n, 8): x, y, z, gx, gy, dx, dy, v2
+    reason: int
+    steps: int
+
+    @property
+    def x(self): return self.rows[:, 0]
+
+    @property
+    def y(self): return self.rows[:, 1]
+
+    @property
+    def z(self): return self.rows[:, 2]
+
+    @property
+    def v2(self): return self.rows[:, 7]
+
+
+def trace(dem: np.ndarray, cell_size: float, params: OracleParams, r: int, c: int, replica: int,
+          step_limit: int, seed: int, run: int = 0, prec: str = "f32") -> Trace:
+    dem = np.ascontiguousarray(dem, dtype=np.float32)
+    h, w = dem.shape
+    buf = np.zeros((step_limit + 1, 8), dtype=_real(prec))
+    reason = ctypes.c_int32(0)
+    steps = ctypes.c_uint64(0)
+    fn = getattr(_lib(prec), f"oracle_trace_{prec}")
+    fn.restype = ctypes.c_int64
+    n = fn(_ptr(dem), ctypes.c_int(h), ctypes.c_int(w), ctypes.c_float(cell_size), ctypes.byref(params),
+           ctypes.c_int(r), ctypes.c_int(c), ctypes.c_uint32(replica), ctypes.c_uint32(step_limit),
+           ctypes.c_uint64(seed), ctypes.c_uint32(run), _ptr(buf), ctypes.byref(reason), ctypes.byref(steps))
+    return Trace(buf[:n].copy(), int(reason.value), int(steps.value))

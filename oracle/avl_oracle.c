@@ -1,0 +1,334 @@
+/*
+ * CPU oracle for the avalanche overlay hot path -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Only the test suite, the smoke check and the benchmark's CPU-baseline leg may load this code. The
+ * product library never links, loads or calls it, and the two share no code: the GPU path is written
+ * separately from the same model definition.
+ *
+ * Plain, slow, single-threaded C11. One source gives two twins:
+ *   - the FP32 oracle (default): every operation is IEEE binary32, round to nearest, evaluated in the
+ *     written order; build with -ffp-contract=off -fno-fast-math so no FMA is formed;
+ *   - the FP64 twin (-DAVL_F64): the same text in binary64, used to state the FP32 error.
+ * Inputs (the DEM, parameters) are float in both twins; the twin converts them exactly to double.
+ *
+ * What the paper fixes (section 5.2, Avalanches): a normals node over the DEM texels; a release-point
+ * node that keeps texels whose steepness lies in a user range; a trajectory node that releases a
+ * user-set number of particles per release texel and moves every particle with a persistence ratio
+ * (momentum), a user-set amount of random deviation from the optimal path and a runout-angle stop;
+ * its output is a per-texel velocity indicator (the maximal vertical displacement per step, figure 4)
+ * and the spread of mass. The paper gives no equations; the definitions below are the readings
+ * listed in the design notes (friction law, direction blend, random draw, accumulation, boundaries).
+ */
+#include <math.h>
+#include <stddef.h>
+#include <stdint.h>
+#include <string.h>
+
+#ifdef AVL_F64
+typedef double real;
+#define SQRT sqrt
+#define FLOOR floor
+#define NAME(x) x##_f64
+#else
+typedef float real;
+#define SQRT sqrtf
+#define FLOOR floorf
+#define NAME(x) x##_f32
+#endif
+
+#define R(v) ((real)(v))
+
+/* ----------------------------------------------------------------------------------------------
+ * Philox4x32-10 (Salmon, Moraes, Dror, Shaw: "Parallel random numbers: as easy as 1, 2, 3", SC'11).
+ * Ten rounds of the 4x32 bijection; each round multiplies words 0 and 2 by the two Philox constants,
+ * takes 64-bit products apart into high and low halves, and mixes in words 1 and 3 and the round key.
+ * The key is bumped by the two Weyl constants between rounds.
+ * ---------------------------------------------------------------------------------------------- */
+void NAME(oracle_philox4x32_10)(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        c0 = hi1 ^ c1 ^ k0;
+        c1 = lo1;
+        c2 = hi0 ^ c3 ^ k1;
+        c3 = lo0;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* Uniform in [0, 1) with 24 random bits: exact in binary32 and binary64. */
+static real unit24(uint32_t u) { return (real)(u >> 8) * R(0x1p-24); }
+
+/* The two uniforms of step n of particle (cell, replica) in run `run`: one Philox block serves two
+ * consecutive steps; even steps take words 0 and 1, odd steps words 2 and 3. Counter = (n/2, replica,
+ * release cell index r*W+c, run), key = the 64-bit seed as (low, high) words. */
+static void draw(uint32_t n, uint32_t replica, uint32_t cell, uint32_t run, uint64_t seed, real* rx, real* ry)
+{
+    uint32_t ctr[4] = {n >> 1, replica, cell, run};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t o[4];
+    NAME(oracle_philox4x32_10)(ctr, key, o);
+    uint32_t ux = (n & 1u) ? o[2] : o[0];
+    uint32_t uy = (n & 1u) ? o[3] : o[1];
+    *rx = R(2) * unit24(ux) - R(1);
+    *ry = R(2) * unit24(uy) - R(1);
+}
+
+static int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+/* ----------------------------------------------------------------------------------------------
+ * Normals and steepness (section 5.2: the normals node, per DEM texel; section 5.1 uses the same
+ * node). Gradient by the textbook finite difference: central (z[i+1]-z[i-1])/(2 cs) inside, one-sided
+ * (z[1]-z[0])/cs and (z[n-1]-z[n-2])/cs at the two edges. x runs along columns, y along rows.
+ * Unit normal n = (-gx, -gy, 1)/sqrt(gx^2+gy^2+1). Channel 3 is the slope angle in degrees, for display.
+ * Output: 4 reals per cell, row-major.
+ * ---------------------------------------------------------------------------------------------- */
+void NAME(oracle_normals)(const float* dem, int H, int W, float cell_size, real* out4)
+{
+    const real cs = (real)cell_size;
+    const real cs2 = R(2) * cs;
+    for (int r = 0; r < H; ++r) {
+        for (int c = 0; c < W; ++c) {
+            real gx, gy;
+            if (c == 0)          gx = ((real)dem[(size_t)r * W + 1] - (real)dem[(size_t)r * W]) / cs;
+            else if (c == W - 1) gx = ((real)dem[(size_t)r * W + W - 1] - (real)dem[(size_t)r * W + W - 2]) / cs;
+            else                 gx = ((real)dem[(size_t)r * W + c + 1] - (real)dem[(size_t)r * W + c - 1]) / cs2;
+            if (r == 0)          gy = ((real)dem[(size_t)W + c] - (real)dem[c]) / cs;
+            else if (r == H - 1) gy = ((real)dem[(size_t)(H - 1) * W + c] - (real)dem[(size_t)(H - 2) * W + c]) / cs;
+            else                 gy = ((real)dem[(size_t)(r + 1) * W + c] - (real)dem[(size_t)(r - 1) * W + c]) / cs2;
+            real gg = gx * gx + gy * gy;
+            real l = SQRT(gg + R(1));
+            real* o = out4 + 4 * ((size_t)r * W + c);
+            o[0] = -(gx / l);
+            o[1] = -(gy / l);
+            o[2] = R(1) / l;
+            o[3] = (real)(atan(sqrt((double)gg)) * (180.0 / 3.14159265358979323846));
+        }
+    }
+}
+
+/* ----------------------------------------------------------------------------------------------
+ * Release mask (section 5.2: the release-point node keeps texels whose steepness lies in the user's
+ * range; the elevation window is an added criterion). Steepness theta lies in [smin, smax] exactly
+ * when nz = cos(theta) lies in [cos(smax), cos(smin)]; the two cosines are taken in binary64 from
+ * degrees * (pi/180) and rounded once to the working precision. Bounds are inclusive.
+ * ---------------------------------------------------------------------------------------------- */
+void NAME(oracle_release_mask)(const real* normals4, const float* dem, int H, int W, float smin_deg,
+                               float smax_deg, float z_min, float z_max, uint8_t* mask)
+{
+    const double d2r = 3.14159265358979323846 / 180.0;
+    const real cmin = (real)cos((double)smax_deg * d2r);
+    const real cmax = (real)cos((double)smin_deg * d2r);
+    for (size_t i = 0; i < (size_t)H * W; ++i) {
+        real nz = normals4[4 * i + 2];
+        real z = (real)dem[i];
+        mask[i] = (cmin <= nz && nz <= cmax && (real)z_min <= z && z <= (real)z_max) ? 1 : 0;
+    }
+}
+
+/* Release-cell list: linear indices r*W+c of the set cells of the mask in row-major order. */
+int64_t NAME(oracle_compact)(const uint8_t* mask, int H, int W, int32_t* cells)
+{
+    int64_t n = 0;
+    for (size_t i = 0; i < (size_t)H * W; ++i)
+        if (mask[i]) cells[n++] = (int32_t)i;
+    return n;
+}
+
+/* ----------------------------------------------------------------------------------------------
+ * Trajectory model (section 5.2, the trajectory node).
+ * ---------------------------------------------------------------------------------------------- */
+typedef struct {
+    float mu;          /* Coulomb friction coefficient (>= 0) */
+    float xi;          /* Voellmy turbulence coefficient in m/s^2 (> 0, +inf = no drag) */
+    float flow_height; /* m (> 0) */
+    float persistence; /* weight of the previous direction, [0, 1] */
+    float randomness;  /* amplitude of the random deviation, >= 0 */
+    float step_cells;  /* horizontal step length in cells (> 0) */
+    float tan_alpha;   /* runout-angle stop: tan of the angle; < 0 disables */
+    uint32_t flags;    /* unused by the oracle */
+} oracle_params;
+
+typedef struct {
+    const float* dem;
+    int H, W;
+    real cs, g2, per, Q, rnd, L, dl2, mdl, cd, tca;
+    int use_alpha;
+    uint32_t S, run;
+    uint64_t seed;
+} model;
+
+static void model_init(model* m, const float* dem, int H, int W, float cell_size, const oracle_params* p,
+                       uint32_t S, uint64_t seed, uint32_t run)
+{
+    m->dem = dem; m->H = H; m->W = W;
+    m->cs = (real)cell_size;
+    const real g = R(9.81);
+    m->g2 = g + g;                                    /* 2g */
+    m->per = (real)p->persistence;
+    m->Q = R(1) - m->per;                             /* weight of the downslope direction */
+    m->rnd = (real)p->randomness;
+    m->L = (real)p->step_cells;
+    const real dl = m->L * m->cs;                     /* horizontal step length, m */
+    m->dl2 = dl * dl;
+    m->mdl = (real)p->mu * dl;                        /* Coulomb loss height per step, m */
+    m->cd = m->g2 / ((real)p->xi * (real)p->flow_height); /* 2g/(xi h), 1/m; 0 when xi = +inf */
+    m->use_alpha = p->tan_alpha >= 0.0f;
+    m->tca = (real)p->tan_alpha * m->cs;
+    m->S = S; m->run = run; m->seed = seed;
+}
+
+/* Bilinear height patch through the four texel centres around (x, y) (texel (r,c) sits at (c+.5, r+.5)),
+ * indices clamped to the grid. Returns the height and its exact gradient (metres per cell). */
+static void sample(const model* m, real x, real y, real* zz, real* gx, real* gy)
+{
+    real sx = x - R(0.5), sy = y - R(0.5);
+    real fc = FLOOR(sx), fr = FLOOR(sy);
+    real fx = sx - fc, fy = sy - fr;
+    int c0 = (int)fc, r0 = (int)fr;
+    int ca = clampi(c0, 0, m->W - 1), cb = clampi(c0 + 1, 0, m->W - 1);
+    int ra = clampi(r0, 0, m->H - 1), rb = clampi(r0 + 1, 0, m->H - 1);
+    real a = (real)m->dem[(size_t)ra * m->W + ca], b = (real)m->dem[(size_t)ra * m->W + cb];
+    real c = (real)m->dem[(size_t)rb * m->W + ca], d = (real)m->dem[(size_t)rb * m->W + cb];
+    real top = a + fx * (b - a);
+    real bot = c + fx * (d - c);
+    *zz = top + fy * (bot - top);
+    *gx = (b - a) + fy * ((d - c) - (b - a));
+    *gy = bot - top;
+}
+
+enum { END_LIMIT = 0, END_EXIT = 1, END_STOP = 2 };
+
+#define TRACE_COLS 8 /* x, y, z, gx, gy, dx, dy, v2 */
+
+/* One particle: released at the centre of cell (r, c), replica `replica`. Adds its cell entries to
+ * counts and its per-cell maximum of v^2 to vmax2 (either may be NULL). With a trace buffer of
+ * (S+1) rows, row 0 is the released state and row n+1 the state after step n. Returns the end reason;
+ * *steps gets the number of steps entered (the terminating one included); *rows the trace rows. */
+static int particle(const model* m, int r, int c, uint32_t replica, uint32_t* counts, real* vmax2,
+                    uint64_t* steps, real* trace, int64_t* rows)
+{
+    const int W = m->W, H = m->H;
+    const uint32_t cell_id = (uint32_t)r * (uint32_t)W + (uint32_t)c;
+    real x = (real)c + R(0.5), y = (real)r + R(0.5);
+    real z, gx, gy;
+    sample(m, x, y, &z, &gx, &gy);
+    const real x0 = x, y0 = y, zr = z;
+    /* initial direction: straight downslope (zero on flat ground) */
+    real dx = 0, dy = 0;
+    {
+        real gg = gx * gx + gy * gy;
+        if (gg > 0) {
+            real t = R(1) / SQRT(gg);
+            dx = -(gx * t);
+            dy = -(gy * t);
+        }
+    }
+    real v2 = 0;
+    int cr = r, cc = c;
+    if (counts) counts[(size_t)cr * W + cc] += 1; /* entry into the release cell, with v = 0 */
+    int64_t nrow = 0;
+    if (trace) {
+        real* t = trace + TRACE_COLS * nrow++;
+        t[0] = x; t[1] = y; t[2] = z; t[3] = gx; t[4] = gy; t[5] = dx; t[6] = dy; t[7] = v2;
+    }
+    int reason = END_LIMIT;
+    uint64_t n_steps = 0;
+    for (uint32_t n = 0; n < m->S; ++n) {
+        ++n_steps;
+        /* direction: persistence * previous + (1 - persistence) * downslope + randomness * uniform square */
+        real rx, ry;
+        draw(n, replica, cell_id, m->run, m->seed, &rx, &ry);
+        real gg = gx * gx + gy * gy;
+        real t = gg > 0 ? m->Q / SQRT(gg) : R(0);
+        real wx = (m->per * dx - t * gx) + m->rnd * rx;
+        real wy = (m->per * dy - t * gy) + m->rnd * ry;
+        real ww = wx * wx + wy * wy;
+        if (ww > 0) {
+            real s = R(1) / SQRT(ww);
+            dx = wx * s;
+            dy = wy * s;
+        }
+        /* move one step; leaving the grid ends the particle */
+        real x1 = x + m->L * dx;
+        real y1 = y + m->L * dy;
+        real fc = FLOOR(x1), fr = FLOOR(y1);
+        if (!(fc >= 0 && fc < (real)W && fr >= 0 && fr < (real)H)) { reason = END_EXIT; break; }
+        real z1, gx1, gy1;
+        sample(m, x1, y1, &z1, &gx1, &gy1);
+        /* kinetic energy: gravity work minus Coulomb loss; Voellmy drag taken implicitly over the path */
+        real dz = z - z1;
+        real ds = SQRT(m->dl2 + dz * dz);
+        real num = v2 + m->g2 * (dz - m->mdl);
+        if (!(num > 0)) { reason = END_STOP; break; }
+        real v2n = num / (R(1) + m->cd * ds);
+        if (m->use_alpha) {
+            real hx = x1 - x0, hy = y1 - y0;
+            if ((zr - z1) < m->tca * SQRT(hx * hx + hy * hy)) { reason = END_STOP; break; }
+        }
+        x = x1; y = y1; z = z1; gx = gx1; gy = gy1; v2 = v2n;
+        int ri = (int)fr, ci = (int)fc;
+        if (ri != cr || ci != cc) {
+            cr = ri; cc = ci;
+            if (counts) counts[(size_t)cr * W + cc] += 1;
+        }
+        if (vmax2 && v2 > vmax2[(size_t)cr * W + cc]) vmax2[(size_t)cr * W + cc] = v2;
+        if (trace) {
+            real* tr = trace + TRACE_COLS * nrow++;
+            tr[0] = x; tr[1] = y; tr[2] = z; tr[3] = gx; tr[4] = gy; tr[5] = dx; tr[6] = dy; tr[7] = v2;
+        }
+    }
+    *steps += n_steps;
+    if (rows) *rows = nrow;
+    return reason;
+}
+
+/* Whole run: particles_per_cell replicas from every set cell of the mask, cells in row-major order.
+ * counts (u32) and vmax (real) are H*W and fully overwritten; vmax is sqrt of the per-cell max of v^2
+ * (0 where no particle came). stats (may be NULL) gets {steps, ended by grid exit, by stop, by limit}. */
+int NAME(oracle_trajectories)(const float* dem, const uint8_t* mask, int H, int W, float cell_size,
+                              const oracle_params* p, uint32_t particles_per_cell, uint32_t step_limit,
+                              uint64_t seed, uint32_t run, uint32_t* counts, real* vmax, uint64_t* stats)
+{
+    model m;
+    model_init(&m, dem, H, W, cell_size, p, step_limit, seed, run);
+    const size_t N = (size_t)H * W;
+    memset(counts, 0, N * sizeof(uint32_t));
+    for (size_t i = 0; i < N; ++i) vmax[i] = 0; /* holds v^2 until the end */
+    uint64_t st[4] = {0, 0, 0, 0};
+    for (int r = 0; r < H; ++r)
+        for (int c = 0; c < W; ++c) {
+            if (!mask[(size_t)r * W + c]) continue;
+            for (uint32_t j = 0; j < particles_per_cell; ++j) {
+                int why = particle(&m, r, c, j, counts, vmax, &st[0], NULL, NULL);
+                st[why == END_EXIT ? 1 : (why == END_STOP ? 2 : 3)] += 1;
+            }
+        }
+    for (size_t i = 0; i < N; ++i) vmax[i] = SQRT(vmax[i]);
+    if (stats) memcpy(stats, st, sizeof st);
+    return 0;
+}
+
+/* Trace of one particle: trace must hold (step_limit+1)*8 reals. Returns the number of rows written;
+ * *reason gets 0 (step limit), 1 (left the grid) or 2 (stopped); *steps the steps entered. */
+int64_t NAME(oracle_trace)(const float* dem, int H, int W, float cell_size, const oracle_params* p,
+                           int r, int c, uint32_t replica, uint32_t step_limit, uint64_t seed, uint32_t run,
+                           real* trace, int32_t* reason, uint64_t* steps)
+{
+    model m;
+    model_init(&m, dem, H, W, cell_size, p, step_limit, seed, run);
+    int64_t rows = 0;
+    uint64_t st = 0;
+    *reason = particle(&m, r, c, replica, NULL, NULL, &st, trace, &rows);
+    *steps = st;
+    return rows;
+}
