@@ -1,0 +1,118 @@
+/*
+ * avl.h -- C ABI of libavl.so, the MI355X (gfx950) hot path of the data-driven avalanche overlay of
+ * "Data-Driven Compute Overlays for Interactive Geographic Simulation and Visualization"
+ * (arXiv 2506.23364), section 5.2 (Avalanches): normals from a DEM, a release-point map from a
+ * steepness range, and Monte-Carlo particle trajectories from every release texel, accumulated into a
+ * hit-count raster and a per-texel maximum-velocity raster (the velocity indicator of figure 4).
+ *
+ * Conventions shared by every entry point
+ *  - Rasters are row-major H x W (row r, column c at index r*W + c). x runs along columns, y along
+ *    rows; texel (r, c) covers [c, c+1) x [r, r+1) in cell units and its height sits at its centre.
+ *  - Every array argument is a DEVICE pointer on the current HIP device, allocated and owned by the
+ *    caller; the library never frees or keeps a caller pointer past the call. Scalars and the
+ *    parameter struct are host values. Outputs are overwritten completely.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream). All work is enqueued
+ *    asynchronously on it; the call returns after the launches, not after the work.
+ *  - Return value: AVL_OK (0) or a negative error code. Arguments are checked on the host before any
+ *    launch, so an error leaves every output untouched. avl_strerror() names a code and
+ *    avl_last_error() gives the detail of the last failure on the calling thread.
+ *  - Arithmetic is IEEE binary32, round to nearest, without contraction, in the order defined for
+ *    each call, so that integer results (counts, masks, cell lists) are reproducible bit for bit and
+ *    independent of launch shape, block order and XCD.
+ *  - Calls are thread-safe; concurrent calls must use distinct workspaces.
+ */
+#ifndef AVL_H
+#define AVL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__)
+#define AVL_API __attribute__((visibility("default")))
+#else
+#define AVL_API
+#endif
+
+#define AVL_OK 0
+#define AVL_EINVAL (-1) /* bad argument: null pointer, size, parameter range */
+#define AVL_ENOMEM (-2) /* workspace smaller than the size the matching *_workspace_bytes call returns */
+#define AVL_EHIP (-3)   /* HIP runtime or launch error; avl_last_error() has the HIP message */
+
+/* Model parameters of the trajectory node (section 5.2: persistence, runout angle, random variation,
+ * plus the friction law that turns the path into a speed). */
+typedef struct avl_params {
+    float mu;          /* Coulomb friction coefficient, finite, >= 0 */
+    float xi;          /* Voellmy turbulence coefficient in m/s^2, > 0; +INFINITY = no drag */
+    float flow_height; /* flow height h in metres, finite, > 0 */
+    float persistence; /* weight of the previous direction, in [0, 1] (the paper's default 0.9) */
+    float randomness;  /* amplitude of the random deviation, finite, >= 0 (the paper's default 0.16) */
+    float step_cells;  /* horizontal step length in cells, finite, in (0, 16] (default 1) */
+    float tan_alpha;   /* runout-angle stop: tan(alpha), finite; any negative value disables it */
+    uint32_t flags;    /* must be 0 */
+} avl_params;
+
+/* Surface normals and steepness (section 5.2, the normals node; section 5.1 shares it).
+ * dem: H*W float heights in metres. cell_size: texel edge in metres, finite, > 0. H, W >= 2.
+ * normals4: H*W*4 floats (16-byte aligned), per texel (nx, ny, nz, slope in degrees), with the gradient
+ *   gx = (z[r][c+1] - z[r][c-1]) / (2 cs) inside and the one-sided (z[r][1]-z[r][0]) / cs,
+ *   (z[r][W-1]-z[r][W-2]) / cs at the left/right edges (gy likewise along rows), l = sqrt(gx^2+gy^2+1),
+ *   n = (-(gx/l), -(gy/l), 1/l). The slope channel atan(sqrt(gx^2+gy^2)) in degrees is for display
+ *   (within a few ulp of the correctly rounded value); the release mask reads only nz. */
+AVL_API int avl_normals(const float* dem, int32_t H, int32_t W, float cell_size, float* normals4, void* stream);
+
+/* Release map (section 5.2, the release-point node: a steepness range per normal texel; an elevation
+ * window is added). mask[i] = 1 when cos(smax) <= nz <= cos(smin) and z_min <= dem[i] <= z_max, else 0.
+ * The cosines are taken on the host in binary64 from deg * (pi / 180) and rounded once to binary32.
+ * normals4 as written by avl_normals; 0 <= slope_min_deg <= slope_max_deg <= 90; z bounds may be
+ * +-INFINITY, not NaN. H, W >= 1. mask: H*W bytes. */
+AVL_API int avl_release_mask(const float* normals4, const float* dem, int32_t H, int32_t W, float slope_min_deg,
+                     float slope_max_deg, float z_min, float z_max, uint8_t* mask, void* stream);
+
+/* Workspace bytes that avl_release_cells and avl_trajectories need for an H x W grid. */
+AVL_API size_t avl_workspace_bytes(int32_t H, int32_t W);
+
+/* Release-cell list (particles are released per coded texel, section 5.2): the linear indices r*W+c
+ * of the nonzero bytes of mask in row-major order, into cells[0 .. n-1], and n into *n_cells (a device
+ * int32). cells must hold H*W entries. workspace: device memory of avl_workspace_bytes(H, W) bytes. */
+AVL_API int avl_release_cells(const uint8_t* mask, int32_t H, int32_t W, int32_t* cells, int32_t* n_cells,
+                      void* workspace, size_t workspace_bytes, void* stream);
+
+/* Particle trajectories (section 5.2, the trajectory node), one pass over every release texel.
+ *
+ * From each nonzero texel of mask (H*W bytes), particles_per_cell particles start at the texel
+ * centre with speed 0, heading straight downslope; particle (cell, j) draws its random deviation from
+ * Philox4x32-10 with counter (step/2, j, cell index r*W+c, run_id) and key (seed low, seed high) words,
+ * so its path does not depend on which other texels are released. Per step, in binary32:
+ *   direction w = (persistence*d - t*g) + randomness*(2u-1) with t = (1-persistence)/|g|, d = w/|w|;
+ *   move by step_cells*d; leaving the grid ends the particle;
+ *   height and gradient g from the bilinear patch through the four surrounding texel centres (indices
+ *   clamped to the grid); the speed follows the Coulomb/Voellmy energy step
+ *   v^2' = (v^2 + 2g(dz - mu*dl)) / (1 + 2g*ds/(xi*h)), dl = step_cells*cell_size, ds = sqrt(dl^2+dz^2);
+ *   a non-positive numerator stops the particle where it is, as does the optional runout angle;
+ *   at most step_limit steps.
+ * counts: H*W uint32, the number of particle entries into each texel (the release texel counts once
+ *   per particle). vmax: H*W float, the maximum speed (m/s) reached in each texel (0 if none).
+ * stats (nullable): 4 uint64 on the device: {steps, particles that left the grid, that stopped, that
+ *   reached step_limit}; "steps" counts every step entered, the terminating one included.
+ * particles_per_cell >= 1; dem, mask, counts, vmax as above; H, W >= 1; H*W < 2^31;
+ * workspace: avl_workspace_bytes(H, W) bytes of device memory, owned by the caller, not retained. */
+AVL_API int avl_trajectories(const float* dem, const uint8_t* mask, int32_t H, int32_t W, float cell_size,
+                     const avl_params* params, uint32_t particles_per_cell, uint32_t step_limit, uint64_t seed,
+                     uint32_t run_id, uint32_t* counts, float* vmax, uint64_t* stats, void* workspace,
+                     size_t workspace_bytes, void* stream);
+
+/* Name of an error code. Never NULL. */
+AVL_API const char* avl_strerror(int code);
+
+/* Detail of the last failed call on the calling thread ("" if none). Valid until the next call. */
+AVL_API const char* avl_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AVL_H */

@@ -1,0 +1,186 @@
+"""MI355X-native hot path of the data-driven avalanche overlay (arXiv 2506.23364, section 5.2).
+
+A thin binding over ``libavl.so`` (C ABI in ``include/avl.h``): it checks tensor types, allocates
+outputs and workspace through PyTorch, passes device pointers and the current HIP stream, and turns
+error codes into exceptions. Every step of the computation runs in the library's HIP kernels; there
+is no CPU fallback. If the library is not built, importing this package raises ImportError.
+
+Functions mirror the C entry points: :func:`normals`, :func:`release_mask`, :func:`release_cells`,
+:func:`trajectories`; :func:`overlay` chains them (DEM -> normals -> release map -> trajectories).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+__all__ = ["AvlError", "Params", "normals", "release_mask", "release_cells", "trajectories", "overlay",
+           "workspace_bytes", "LIB_PATH", "lib"]
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libavl.so")
+
+AVL_OK, AVL_EINVAL, AVL_ENOMEM, AVL_EHIP = 0, -1, -2, -3
+
+
+class AvlError(RuntimeError):
+    def __init__(self, code: int, where: str, detail: str):
+        super().__init__(f"{where}: error {code} ({detail})")
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    """Mirror of ``avl_params``."""
+    _fields_ = [
+        ("mu", ctypes.c_float), ("xi", ctypes.c_float), ("flow_height", ctypes.c_float),
+        ("persistence", ctypes.c_float), ("randomness", ctypes.c_float), ("step_cells", ctypes.c_float),
+        ("tan_alpha", ctypes.c_float), ("flags", ctypes.c_uint32),
+    ]
+
+    @classmethod
+    def make(cls, mu=0.2, xi=2000.0, flow_height=1.0, persistence=0.9, randomness=0.16, step_cells=1.0,
+             tan_alpha=-1.0, flags=0) -> "Params":
+        return cls(mu, xi, flow_height, persistence, randomness, step_cells, tan_alpha, flags)
+
+
+def _load() -> ctypes.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2506_23364_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, u32, u64, f32, sz = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32, ctypes.c_uint64,
+                                  ctypes.c_float, ctypes.c_size_t)
+    L.avl_normals.argtypes = [vp, i32, i32, f32, vp, vp]
+    L.avl_release_mask.argtypes = [vp, vp, i32, i32, f32, f32, f32, f32, vp, vp]
+    L.avl_workspace_bytes.argtypes = [i32, i32]
+    L.avl_workspace_bytes.restype = sz
+    L.avl_release_cells.argtypes = [vp, i32, i32, vp, vp, vp, sz, vp]
+    L.avl_trajectories.argtypes = [vp, vp, i32, i32, f32, ctypes.POINTER(Params), u32, u32, u64, u32, vp, vp, vp,
+                                   vp, sz, vp]
+    L.avl_strerror.argtypes = [ctypes.c_int]
+    L.avl_strerror.restype = ctypes.c_char_p
+    L.avl_last_error.argtypes = []
+    L.avl_last_error.restype = ctypes.c_char_p
+    for name in ("avl_normals", "avl_release_mask", "avl_release_cells", "avl_trajectories"):
+        getattr(L, name).restype = ctypes.c_int
+    return L
+
+
+lib = _load()
+
+
+def _check(code: int, where: str) -> None:
+    if code != AVL_OK:
+        raise AvlError(code, where, (lib.avl_last_error() or b"").decode() or lib.avl_strerror(code).decode())
+
+
+def _need(t: torch.Tensor, name: str, dtype: torch.dtype, dim: int | None = None) -> None:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor (there is no CPU path)")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dim is not None and t.dim() != dim:
+        raise ValueError(f"{name} must have {dim} dimensions")
+
+
+def _stream(dev: torch.device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+
+
+_ws: dict = {}
+
+
+def _workspace(dev: torch.device, nbytes: int) -> torch.Tensor:
+    """Per-device workspace, grown on demand and reused (calls on one stream are ordered)."""
+    key = dev.index if dev.index is not None else torch.cuda.current_device()
+    buf = _ws.get(key)
+    if buf is None or buf.numel() < nbytes:
+        buf = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=dev)
+        _ws[key] = buf
+    return buf
+
+
+def workspace_bytes(h: int, w: int) -> int:
+    return int(lib.avl_workspace_bytes(h, w))
+
+
+def normals(dem: torch.Tensor, cell_size: float) -> torch.Tensor:
+    """(H, W) float32 DEM -> (H, W, 4) float32 (nx, ny, nz, slope degrees)."""
+    _need(dem, "dem", torch.float32, 2)
+    h, w = dem.shape
+    out = torch.empty((h, w, 4), dtype=torch.float32, device=dem.device)
+    with torch.cuda.device(dem.device):
+        _check(lib.avl_normals(dem.data_ptr(), h, w, cell_size, out.data_ptr(), _stream(dem.device)), "avl_normals")
+    return out
+
+
+def release_mask(nrm: torch.Tensor, dem: torch.Tensor, slope_min_deg: float, slope_max_deg: float,
+                 z_min: float = float("-inf"), z_max: float = float("inf")) -> torch.Tensor:
+    """Release map: uint8 (H, W), 1 where the steepness and elevation are in range."""
+    _need(nrm, "normals", torch.float32, 3)
+    _need(dem, "dem", torch.float32, 2)
+    h, w = dem.shape
+    if nrm.shape != (h, w, 4):
+        raise ValueError("normals must be (H, W, 4)")
+    out = torch.empty((h, w), dtype=torch.uint8, device=dem.device)
+    with torch.cuda.device(dem.device):
+        _check(lib.avl_release_mask(nrm.data_ptr(), dem.data_ptr(), h, w, slope_min_deg, slope_max_deg, z_min, z_max,
+                                    out.data_ptr(), _stream(dem.device)), "avl_release_mask")
+    return out
+
+
+def release_cells(mask: torch.Tensor) -> tuple[torch.Tensor, torch.Tensor]:
+    """Row-major list of release texels: (cells int32 [H*W], n int32 [1]); cells[:n] are valid."""
+    _need(mask, "mask", torch.uint8, 2)
+    h, w = mask.shape
+    cells = torch.empty(h * w, dtype=torch.int32, device=mask.device)
+    n = torch.empty(1, dtype=torch.int32, device=mask.device)
+    nb = workspace_bytes(h, w)
+    with torch.cuda.device(mask.device):
+        ws = _workspace(mask.device, nb)
+        _check(lib.avl_release_cells(mask.data_ptr(), h, w, cells.data_ptr(), n.data_ptr(), ws.data_ptr(), ws.numel(),
+                                     _stream(mask.device)), "avl_release_cells")
+    return cells, n
+
+
+@dataclass
+class RunResult:
+    counts: torch.Tensor   # (H, W) uint32: particle entries per texel
+    vmax: torch.Tensor     # (H, W) float32: max speed per texel, m/s
+    stats: torch.Tensor    # (4,) uint64: steps, exits, stops, step-limit ends
+
+
+def trajectories(dem: torch.Tensor, mask: torch.Tensor, cell_size: float, params: Params,
+                 particles_per_cell: int, step_limit: int, seed: int, run_id: int = 0,
+                 out: RunResult | None = None) -> RunResult:
+    """One pass of the trajectory model over every release texel of ``mask``."""
+    _need(dem, "dem", torch.float32, 2)
+    _need(mask, "mask", torch.uint8, 2)
+    h, w = dem.shape
+    if mask.shape != (h, w):
+        raise ValueError("mask must have the DEM's shape")
+    if out is None:
+        out = RunResult(torch.empty((h, w), dtype=torch.uint32, device=dem.device),
+                        torch.empty((h, w), dtype=torch.float32, device=dem.device),
+                        torch.empty(4, dtype=torch.uint64, device=dem.device))
+    nb = workspace_bytes(h, w)
+    with torch.cuda.device(dem.device):
+        ws = _workspace(dem.device, nb)
+        _check(lib.avl_trajectories(dem.data_ptr(), mask.data_ptr(), h, w, cell_size, ctypes.byref(params),
+                                    particles_per_cell, step_limit, seed & (2**64 - 1), run_id,
+                                    out.counts.data_ptr(), out.vmax.data_ptr(), out.stats.data_ptr(), ws.data_ptr(),
+                                    ws.numel(), _stream(dem.device)), "avl_trajectories")
+    return out
+
+
+def overlay(dem: torch.Tensor, cell_size: float, slope_min_deg: float, slope_max_deg: float, z_min: float,
+            z_max: float, params: Params, particles_per_cell: int, step_limit: int, seed: int,
+            run_id: int = 0) -> tuple[torch.Tensor, torch.Tensor, RunResult]:
+    """The whole avalanche overlay: normals -> release map -> trajectories."""
+    nrm = normals(dem, cell_size)
+    mask = release_mask(nrm, dem, slope_min_deg, slope_max_deg, z_min, z_max)
+    return nrm, mask, trajectories(dem, mask, cell_size, params, particles_per_cell, step_limit, seed, run_id)

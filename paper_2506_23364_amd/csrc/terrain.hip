@@ -1,0 +1,267 @@
+// Terrain passes of the avalanche overlay (section 5.2 of arXiv 2506.23364): surface normals and
+// steepness per DEM texel, the release-point map from a steepness range and an elevation window, and
+// the row-major list of release texels. Plus the raster fill / merge helpers of the trajectory pass.
+//
+// All of these are streaming passes bound by HBM bandwidth; each is written for 64-wide wavefronts
+// with every wave touching whole 256-byte stretches of consecutive cells.
+#include "avl_internal.h"
+
+namespace avl {
+
+// ------------------------------------------------------------------------------------------ normals
+// Block = 64 x 4 texels (one wave per row of the tile); the tile plus a one-texel halo is staged in LDS
+// so every DEM value is read from L2/HBM once per tile. Gradient: central difference inside, one-sided
+// at the grid edges (the textbook finite difference); n = (-gx, -gy, 1)/sqrt(gx^2 + gy^2 + 1).
+constexpr int kNTX = 64, kNTY = 4;
+
+__global__ __launch_bounds__(kNTX * kNTY) void k_normals(const float* __restrict__ dem, int H, int W, float cs,
+                                                         float cs2, float4* __restrict__ out) {
+    __shared__ float tile[kNTY + 2][kNTX + 2];
+    const int tx = threadIdx.x & (kNTX - 1), ty = threadIdx.x / kNTX;
+    const int c0 = blockIdx.x * kNTX, r0 = blockIdx.y * kNTY;
+    // stage (kNTY + 2) x (kNTX + 2) texels with clamped indices
+    for (int i = threadIdx.x; i < (kNTY + 2) * (kNTX + 2); i += kNTX * kNTY) {
+        int lr = i / (kNTX + 2), lc = i - lr * (kNTX + 2);
+        int r = min(max(r0 + lr - 1, 0), H - 1);
+        int c = min(max(c0 + lc - 1, 0), W - 1);
+        tile[lr][lc] = dem[(size_t)r * W + c];
+    }
+    __syncthreads();
+    const int r = r0 + ty, c = c0 + tx;
+    if (r >= H || c >= W) return;
+    const int lr = ty + 1, lc = tx + 1;
+    float gx, gy;
+    if (c == 0)
+        gx = (tile[lr][lc + 1] - tile[lr][lc]) / cs;
+    else if (c == W - 1)
+        gx = (tile[lr][lc] - tile[lr][lc - 1]) / cs;
+    else
+        gx = (tile[lr][lc + 1] - tile[lr][lc - 1]) / cs2;
+    if (r == 0)
+        gy = (tile[lr + 1][lc] - tile[lr][lc]) / cs;
+    else if (r == H - 1)
+        gy = (tile[lr][lc] - tile[lr - 1][lc]) / cs;
+    else
+        gy = (tile[lr + 1][lc] - tile[lr - 1][lc]) / cs2;
+    const float gg = gx * gx + gy * gy;
+    const float l = sqrtf(gg + 1.0f);
+    float4 o;
+    o.x = -(gx / l);
+    o.y = -(gy / l);
+    o.z = 1.0f / l;
+    o.w = atanf(sqrtf(gg)) * 57.295779513082320876798f;
+    out[(size_t)r * W + c] = o;
+}
+
+hipError_t launch_normals(const float* dem, int H, int W, float cs, float* out4, hipStream_t s) {
+    dim3 grid((W + kNTX - 1) / kNTX, (H + kNTY - 1) / kNTY);
+    const float cs2 = 2.0f * cs;
+    hipLaunchKernelGGL(k_normals, grid, dim3(kNTX * kNTY), 0, s, dem, H, W, cs, cs2,
+                       reinterpret_cast<float4*>(out4));
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------ release mask
+// Four texels per thread: one 16-byte load of each normal, one 16-byte load of four heights when the
+// four are in range, one 4-byte store of four mask bytes.
+__global__ __launch_bounds__(256) void k_release_mask(const float4* __restrict__ nrm, const float* __restrict__ dem,
+                                                      int64_t n, float cmin, float cmax, float zmin, float zmax,
+                                                      uint8_t* __restrict__ mask) {
+    const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+    if (i0 >= n) return;
+    if (i0 + 4 <= n) {
+        uint32_t packed = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const float nz = nrm[i0 + k].z;
+            const float z = dem[i0 + k];
+            const uint32_t m = (cmin <= nz && nz <= cmax && zmin <= z && z <= zmax) ? 1u : 0u;
+            packed |= m << (8 * k);
+        }
+        if ((reinterpret_cast<uintptr_t>(mask + i0) & 3) == 0) {
+            *reinterpret_cast<uint32_t*>(mask + i0) = packed;
+        } else {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) mask[i0 + k] = (uint8_t)(packed >> (8 * k));
+        }
+    } else {
+        for (int64_t i = i0; i < n; ++i) {
+            const float nz = nrm[i].z;
+            const float z = dem[i];
+            mask[i] = (cmin <= nz && nz <= cmax && zmin <= z && z <= zmax) ? 1 : 0;
+        }
+    }
+}
+
+hipError_t launch_release_mask(const float* normals4, const float* dem, int64_t n, float cmin, float cmax,
+                               float zmin, float zmax, uint8_t* mask, hipStream_t s) {
+    const int64_t threads = (n + 3) / 4;
+    const unsigned blocks = (unsigned)((threads + 255) / 256);
+    hipLaunchKernelGGL(k_release_mask, dim3(blocks), dim3(256), 0, s,
+                       reinterpret_cast<const float4*>(normals4), dem, n, cmin, cmax, zmin, zmax, mask);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------ compaction
+// Order-preserving stream compaction of the mask into linear indices, in three passes over
+// kScanChunk-cell blocks: per-block counts, one-block exclusive scan of the counts, per-block write.
+
+__device__ inline uint32_t wave_incl_scan(uint32_t v) {
+    const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        uint32_t t = __shfl_up(v, d, kWave);
+        if (lane >= d) v += t;
+    }
+    return v;
+}
+
+// exclusive scan of one value per thread over a block of kScanThreads; returns the block total in *total
+__device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t* total) {
+    __shared__ uint32_t wsum[kScanThreads / kWave];
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    const uint32_t inc = wave_incl_scan(v);
+    if (lane == kWave - 1) wsum[wid] = inc;
+    __syncthreads();
+    uint32_t before = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < kScanThreads / kWave; ++k) {
+        before += (k < wid) ? wsum[k] : 0u;
+        tot += wsum[k];
+    }
+    __syncthreads();
+    *total = tot;
+    return before + inc - v;
+}
+
+__device__ inline uint32_t count16(const uint8_t* __restrict__ mask, int64_t base, int64_t n) {
+    uint32_t c = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPerThread; ++k) {
+        const int64_t i = base + k;
+        if (i < n) c += mask[i] != 0;
+    }
+    return c;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_compact_count(const uint8_t* __restrict__ mask, int64_t n,
+                                                                uint32_t* __restrict__ blk) {
+    const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanPerThread;
+    uint32_t total;
+    (void)block_excl_scan(count16(mask, base, n), &total);
+    if (threadIdx.x == 0) blk[blockIdx.x] = total;
+}
+
+// one block: exclusive scan of nb block counts in place; the grand total goes to *n_cells
+__global__ __launch_bounds__(1024) void k_compact_scan(uint32_t* __restrict__ blk, int64_t nb,
+                                                       int32_t* __restrict__ n_cells) {
+    __shared__ uint32_t wsum[1024 / kWave];
+    const int64_t per = (nb + 1023) / 1024;
+    const int64_t b0 = (int64_t)threadIdx.x * per;
+    uint32_t local = 0;
+    for (int64_t k = 0; k < per; ++k)
+        if (b0 + k < nb) local += blk[b0 + k];
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    const uint32_t inc = wave_incl_scan(local);
+    if (lane == kWave - 1) wsum[wid] = inc;
+    __syncthreads();
+    uint32_t before = 0, tot = 0;
+    for (int k = 0; k < 1024 / kWave; ++k) {
+        before += (k < wid) ? wsum[k] : 0u;
+        tot += wsum[k];
+    }
+    uint32_t run = before + inc - local;
+    for (int64_t k = 0; k < per; ++k) {
+        if (b0 + k < nb) {
+            const uint32_t v = blk[b0 + k];
+            blk[b0 + k] = run;
+            run += v;
+        }
+    }
+    if (threadIdx.x == 0) *n_cells = (int32_t)tot;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_compact_write(const uint8_t* __restrict__ mask, int64_t n,
+                                                                const uint32_t* __restrict__ blk,
+                                                                int32_t* __restrict__ cells) {
+    const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanPerThread;
+    uint32_t total;
+    uint32_t pos = blk[blockIdx.x] + block_excl_scan(count16(mask, base, n), &total);
+#pragma unroll
+    for (int k = 0; k < kScanPerThread; ++k) {
+        const int64_t i = base + k;
+        if (i < n && mask[i] != 0) cells[pos++] = (int32_t)i;
+    }
+}
+
+hipError_t launch_compact(const uint8_t* mask, int64_t n, int32_t* cells, int32_t* n_cells, uint32_t* blk,
+                          hipStream_t s) {
+    const int64_t nb = scan_blocks(n);
+    if (nb == 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_compact_count, dim3((unsigned)nb), dim3(kScanThreads), 0, s, mask, n, blk);
+    hipLaunchKernelGGL(k_compact_scan, dim3(1), dim3(1024), 0, s, blk, nb, n_cells);
+    hipLaunchKernelGGL(k_compact_write, dim3((unsigned)nb), dim3(kScanThreads), 0, s, mask, n, blk, cells);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------ raster helpers
+// Fill kernels instead of memset nodes, so that the same sequence can be captured into a graph.
+__global__ __launch_bounds__(256) void k_fill_u32(uint32_t* __restrict__ p, uint32_t v, int64_t n) {
+    const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+    if (i0 + 4 <= n && (reinterpret_cast<uintptr_t>(p + i0) & 15) == 0) {
+        *reinterpret_cast<uint4*>(p + i0) = make_uint4(v, v, v, v);
+    } else {
+        for (int64_t i = i0; i < n && i < i0 + 4; ++i) p[i] = v;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_fill_u64(unsigned long long* __restrict__ p, unsigned long long v,
+                                                  int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// Merge of the per-XCD private rasters of the trajectory pass into the caller's rasters:
+// counts = sum over XCDs, vmax = sqrt(max over XCDs of the v^2 bits). One cell per thread, each of the
+// 2 x kXcds reads coalesced across the wave.
+__global__ __launch_bounds__(256) void k_merge_rasters(const uint32_t* __restrict__ pc, const uint32_t* __restrict__ pv,
+                                                       int64_t n, uint32_t* __restrict__ counts,
+                                                       float* __restrict__ vmax) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t c = 0, v = 0;
+#pragma unroll
+    for (int x = 0; x < kXcds; ++x) {
+        c += pc[x * n + i];
+        v = max(v, pv[x * n + i]);
+    }
+    counts[i] = c;
+    vmax[i] = sqrtf(__uint_as_float(v));
+}
+
+static unsigned blocks_for(int64_t items, int per_thread) {
+    const int64_t threads = (items + per_thread - 1) / per_thread;
+    return (unsigned)((threads + 255) / 256);
+}
+
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(n, 4)), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u64, dim3(blocks_for(n, 1)), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_merge_rasters(const uint32_t* priv_counts, const uint32_t* priv_vmax2, int64_t n, uint32_t* counts,
+                                float* vmax, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_merge_rasters, dim3(blocks_for(n, 1)), dim3(256), 0, s, priv_counts, priv_vmax2, n, counts,
+                       vmax);
+    return hipGetLastError();
+}
+
+}  // namespace avl

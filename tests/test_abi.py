@@ -1,0 +1,102 @@
+"""CPU checks of the C ABI: the library loads, exports every entry point that include/avl.h declares,
+and rejects bad arguments on the host before any GPU work (so these run without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "avl.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"AVL_API\s+[\w\s\*]+?\b(avl_\w+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for n in ("avl_normals", "avl_release_mask", "avl_release_cells", "avl_trajectories", "avl_workspace_bytes",
+              "avl_strerror", "avl_last_error"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    avl = pytest.importorskip("paper_2506_23364_amd")
+    lib = ctypes.CDLL(avl.LIB_PATH)
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    import paper_2506_23364_amd as avl
+    monkeypatch.setattr(avl, "LIB_PATH", str(tmp_path / "libavl.so"))
+    with pytest.raises(ImportError):
+        avl._load()
+
+
+@pytest.fixture(scope="module")
+def L():
+    import paper_2506_23364_amd as avl
+    return avl
+
+
+FAKE = 0x100000  # never dereferenced: every case below fails the host checks first
+
+
+def test_strerror_and_workspace_size(L):
+    for code in (0, -1, -2, -3, 7):
+        assert L.lib.avl_strerror(code)
+    assert L.workspace_bytes(0, 5) == 0
+    n = 2048 * 2048
+    assert L.workspace_bytes(2048, 2048) >= 4 * n
+    assert L.workspace_bytes(3, 5) >= 4 * 15
+
+
+def _traj(L, **kw):
+    a = dict(dem=FAKE, mask=FAKE, H=16, W=16, cs=10.0, params=L.Params.make(), P=4, S=10, seed=1, run=0,
+             counts=FAKE, vmax=FAKE, stats=None, ws=FAKE, wsb=L.workspace_bytes(16, 16), stream=None)
+    a.update(kw)
+    p = a["params"]
+    return L.lib.avl_trajectories(a["dem"], a["mask"], a["H"], a["W"], a["cs"], ctypes.byref(p) if p else None,
+                                  a["P"], a["S"], a["seed"], a["run"], a["counts"], a["vmax"], a["stats"], a["ws"],
+                                  a["wsb"], a["stream"])
+
+
+@pytest.mark.parametrize("kw", [
+    dict(dem=None), dict(mask=None), dict(counts=None), dict(vmax=None), dict(ws=None), dict(params=None),
+    dict(H=0), dict(W=-3), dict(H=65536, W=65536), dict(cs=0.0), dict(cs=float("nan")), dict(P=0),
+])
+def test_trajectories_rejects_bad_arguments(L, kw):
+    assert _traj(L, **kw) == L.AVL_EINVAL
+    assert L.lib.avl_last_error()
+
+
+@pytest.mark.parametrize("field,value", [
+    ("mu", -0.1), ("mu", float("inf")), ("xi", 0.0), ("xi", float("nan")), ("flow_height", 0.0),
+    ("persistence", 1.5), ("persistence", -0.01), ("randomness", -1.0), ("step_cells", 0.0),
+    ("step_cells", 17.0), ("tan_alpha", float("nan")), ("flags", 1),
+])
+def test_trajectories_rejects_bad_params(L, field, value):
+    p = L.Params.make()
+    setattr(p, field, value)
+    assert _traj(L, params=p) == L.AVL_EINVAL
+
+
+def test_trajectories_workspace_too_small(L):
+    assert _traj(L, wsb=L.workspace_bytes(16, 16) - 1) == L.AVL_ENOMEM
+
+
+def test_terrain_calls_reject_bad_arguments(L):
+    lib = L.lib
+    assert lib.avl_normals(None, 4, 4, 10.0, FAKE, None) == L.AVL_EINVAL
+    assert lib.avl_normals(FAKE, 1, 4, 10.0, FAKE, None) == L.AVL_EINVAL
+    assert lib.avl_normals(FAKE, 4, 4, -1.0, FAKE, None) == L.AVL_EINVAL
+    assert lib.avl_normals(FAKE, 4, 4, 10.0, FAKE + 4, None) == L.AVL_EINVAL  # misaligned float4 output
+    assert lib.avl_release_mask(FAKE, FAKE, 4, 4, 40.0, 30.0, 0.0, 1.0, FAKE, None) == L.AVL_EINVAL
+    assert lib.avl_release_mask(FAKE, FAKE, 4, 4, 30.0, 91.0, 0.0, 1.0, FAKE, None) == L.AVL_EINVAL
+    assert lib.avl_release_mask(FAKE, FAKE, 4, 4, 30.0, 45.0, float("nan"), 1.0, FAKE, None) == L.AVL_EINVAL
+    assert lib.avl_release_mask(None, FAKE, 4, 4, 30.0, 45.0, 0.0, 1.0, FAKE, None) == L.AVL_EINVAL
+    assert lib.avl_release_cells(FAKE, 4, 4, FAKE, FAKE, FAKE, 10, None) == L.AVL_ENOMEM
+    assert lib.avl_release_cells(None, 4, 4, FAKE, FAKE, FAKE, 1 << 20, None) == L.AVL_EINVAL
