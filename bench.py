@@ -45,6 +45,7 @@ def parse():
     ap.add_argument("--workload", default="alpine", choices=["tiny", "alpine", "large"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-stride", type=int, default=0, help="oracle sample: every n-th release cell (0 = auto)")
+    ap.add_argument("--no-batched", action="store_true", help="skip the ensemble (batched vs plain) leg")
     return ap.parse_args()
 
 
@@ -63,6 +64,59 @@ def cpu_baseline(w, mask: np.ndarray, stride: int) -> dict:
     return {"value": res.steps / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
             "sample": f"every {stride}th release cell ({int(sample.sum())} cells x {w.particles_per_cell} "
                       f"particles, {res.steps} particle-steps, {dt:.1f} s, single-threaded FP32 C oracle)"}
+
+
+def batched_leg(avl, torch, reps: int) -> dict:
+    """Ensemble sweep: 16 ridged-fBm tiles of 1024^2 at 10 m, one release scenario each (103-26,397
+    cells), crossed with 64 (mu, xi, h) sets: 1024 runs of 32 particles per cell and 2000 steps. Timed
+    as one batched call (captured once into a HIP graph, then replayed) and as 1024 plain calls."""
+    import synth
+    e = synth.make_ensemble()
+    dev = torch.device("cuda", 0)
+    dems = torch.from_numpy(e.dems).to(dev)
+    masks = torch.from_numpy(e.masks).to(dev)
+    ptab = avl.params_tensor(e.params, dev)
+    rtab = avl.runs_tensor(e.runs, dev)
+    stream = torch.cuda.Stream()
+    out = None
+    with torch.cuda.stream(stream):
+        for _ in range(2):  # tune, capture, replay once
+            out = avl.trajectories_batched(dems, masks, e.cell_size, ptab, rtab, e.particles_per_cell, e.step_limit, out)
+        stream.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            out = avl.trajectories_batched(dems, masks, e.cell_size, ptab, rtab, e.particles_per_cell, e.step_limit, out)
+        stream.synchronize()
+        t_batch = (time.perf_counter() - t0) / reps
+    steps = int(out.stats.cpu().numpy()[:, 0].sum())
+    variant = avl.last_variant()
+    # the same runs as plain calls, each into its own slice of the output rasters
+    plain = avl.BatchResult(torch.empty_like(out.counts), torch.empty_like(out.vmax), torch.empty_like(out.stats),
+                            out.status)
+    params = [avl.Params.make(**p) for p in e.params]
+
+    def plain_loop():
+        for k, (t, sc, p, run_id, seed) in enumerate(e.runs):
+            avl.trajectories(dems[t], masks[sc], e.cell_size, params[p], e.particles_per_cell, e.step_limit, seed,
+                             run_id, avl.RunResult(plain.counts[k], plain.vmax[k], plain.stats[k]))
+    plain_loop()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        plain_loop()
+    torch.cuda.synchronize()
+    t_plain = (time.perf_counter() - t0) / reps
+    same = bool(torch.equal(plain.counts.view(torch.int32), out.counts.view(torch.int32))
+                and torch.equal(plain.vmax, out.vmax)
+                and torch.equal(plain.stats.view(torch.int64), out.stats.view(torch.int64)))
+    return {"workload": "16 tiles x 64 parameter sets = 1024 runs, 1024^2 at 10 m, 32 particles/cell, "
+                        "2000 steps, scenarios 103-26397 cells",
+            "runs": len(e.runs), "particles": int(e.masks.sum(axis=(1, 2))[[r[1] for r in e.runs]].sum()
+                                                   * e.particles_per_cell),
+            "particle_steps": steps, "ms_batched": t_batch * 1e3, "ms_plain_calls": t_plain * 1e3,
+            "speedup_batched_vs_plain": t_plain / t_batch,
+            "particle_steps_per_s_batched": steps / t_batch, "particle_steps_per_s_plain": steps / t_plain,
+            "variant": variant, "batched_equals_plain": same}
 
 
 def main() -> int:
@@ -176,6 +230,8 @@ def main() -> int:
                          "peak_GBs": HBM_PEAK_GBS},
         },
     }
+    if not args.no_batched:
+        out["batched"] = batched_leg(avl, torch, 3)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, mask_np, args.cpu_stride)
     print(json.dumps(out), flush=True)

@@ -105,6 +105,47 @@ AVL_API int avl_trajectories(const float* dem, const uint8_t* mask, int32_t H, i
                      uint32_t run_id, uint32_t* counts, float* vmax, uint64_t* stats, void* workspace,
                      size_t workspace_bytes, void* stream);
 
+/* One run of a batch: which DEM tile, which release scenario (mask) and which parameter set, and the
+ * run's random stream (Philox key = seed, counter word 3 = run_id). 24 bytes. */
+typedef struct avl_run {
+    uint32_t tile;     /* index into dems, < n_tiles */
+    uint32_t scenario; /* index into masks, < n_masks */
+    uint32_t param;    /* index into params, < n_params */
+    uint32_t run_id;   /* Philox counter word 3 */
+    uint64_t seed;     /* Philox key */
+} avl_run;
+
+/* Workspace bytes that avl_trajectories_batched needs. */
+AVL_API size_t avl_batched_workspace_bytes(int32_t H, int32_t W, int32_t n_masks, int32_t n_runs);
+
+/* Batched ensembles (section 5.2 motivates interactive sweeps of the trajectory parameters; section 3
+ * recomputes the overlay whenever the user changes them): n_runs independent trajectory passes, each
+ * exactly the avl_trajectories pass of its (tile, scenario, parameter set, seed, run_id), all in one
+ * persistent launch over a shared particle queue.
+ * dems: n_tiles*H*W floats (tile t at t*H*W). masks: n_masks*H*W bytes. params: n_params avl_params and
+ * runs: n_runs avl_run, both DEVICE arrays (so a captured sequence can be replayed with new values).
+ * counts, vmax: n_runs*H*W (run r at r*H*W), as in avl_trajectories. stats (nullable): n_runs*4 uint64.
+ * run_status (nullable): n_runs int32, 0 = ran, 1 = an index out of range, 2 = invalid parameters (such a
+ * run releases no particle and leaves zero rasters). particles_per_cell and step_limit are shared.
+ * Need n_runs*H*W, n_tiles*H*W and n_masks*H*W all < 2^32 - 1. When `stream` is not the null stream, the
+ * whole sequence (zero fills, compactions, run setup, trajectory kernel, finalize) is captured once into
+ * a HIP graph per argument set and replayed on later calls. */
+AVL_API int avl_trajectories_batched(const float* dems, int32_t n_tiles, const uint8_t* masks, int32_t n_masks,
+                                     int32_t H, int32_t W, float cell_size, const avl_params* params,
+                                     int32_t n_params, const avl_run* runs, int32_t n_runs,
+                                     uint32_t particles_per_cell, uint32_t step_limit, uint32_t* counts, float* vmax,
+                                     uint64_t* stats, int32_t* run_status, void* workspace, size_t workspace_bytes,
+                                     void* stream);
+
+/* Tuning controls. variant: -1 = autotune (default: the first call per device and problem-size bucket
+ * times every kernel variant and keeps the fastest; all variants give identical results), or a fixed
+ * variant index in [0, avl_tuning_variants()). graphs: 1 = capture batched calls into HIP graphs
+ * (default), 0 = launch eagerly. Returns AVL_EINVAL for an out-of-range variant. */
+AVL_API int avl_set_tuning(int32_t variant, int32_t graphs);
+AVL_API int32_t avl_tuning_variants(void);
+/* The variant the last trajectory call on this thread used. */
+AVL_API int32_t avl_last_variant(void);
+
 /* Name of an error code. Never NULL. */
 AVL_API const char* avl_strerror(int code);
 

@@ -16,8 +16,9 @@ from dataclasses import dataclass
 
 import torch
 
-__all__ = ["AvlError", "Params", "normals", "release_mask", "release_cells", "trajectories", "overlay",
-           "workspace_bytes", "LIB_PATH", "lib"]
+__all__ = ["AvlError", "Params", "Run", "normals", "release_mask", "release_cells", "trajectories",
+           "trajectories_batched", "overlay", "workspace_bytes", "batched_workspace_bytes", "set_tuning",
+           "tuning_variants", "last_variant", "LIB_PATH", "lib"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libavl.so")
 
@@ -44,6 +45,12 @@ class Params(ctypes.Structure):
         return cls(mu, xi, flow_height, persistence, randomness, step_cells, tan_alpha, flags)
 
 
+class Run(ctypes.Structure):
+    """Mirror of ``avl_run``: one run of a batch."""
+    _fields_ = [("tile", ctypes.c_uint32), ("scenario", ctypes.c_uint32), ("param", ctypes.c_uint32),
+                ("run_id", ctypes.c_uint32), ("seed", ctypes.c_uint64)]
+
+
 def _load() -> ctypes.CDLL:
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2506_23364_amd.build`")
@@ -57,6 +64,17 @@ def _load() -> ctypes.CDLL:
     L.avl_release_cells.argtypes = [vp, i32, i32, vp, vp, vp, sz, vp]
     L.avl_trajectories.argtypes = [vp, vp, i32, i32, f32, ctypes.POINTER(Params), u32, u32, u64, u32, vp, vp, vp,
                                    vp, sz, vp]
+    L.avl_batched_workspace_bytes.argtypes = [i32, i32, i32, i32]
+    L.avl_batched_workspace_bytes.restype = sz
+    L.avl_trajectories_batched.argtypes = [vp, i32, vp, i32, i32, i32, f32, vp, i32, vp, i32, u32, u32, vp, vp, vp,
+                                           vp, vp, sz, vp]
+    L.avl_trajectories_batched.restype = ctypes.c_int
+    L.avl_set_tuning.argtypes = [i32, i32]
+    L.avl_set_tuning.restype = ctypes.c_int
+    L.avl_tuning_variants.argtypes = []
+    L.avl_tuning_variants.restype = i32
+    L.avl_last_variant.argtypes = []
+    L.avl_last_variant.restype = i32
     L.avl_strerror.argtypes = [ctypes.c_int]
     L.avl_strerror.restype = ctypes.c_char_p
     L.avl_last_error.argtypes = []
@@ -106,6 +124,23 @@ def _workspace(dev: torch.device, nbytes: int) -> torch.Tensor:
 
 def workspace_bytes(h: int, w: int) -> int:
     return int(lib.avl_workspace_bytes(h, w))
+
+
+def batched_workspace_bytes(h: int, w: int, n_masks: int, n_runs: int) -> int:
+    return int(lib.avl_batched_workspace_bytes(h, w, n_masks, n_runs))
+
+
+def set_tuning(variant: int = -1, graphs: bool = True) -> None:
+    """variant -1 = autotune; graphs = capture batched calls into HIP graphs on non-null streams."""
+    _check(lib.avl_set_tuning(variant, 1 if graphs else 0), "avl_set_tuning")
+
+
+def tuning_variants() -> int:
+    return int(lib.avl_tuning_variants())
+
+
+def last_variant() -> int:
+    return int(lib.avl_last_variant())
 
 
 def normals(dem: torch.Tensor, cell_size: float) -> torch.Tensor:
@@ -174,6 +209,60 @@ def trajectories(dem: torch.Tensor, mask: torch.Tensor, cell_size: float, params
                                     particles_per_cell, step_limit, seed & (2**64 - 1), run_id,
                                     out.counts.data_ptr(), out.vmax.data_ptr(), out.stats.data_ptr(), ws.data_ptr(),
                                     ws.numel(), _stream(dem.device)), "avl_trajectories")
+    return out
+
+
+def params_tensor(params, device) -> torch.Tensor:
+    """Device array of avl_params from a list of Params (or dicts of Params.make keywords)."""
+    ps = [p if isinstance(p, Params) else Params.make(**p) for p in params]
+    raw = b"".join(bytes(p) for p in ps)
+    return torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(device)
+
+
+def runs_tensor(runs, device) -> torch.Tensor:
+    """Device array of avl_run from a list of Run (or (tile, scenario, param, run_id, seed) tuples)."""
+    rs = [r if isinstance(r, Run) else Run(*r) for r in runs]
+    raw = b"".join(bytes(r) for r in rs)
+    return torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(device)
+
+
+@dataclass
+class BatchResult:
+    counts: torch.Tensor   # (n_runs, H, W) uint32
+    vmax: torch.Tensor     # (n_runs, H, W) float32
+    stats: torch.Tensor    # (n_runs, 4) uint64
+    status: torch.Tensor   # (n_runs,) int32: 0 ran, 1 bad index, 2 bad parameters
+
+
+def trajectories_batched(dems: torch.Tensor, masks: torch.Tensor, cell_size: float, params: torch.Tensor,
+                         runs: torch.Tensor, particles_per_cell: int, step_limit: int,
+                         out: BatchResult | None = None) -> BatchResult:
+    """Many runs in one launch. dems (n_tiles, H, W) f32; masks (n_masks, H, W) u8; params and runs are
+    device byte tensors from params_tensor / runs_tensor (they may be rewritten between calls)."""
+    _need(dems, "dems", torch.float32, 3)
+    _need(masks, "masks", torch.uint8, 3)
+    _need(params, "params", torch.uint8, 1)
+    _need(runs, "runs", torch.uint8, 1)
+    n_tiles, h, w = dems.shape
+    n_masks = masks.shape[0]
+    if masks.shape[1:] != (h, w):
+        raise ValueError("masks must have the tiles' shape")
+    n_params = params.numel() // ctypes.sizeof(Params)
+    n_runs = runs.numel() // ctypes.sizeof(Run)
+    if out is None:
+        dev = dems.device
+        out = BatchResult(torch.empty((n_runs, h, w), dtype=torch.uint32, device=dev),
+                          torch.empty((n_runs, h, w), dtype=torch.float32, device=dev),
+                          torch.empty((n_runs, 4), dtype=torch.uint64, device=dev),
+                          torch.empty(n_runs, dtype=torch.int32, device=dev))
+    nb = batched_workspace_bytes(h, w, n_masks, n_runs)
+    with torch.cuda.device(dems.device):
+        ws = _workspace(dems.device, nb)
+        _check(lib.avl_trajectories_batched(dems.data_ptr(), n_tiles, masks.data_ptr(), n_masks, h, w, cell_size,
+                                            params.data_ptr(), n_params, runs.data_ptr(), n_runs, particles_per_cell,
+                                            step_limit, out.counts.data_ptr(), out.vmax.data_ptr(),
+                                            out.stats.data_ptr(), out.status.data_ptr(), ws.data_ptr(), ws.numel(),
+                                            _stream(dems.device)), "avl_trajectories_batched")
     return out
 
 

@@ -1,27 +1,32 @@
-// extern "C" entry points of libavl.so: host-side argument checks, derived constants, workspace
-// carving and kernel enqueueing. See include/avl.h for the contract of each call.
+// extern "C" entry points of libavl.so: host-side argument checks, workspace carving, kernel
+// enqueueing, the autotuner of the trajectory kernel and the graph cache of batched calls.
+// See include/avl.h for the contract of each call.
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
+#include <vector>
 
-#include "../../include/avl.h"
 #include "avl_internal.h"
 
 namespace avl {
 
 size_t workspace_bytes(int64_t n) {
-    return 256 + round256((size_t)scan_blocks(n) * sizeof(uint32_t)) + round256((size_t)n * sizeof(int32_t)) +
+    return kControl + round256((size_t)scan_blocks(n) * sizeof(uint32_t)) + round256((size_t)n * sizeof(int32_t)) +
            2 * round256((size_t)kXcds * n * sizeof(uint32_t));
 }
 
 Workspace carve(void* base, int64_t n) {
     char* p = static_cast<char*>(base);
-    Workspace w;
+    Workspace w{};
     w.n_cells = reinterpret_cast<int32_t*>(p);
-    w.stats = reinterpret_cast<unsigned long long*>(p + 16);
-    w.queues = reinterpret_cast<unsigned long long*>(p + 64);
-    p += 256;
+    w.stats = reinterpret_cast<unsigned long long*>(p + 64);
+    w.queues = reinterpret_cast<unsigned long long*>(p + 128);
+    w.run_off = reinterpret_cast<unsigned long long*>(p + 192);
+    w.runs = reinterpret_cast<RunConst*>(p + 256);
+    p += kControl;
     w.blk = reinterpret_cast<uint32_t*>(p);
     p += round256((size_t)scan_blocks(n) * sizeof(uint32_t));
     w.cells = reinterpret_cast<int32_t*>(p);
@@ -32,11 +37,38 @@ Workspace carve(void* base, int64_t n) {
     return w;
 }
 
+size_t batched_workspace_bytes(int64_t n, int64_t n_masks, int64_t n_runs) {
+    return kControl + round256((size_t)scan_blocks(n) * sizeof(uint32_t)) +
+           round256((size_t)n_masks * n * sizeof(int32_t)) + round256((size_t)n_masks * sizeof(int32_t)) +
+           round256((size_t)n_runs * sizeof(RunConst)) + round256((size_t)(n_runs + 1) * sizeof(unsigned long long)) +
+           round256((size_t)n_runs * 4 * sizeof(unsigned long long));
+}
+
+Workspace carve_batched(void* base, int64_t n, int64_t n_masks, int64_t n_runs) {
+    char* p = static_cast<char*>(base);
+    Workspace w{};
+    w.queues = reinterpret_cast<unsigned long long*>(p + 128);
+    p += kControl;
+    w.blk = reinterpret_cast<uint32_t*>(p);
+    p += round256((size_t)scan_blocks(n) * sizeof(uint32_t));
+    w.cells = reinterpret_cast<int32_t*>(p);
+    p += round256((size_t)n_masks * n * sizeof(int32_t));
+    w.n_cells = reinterpret_cast<int32_t*>(p);
+    p += round256((size_t)n_masks * sizeof(int32_t));
+    w.runs = reinterpret_cast<RunConst*>(p);
+    p += round256((size_t)n_runs * sizeof(RunConst));
+    w.run_off = reinterpret_cast<unsigned long long*>(p);
+    p += round256((size_t)(n_runs + 1) * sizeof(unsigned long long));
+    w.stats = reinterpret_cast<unsigned long long*>(p);
+    return w;
+}
+
 }  // namespace avl
 
 namespace {
 
 thread_local std::string g_last_error;
+thread_local int32_t g_last_variant = -1;
 
 int fail(int code, const char* fmt, const char* detail = nullptr) {
     char buf[512];
@@ -72,6 +104,95 @@ const char* check_params(const avl_params* p) {
     return nullptr;
 }
 
+// ------------------------------------------------------------------ tuning state
+std::mutex g_mu;
+int32_t g_variant_override = -1;
+bool g_graphs = true;
+std::map<std::vector<int64_t>, int> g_best;  // (device, batched, size buckets) -> variant
+
+int ilog2(uint64_t v) {
+    int r = 0;
+    while (v > 1) {
+        v >>= 1;
+        ++r;
+    }
+    return r;
+}
+
+std::vector<int64_t> tune_key(bool batched, int64_t n, int64_t n_runs, uint32_t P, uint32_t S) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    return {dev, batched ? 1 : 0, ilog2((uint64_t)n), ilog2((uint64_t)n_runs), ilog2(P), ilog2((uint64_t)S + 1)};
+}
+
+bool capturing(hipStream_t s) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    return s && hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone;
+}
+
+// Variant for this problem: the override, the cached choice, or (first time, not under capture) the
+// fastest of all variants, each timed once with HIP events after `zero` re-zeroes what the kernel
+// accumulates into. The inputs of the kernel (cell lists, run table) must already be enqueued.
+template <class Zero>
+hipError_t choose_variant(const avl::TrajArgs& a, bool batched, const std::vector<int64_t>& key, hipStream_t s,
+                          Zero zero, int* variant) {
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        if (g_variant_override >= 0) {
+            *variant = g_variant_override;
+            return hipSuccess;
+        }
+        auto it = g_best.find(key);
+        if (it != g_best.end()) {
+            *variant = it->second;
+            return hipSuccess;
+        }
+    }
+    if (capturing(s)) {
+        *variant = 0;
+        return hipSuccess;
+    }
+    hipEvent_t e0, e1;
+    hipError_t e;
+    if ((e = hipEventCreate(&e0)) != hipSuccess) return e;
+    if ((e = hipEventCreate(&e1)) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return e;
+    }
+    float best_ms = 1e30f;
+    int best = 0;
+    for (int v = 0; v < avl::trajectory_variants(); ++v) {
+        const avl::LaunchShape sh = avl::trajectory_shape(batched, v);
+        if ((e = zero()) != hipSuccess) break;
+        if ((e = hipEventRecord(e0, s)) != hipSuccess) break;
+        if ((e = avl::launch_trajectories(a, batched, sh, s)) != hipSuccess) break;
+        if ((e = hipEventRecord(e1, s)) != hipSuccess) break;
+        if ((e = hipEventSynchronize(e1)) != hipSuccess) break;
+        float ms = 0.0f;
+        if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = v;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_best[key] = best;
+    *variant = best;
+    return hipSuccess;
+}
+
+// ------------------------------------------------------------------ graph cache of batched calls
+struct GraphEntry {
+    hipGraphExec_t exec;
+    uint64_t last_use;
+};
+std::map<std::vector<uint64_t>, GraphEntry> g_graph_cache;
+uint64_t g_clock = 0;
+constexpr size_t kMaxGraphs = 16;
+
 }  // namespace
 
 extern "C" {
@@ -88,9 +209,26 @@ const char* avl_strerror(int code) {
 
 const char* avl_last_error(void) { return g_last_error.c_str(); }
 
+int avl_set_tuning(int32_t variant, int32_t graphs) {
+    if (variant < -1 || variant >= avl::trajectory_variants()) return AVL_EINVAL;
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_variant_override = variant;
+    g_graphs = graphs != 0;
+    return AVL_OK;
+}
+
+int32_t avl_tuning_variants(void) { return avl::trajectory_variants(); }
+
+int32_t avl_last_variant(void) { return g_last_variant; }
+
 size_t avl_workspace_bytes(int32_t H, int32_t W) {
     if (H < 1 || W < 1) return 0;
     return avl::workspace_bytes((int64_t)H * W);
+}
+
+size_t avl_batched_workspace_bytes(int32_t H, int32_t W, int32_t n_masks, int32_t n_runs) {
+    if (H < 1 || W < 1 || n_masks < 1 || n_runs < 1) return 0;
+    return avl::batched_workspace_bytes((int64_t)H * W, n_masks, n_runs);
 }
 
 int avl_normals(const float* dem, int32_t H, int32_t W, float cell_size, float* normals4, void* stream) {
@@ -148,57 +286,184 @@ int avl_trajectories(const float* dem, const uint8_t* mask, int32_t H, int32_t W
     hipStream_t s = static_cast<hipStream_t>(stream);
     avl::Workspace ws = avl::carve(workspace, n);
 
-    // derived constants, binary32, in this order
     avl::TrajArgs a{};
-    const float g = 9.81f;
-    a.g2 = g + g;
-    a.per = params->persistence;
-    a.Q = 1.0f - a.per;
-    a.rnd = params->randomness;
-    a.L = params->step_cells;
-    const float dl = a.L * cell_size;
-    a.dl2 = dl * dl;
-    a.mdl = params->mu * dl;
-    a.cd = a.g2 / (params->xi * params->flow_height);
-    a.use_alpha = params->tan_alpha >= 0.0f ? 1 : 0;
-    a.tca = params->tan_alpha * cell_size;
     a.dem = dem;
     a.cells = ws.cells;
-    a.n_cells = ws.n_cells;
+    a.runs = ws.runs;
+    a.run_off = ws.run_off;
     a.queues = ws.queues;
     a.counts = ws.priv_counts;
     a.vmax2 = ws.priv_vmax2;
     a.stats = stats ? reinterpret_cast<unsigned long long*>(stats) : ws.stats;
     a.H = H;
     a.W = W;
-    a.P = particles_per_cell;
+    a.n_runs = 1;
     a.S = step_limit;
-    a.run = run_id;
-    a.key0 = (uint32_t)seed;
-    a.key1 = (uint32_t)(seed >> 32);
+    a.g2 = 9.81f + 9.81f;
+    a.xcd_stride = (uint32_t)n;
 
+    // the private rasters (counts then v^2 bits) are one contiguous region
+    const int64_t priv_words = (int64_t)(ws.priv_vmax2 - ws.priv_counts) + avl::kXcds * n;
+    auto zero = [&]() -> hipError_t {
+        hipError_t e;
+        if ((e = avl::launch_fill_u32(ws.priv_counts, 0u, priv_words, s)) != hipSuccess) return e;
+        if ((e = avl::launch_fill_u64(ws.queues, 0ull, avl::kXcds, s)) != hipSuccess) return e;
+        return avl::launch_fill_u64(a.stats, 0ull, 4, s);
+    };
     hipError_t e;
-    // private rasters (counts then v^2 bits, contiguous), the internal stats and the per-XCD queues
-    if ((e = avl::launch_fill_u32(ws.priv_counts, 0u, (int64_t)(ws.priv_vmax2 - ws.priv_counts) + avl::kXcds * n, s)) !=
-        hipSuccess)
-        return hip_fail(e, "avl_trajectories: zero rasters");
-    if ((e = avl::launch_fill_u64(ws.stats, 0ull, 4 + 2 + avl::kXcds, s)) != hipSuccess)
-        return hip_fail(e, "avl_trajectories: zero queues");
-    if (stats && (e = avl::launch_fill_u64(a.stats, 0ull, 4, s)) != hipSuccess)
-        return hip_fail(e, "avl_trajectories: zero stats");
     if ((e = avl::launch_compact(mask, n, ws.cells, ws.n_cells, ws.blk, s)) != hipSuccess)
         return hip_fail(e, "avl_trajectories: compaction");
-    static thread_local int cached_dev = -1;
-    static thread_local avl::LaunchShape cached_shape{256, 2048};
-    int dev = 0;
-    if ((e = hipGetDevice(&dev)) != hipSuccess) return hip_fail(e, "avl_trajectories: hipGetDevice");
-    if (dev != cached_dev) {
-        cached_shape = avl::trajectory_shape();
-        cached_dev = dev;
-    }
-    if ((e = avl::launch_trajectories(a, cached_shape, s)) != hipSuccess) return hip_fail(e, "avl_trajectories: launch");
+    const avl::RunSpec spec{0u, 0u, 0u, run_id, (unsigned long long)seed};
+    if ((e = avl::launch_setup_runs(nullptr, nullptr, 0, spec, *params, ws.n_cells, 1, 1, 1, H, W, cell_size,
+                                    particles_per_cell, false, ws.runs, ws.run_off, nullptr, s)) != hipSuccess)
+        return hip_fail(e, "avl_trajectories: run setup");
+    int variant = 0;
+    if ((e = choose_variant(a, false, tune_key(false, n, 1, particles_per_cell, step_limit), s, zero, &variant)) !=
+        hipSuccess)
+        return hip_fail(e, "avl_trajectories: autotune");
+    g_last_variant = variant;
+    if ((e = zero()) != hipSuccess) return hip_fail(e, "avl_trajectories: zero");
+    if ((e = avl::launch_trajectories(a, false, avl::trajectory_shape(false, variant), s)) != hipSuccess)
+        return hip_fail(e, "avl_trajectories: launch");
     if ((e = avl::launch_merge_rasters(ws.priv_counts, ws.priv_vmax2, n, counts, vmax, s)) != hipSuccess)
         return hip_fail(e, "avl_trajectories: merge");
+    return AVL_OK;
+}
+
+int avl_trajectories_batched(const float* dems, int32_t n_tiles, const uint8_t* masks, int32_t n_masks, int32_t H,
+                             int32_t W, float cell_size, const avl_params* params, int32_t n_params,
+                             const avl_run* runs, int32_t n_runs, uint32_t particles_per_cell, uint32_t step_limit,
+                             uint32_t* counts, float* vmax, uint64_t* stats, int32_t* run_status, void* workspace,
+                             size_t workspace_bytes, void* stream) {
+    g_last_error.clear();
+    static_assert(sizeof(avl_run) == sizeof(avl::RunSpec), "avl_run layout");
+    if (!dems || !masks || !params || !runs || !counts || !vmax || !workspace)
+        return fail(AVL_EINVAL, "avl_trajectories_batched: null pointer");
+    if (!grid_ok(H, W, 1)) return fail(AVL_EINVAL, "avl_trajectories_batched: need H, W >= 1 and H*W < 2^31");
+    if (n_tiles < 1 || n_masks < 1 || n_params < 1 || n_runs < 1)
+        return fail(AVL_EINVAL, "avl_trajectories_batched: need n_tiles, n_masks, n_params, n_runs >= 1");
+    const int64_t n = (int64_t)H * W;
+    const int64_t lim = (int64_t)0xFFFFFFFFll;
+    if ((int64_t)n_runs * n >= lim || (int64_t)n_tiles * n >= lim || (int64_t)n_masks * n >= lim)
+        return fail(AVL_EINVAL, "avl_trajectories_batched: n_runs*H*W, n_tiles*H*W, n_masks*H*W must be < 2^32 - 1");
+    if (!finite(cell_size) || !(cell_size > 0.0f))
+        return fail(AVL_EINVAL, "avl_trajectories_batched: cell_size must be > 0");
+    if (particles_per_cell == 0) return fail(AVL_EINVAL, "avl_trajectories_batched: particles_per_cell must be >= 1");
+    if (workspace_bytes < avl::batched_workspace_bytes(n, n_masks, n_runs))
+        return fail(AVL_ENOMEM, "avl_trajectories_batched: workspace too small");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    avl::Workspace ws = avl::carve_batched(workspace, n, n_masks, n_runs);
+
+    avl::TrajArgs a{};
+    a.dem = dems;
+    a.cells = ws.cells;
+    a.runs = ws.runs;
+    a.run_off = ws.run_off;
+    a.queues = ws.queues;
+    a.counts = counts;
+    a.vmax2 = reinterpret_cast<uint32_t*>(vmax);
+    a.stats = stats ? reinterpret_cast<unsigned long long*>(stats) : ws.stats;
+    a.H = H;
+    a.W = W;
+    a.n_runs = (uint32_t)n_runs;
+    a.S = step_limit;
+    a.g2 = 9.81f + 9.81f;
+    a.xcd_stride = 0;
+    const int64_t raster = (int64_t)n_runs * n;
+
+    auto zero = [&]() -> hipError_t {
+        hipError_t e;
+        if ((e = avl::launch_fill_u32(counts, 0u, raster, s)) != hipSuccess) return e;
+        if ((e = avl::launch_fill_u32(a.vmax2, 0u, raster, s)) != hipSuccess) return e;
+        if ((e = avl::launch_fill_u64(ws.queues, 0ull, avl::kXcds, s)) != hipSuccess) return e;
+        return avl::launch_fill_u64(a.stats, 0ull, 4 * (int64_t)n_runs, s);
+    };
+    // release-cell lists of every scenario, then the run table
+    auto prologue = [&]() -> hipError_t {
+        hipError_t e;
+        for (int32_t m = 0; m < n_masks; ++m)
+            if ((e = avl::launch_compact(masks + (size_t)m * n, n, ws.cells + (size_t)m * n, ws.n_cells + m, ws.blk,
+                                         s)) != hipSuccess)
+                return e;
+        const avl::RunSpec none{};
+        const avl_params none_p{};
+        return avl::launch_setup_runs(reinterpret_cast<const avl::RunSpec*>(runs), params, (uint32_t)n_params, none,
+                                      none_p, ws.n_cells, (uint32_t)n_masks, (uint32_t)n_tiles, (uint32_t)n_runs, H, W,
+                                      cell_size, particles_per_cell, true, ws.runs, ws.run_off, run_status, s);
+    };
+    auto body = [&](const avl::LaunchShape& shape) -> hipError_t {
+        hipError_t e;
+        if ((e = prologue()) != hipSuccess) return e;
+        if ((e = zero()) != hipSuccess) return e;
+        if ((e = avl::launch_trajectories(a, true, shape, s)) != hipSuccess) return e;
+        return avl::launch_finalize_vmax(a.vmax2, raster, s);
+    };
+
+    // the variant is chosen eagerly, before any capture (tuning runs need the run table in place)
+    hipError_t e;
+    int variant = 0;
+    const std::vector<int64_t> tkey = tune_key(true, n, n_runs, particles_per_cell, step_limit);
+    bool known = false;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        known = g_variant_override >= 0 || g_best.count(tkey) != 0;
+    }
+    if (!known && !capturing(s)) {
+        if ((e = prologue()) != hipSuccess) return hip_fail(e, "avl_trajectories_batched: setup");
+    }
+    if ((e = choose_variant(a, true, tkey, s, zero, &variant)) != hipSuccess)
+        return hip_fail(e, "avl_trajectories_batched: autotune");
+    g_last_variant = variant;
+    const avl::LaunchShape shape = avl::trajectory_shape(true, variant);  // queried outside any capture
+
+    bool use_graph;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        use_graph = g_graphs && s != nullptr;
+    }
+    if (!use_graph || capturing(s)) {
+        e = body(shape);
+        return e == hipSuccess ? AVL_OK : hip_fail(e, "avl_trajectories_batched");
+    }
+
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    uint32_t cs_bits;
+    std::memcpy(&cs_bits, &cell_size, 4);
+    const std::vector<uint64_t> key{
+        (uint64_t)dev, (uint64_t)(uintptr_t)s, (uint64_t)(uintptr_t)dems, (uint64_t)n_tiles, (uint64_t)(uintptr_t)masks,
+        (uint64_t)n_masks, (uint64_t)H, (uint64_t)W, cs_bits, (uint64_t)(uintptr_t)params, (uint64_t)n_params,
+        (uint64_t)(uintptr_t)runs, (uint64_t)n_runs, particles_per_cell, step_limit, (uint64_t)(uintptr_t)counts,
+        (uint64_t)(uintptr_t)vmax, (uint64_t)(uintptr_t)stats, (uint64_t)(uintptr_t)run_status,
+        (uint64_t)(uintptr_t)workspace, (uint64_t)variant};
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_graph_cache.find(key);
+    if (it == g_graph_cache.end()) {
+        if (g_graph_cache.size() >= kMaxGraphs) {
+            auto old = g_graph_cache.begin();
+            for (auto j = g_graph_cache.begin(); j != g_graph_cache.end(); ++j)
+                if (j->second.last_use < old->second.last_use) old = j;
+            (void)hipGraphExecDestroy(old->second.exec);
+            g_graph_cache.erase(old);
+        }
+        if ((e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+            return hip_fail(e, "avl_trajectories_batched: begin capture");
+        const hipError_t eb = body(shape);
+        hipGraph_t graph = nullptr;
+        e = hipStreamEndCapture(s, &graph);
+        if (eb != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return hip_fail(eb, "avl_trajectories_batched: capture");
+        }
+        if (e != hipSuccess) return hip_fail(e, "avl_trajectories_batched: end capture");
+        hipGraphExec_t exec = nullptr;
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) return hip_fail(e, "avl_trajectories_batched: instantiate");
+        it = g_graph_cache.emplace(key, GraphEntry{exec, 0}).first;
+    }
+    it->second.last_use = ++g_clock;
+    if ((e = hipGraphLaunch(it->second.exec, s)) != hipSuccess) return hip_fail(e, "avl_trajectories_batched: launch");
     return AVL_OK;
 }
 

@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include "../../include/avl.h"
+
 #include <cstddef>
 #include <cstdint>
 
@@ -11,51 +13,82 @@ namespace avl {
 constexpr int kWave = 64;
 
 // ------------------------------------------------------------------ workspace layout
-// [0, 256)            control block: n_cells (i32 @0), internal stats (4 x u64 @16), one particle-slot
-//                     queue per XCD (kXcds x u64 @64)
-// [256, 256 + B)      per-block counts / offsets of the compaction scan (u32 each), B rounded to 256
-// [.., .. + 4 H W)    release-cell list (i32), rounded to 256
-// [.., .. + 2 kXcds 4 H W)  per-XCD private count rasters, then per-XCD private v^2-bit rasters
+// Single run (avl_workspace_bytes):
+//   [0, 512)     control block: n_cells (i32 @0), stats (4 x u64 @64), per-XCD slot queues (kXcds x u64
+//                @128), run offsets (2 x u64 @192), the run's constants (RunConst @256)
+//   then         per-block sums of the compaction scan (u32), the release-cell list (i32, H*W), and the
+//                per-XCD private rasters: kXcds count rasters, then kXcds v^2-bit rasters (u32, H*W each)
+// Batch (avl_batched_workspace_bytes):
+//   [0, 512)     control block: per-XCD slot queues @128
+//   then         compaction scan sums; n_masks release-cell lists (i32, H*W each); n_masks cell counts;
+//                n_runs RunConst; n_runs + 1 slot offsets; n_runs x 4 internal statistics
+// Every region starts on a 256-byte boundary.
 constexpr int kXcds = 8;            // MI355X: 8 XCDs, each with its own L2
 constexpr int kScanThreads = 256;
 constexpr int kScanPerThread = 16;
 constexpr int kScanChunk = kScanThreads * kScanPerThread;  // cells per compaction block
+constexpr size_t kControl = 512;
 
 inline size_t round256(size_t v) { return (v + 255) & ~size_t(255); }
 inline int64_t scan_blocks(int64_t n) { return (n + kScanChunk - 1) / kScanChunk; }
 
+struct RunConst;
+
 struct Workspace {
-    int32_t* n_cells;
-    unsigned long long* queues;  // kXcds counters
-    unsigned long long* stats;
+    int32_t* n_cells;             // single: 1; batch: n_masks
+    unsigned long long* queues;   // kXcds counters
+    unsigned long long* stats;    // single: 4; batch: 4 x n_runs
+    unsigned long long* run_off;  // n_runs + 1
+    RunConst* runs;               // n_runs
     uint32_t* blk;
-    int32_t* cells;
-    uint32_t* priv_counts;  // kXcds x H*W
-    uint32_t* priv_vmax2;   // kXcds x H*W
+    int32_t* cells;               // single: H*W; batch: n_masks x H*W
+    uint32_t* priv_counts;        // single only: kXcds x H*W
+    uint32_t* priv_vmax2;         // single only: kXcds x H*W
 };
 
 size_t workspace_bytes(int64_t n);
 Workspace carve(void* base, int64_t n);
+size_t batched_workspace_bytes(int64_t n, int64_t n_masks, int64_t n_runs);
+Workspace carve_batched(void* base, int64_t n, int64_t n_masks, int64_t n_runs);
 
 // ------------------------------------------------------------------ trajectory kernel arguments
+// Derived constants of one run (one parameter set on one DEM tile and release scenario), binary32,
+// computed on the device by k_setup_runs in the model's order.
+struct RunConst {
+    float per, Q, rnd, L;      // persistence, 1 - persistence, randomness, step length (cells)
+    float dl2, mdl, cd, tca;   // (L cs)^2, mu L cs, 2g / (xi h), tan(alpha) cs
+    uint32_t key0, key1;       // Philox key = 64-bit seed
+    uint32_t run, use_alpha;   // Philox counter word 3; runout-angle stop on/off
+    uint32_t dem_off;          // element offset of the run's DEM tile
+    uint32_t cells_off;        // element offset of the run's release-cell list
+    uint32_t raster_off;       // element offset of the run's rasters
+    uint32_t P;                // particles per release cell
+    unsigned long long n_slots;  // release cells x P
+    unsigned long long pad;
+};
+static_assert(sizeof(RunConst) == 80, "RunConst layout");
+
 struct TrajArgs {
-    const float* __restrict__ dem;
-    const int32_t* __restrict__ cells;
-    const int32_t* __restrict__ n_cells;
-    unsigned long long* __restrict__ queues;  // kXcds slot counters, zero at launch
-    uint32_t* __restrict__ counts;  // kXcds private count rasters (H*W each), zero at launch
-    uint32_t* __restrict__ vmax2;   // kXcds private rasters of the binary32 bits of the per-cell max of v^2
-                                    // (v^2 >= 0, so bit order is value order), zero at launch
-    unsigned long long* __restrict__ stats;
+    const float* __restrict__ dem;               // all DEM tiles, H*W each
+    const int32_t* __restrict__ cells;           // all release-cell lists, H*W each
+    const RunConst* __restrict__ runs;           // n_runs
+    const unsigned long long* __restrict__ run_off;  // n_runs + 1 slot offsets, each a multiple of 64
+    unsigned long long* __restrict__ queues;     // kXcds slot counters, zero at launch
+    uint32_t* __restrict__ counts;               // count rasters, zero at launch
+    uint32_t* __restrict__ vmax2;                // binary32 bits of the per-cell max of v^2 (v^2 >= 0, so bit
+                                                 // order is value order), zero at launch
+    unsigned long long* __restrict__ stats;      // 4 u64 per run: steps, exits, stops, step-limit ends
     int32_t H, W;
-    float g2, per, Q, rnd, L, dl2, mdl, cd, tca;
-    int32_t use_alpha;
-    uint32_t P, S, run, key0, key1;
+    uint32_t n_runs;
+    uint32_t S;                                  // step limit
+    float g2;                                    // 2g
+    uint32_t xcd_stride;  // single run: elements between the per-XCD private rasters; batched: 0
 };
 
 struct LaunchShape {
     int block;  // threads per block (multiple of 64)
     int grid;   // blocks
+    int variant;  // kernel variant index (see trajectory_variants)
 };
 
 // ------------------------------------------------------------------ launchers (enqueue only; return hipError_t)
@@ -68,9 +101,22 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t n, hipStream_t s);
 hipError_t launch_merge_rasters(const uint32_t* priv_counts, const uint32_t* priv_vmax2, int64_t n, uint32_t* counts,
                                 float* vmax, hipStream_t s);
-hipError_t launch_trajectories(const TrajArgs& a, const LaunchShape& shape, hipStream_t s);
+// Setup of the run table: per run, constants from its parameter set and the slot count from its
+// scenario's release-cell count (written by the compaction); then 64-aligned slot offsets.
+struct RunSpec {
+    uint32_t tile, scenario, param, run_id;
+    unsigned long long seed;
+};
+// specs/params: device arrays (batched) or NULL, then one_spec/one_param are used for the single run.
+hipError_t launch_setup_runs(const RunSpec* specs, const ::avl_params* params, uint32_t n_params, RunSpec one_spec,
+                             ::avl_params one_param, const int32_t* n_cells_per_scen, uint32_t n_scen, uint32_t n_tiles,
+                             uint32_t n_runs, int32_t H, int32_t W, float cell_size, uint32_t P, bool batched,
+                             RunConst* runs, unsigned long long* run_off, int32_t* status, hipStream_t s);
+hipError_t launch_trajectories(const TrajArgs& a, bool batched, const LaunchShape& shape, hipStream_t s);
+hipError_t launch_finalize_vmax(uint32_t* vmax_bits, int64_t n, hipStream_t s);
 
-// persistent-grid shape for the trajectory kernel on the current device
-LaunchShape trajectory_shape();
+// Persistent-grid shape of kernel variant `variant` on the current device; number of variants.
+LaunchShape trajectory_shape(bool batched, int variant);
+int trajectory_variants();
 
 }  // namespace avl

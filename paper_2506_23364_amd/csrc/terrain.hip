@@ -239,6 +239,21 @@ __global__ __launch_bounds__(256) void k_merge_rasters(const uint32_t* __restric
     vmax[i] = sqrtf(__uint_as_float(v));
 }
 
+// v^2 bits -> speed, in place: vmax = sqrt(max v^2)
+__global__ __launch_bounds__(256) void k_finalize_vmax(uint32_t* __restrict__ bits, int64_t n) {
+    const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+    if (i0 + 4 <= n && (reinterpret_cast<uintptr_t>(bits + i0) & 15) == 0) {
+        uint4 b = *reinterpret_cast<uint4*>(bits + i0);
+        b.x = __float_as_uint(sqrtf(__uint_as_float(b.x)));
+        b.y = __float_as_uint(sqrtf(__uint_as_float(b.y)));
+        b.z = __float_as_uint(sqrtf(__uint_as_float(b.z)));
+        b.w = __float_as_uint(sqrtf(__uint_as_float(b.w)));
+        *reinterpret_cast<uint4*>(bits + i0) = b;
+    } else {
+        for (int64_t i = i0; i < n && i < i0 + 4; ++i) bits[i] = __float_as_uint(sqrtf(__uint_as_float(bits[i])));
+    }
+}
+
 static unsigned blocks_for(int64_t items, int per_thread) {
     const int64_t threads = (items + per_thread - 1) / per_thread;
     return (unsigned)((threads + 255) / 256);
@@ -253,6 +268,12 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s) {
 hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_fill_u64, dim3(blocks_for(n, 1)), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize_vmax(uint32_t* vmax_bits, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_finalize_vmax, dim3(blocks_for(n, 4)), dim3(256), 0, s, vmax_bits, n);
     return hipGetLastError();
 }
 

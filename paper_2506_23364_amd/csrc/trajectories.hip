@@ -1,25 +1,28 @@
 // Particle trajectories of the avalanche overlay (section 5.2 of arXiv 2506.23364, the trajectory node):
 // particles released per coded texel, steered by persistence and a random deviation from the optimal
 // (downslope) path, slowed by Coulomb/Voellmy friction, stopped by the energy line or a runout angle;
-// accumulated into a hit-count raster and a max-velocity raster.
+// accumulated into a hit-count raster and a max-velocity raster. One kernel serves a single run and a
+// batch of runs (parameter sets x DEM tiles x release scenarios) in one persistent launch.
 //
 // Design for gfx950 (measured choices; the alternatives are recorded in the design notes):
 //  - One persistent grid sized to the chip's occupancy; one lane carries one particle at a time and its
 //    whole state stays in VGPRs. A lane whose particle ended takes the next particle slot in the same
 //    iteration, from a per-wave reservoir refilled 64 slots at a time from a device-wide counter.
-//  - Slots are ordered replica-major within a release cell, so the 64 lanes of a wave mostly carry
+//  - Slots are ordered replica-major within a release cell and run-major across runs; every run starts
+//    at a multiple of 64, so a 64-slot chunk belongs to one run. The 64 lanes of a wave mostly carry
 //    replicas of one release cell: their 2x2 DEM gathers hit the same L2 lines, and their paths enter
 //    the same cells.
 //  - The slot range is split into one partition per XCD; a wave starts on its own XCD's partition and
 //    moves on to the others only when it is empty. Each XCD's L2 then holds its own band of the DEM and
-//    of the rasters instead of all eight caching the same band.
+//    rasters (or its own runs) instead of all eight caching the same band.
 //  - Hit counts and per-cell max v^2 go first into a wave-private direct-mapped table in LDS (tag,
-//    count, max), flushed to the rasters every kFlushEvery iterations. Replicas on overlapping paths
-//    then cost one global atomic per cell and flush period instead of one per entry. A cell whose slot
-//    is held by another cell goes straight to the global raster.
-//  - The global rasters are private per XCD (merged after the kernel), so no two XCDs update one line.
+//    count, max), flushed to the rasters every kFlush iterations. Replicas on overlapping paths then
+//    cost one global atomic per cell and flush period instead of one per entry. A cell whose slot is
+//    held by another cell goes straight to the global raster.
+//  - A single run accumulates into private per-XCD rasters (merged after the kernel), so no two XCDs
+//    update one line; a batch writes each run's own rasters, which the XCD partition already separates.
 //  - Accumulation is integer only (u32 add; u32 max on the bits of v^2 >= 0, whose order is the value
-//    order), so every raster is independent of scheduling: bit-reproducible.
+//    order), so every raster is independent of scheduling and of the kernel variant: bit-reproducible.
 //  - Philox4x32-10 gives four words per block; one block serves two consecutive steps.
 #include "avl_internal.h"
 
@@ -28,11 +31,8 @@ namespace avl {
 namespace {
 
 constexpr int kTbl = 256;          // table slots per wave (power of two)
-constexpr int kFlushEvery = 16;    // iterations between table flushes
 constexpr uint32_t kChunk = 64;    // particle slots taken from a queue per reservoir refill
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;
-constexpr int kBlock = 256;
-constexpr int kWavesPerBlock = kBlock / kWave;
 
 // Philox4x32-10 (Salmon et al., SC'11): ten rounds of the 4x32 multiply-xor bijection with a Weyl key
 // schedule.
@@ -119,23 +119,72 @@ __device__ __forceinline__ void global_max(uint32_t* __restrict__ p, uint32_t bi
     if (__builtin_nontemporal_load(p) < bits) atomicMax(p, bits);
 }
 
+// Run holding padded slot `slot`: the r with run_off[r] <= slot < run_off[r + 1]. Wave-uniform input.
+__device__ __forceinline__ uint32_t find_run(const unsigned long long* __restrict__ off, uint32_t n_runs,
+                                             uint64_t slot) {
+    uint32_t lo = 0, hi = n_runs;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (off[mid] <= slot)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ float uniform_f(float v) {
+    return __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(v)));
+}
+__device__ __forceinline__ uint32_t uniform_u(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// The run constants held in scalar registers (the single-run kernel: every lane has the same run).
+__device__ __forceinline__ RunConst uniform_run(const RunConst& r) {
+    RunConst u = r;
+    u.per = uniform_f(r.per);
+    u.Q = uniform_f(r.Q);
+    u.rnd = uniform_f(r.rnd);
+    u.L = uniform_f(r.L);
+    u.dl2 = uniform_f(r.dl2);
+    u.mdl = uniform_f(r.mdl);
+    u.cd = uniform_f(r.cd);
+    u.tca = uniform_f(r.tca);
+    u.key0 = uniform_u(r.key0);
+    u.key1 = uniform_u(r.key1);
+    u.run = uniform_u(r.run);
+    u.use_alpha = uniform_u(r.use_alpha);
+    u.dem_off = uniform_u(r.dem_off);
+    u.cells_off = uniform_u(r.cells_off);
+    u.raster_off = uniform_u(r.raster_off);
+    u.P = uniform_u(r.P);
+    u.n_slots = ((unsigned long long)uniform_u((uint32_t)(r.n_slots >> 32)) << 32) | uniform_u((uint32_t)r.n_slots);
+    return u;
+}
+
+// start of XCD partition p of the padded slot range [0, total): a multiple of kChunk
+__device__ __forceinline__ uint64_t part_begin(uint64_t total, uint32_t p) {
+    if (p >= (uint32_t)kXcds) return total;
+    return (total / kChunk * p / kXcds) * kChunk;
+}
+
 }  // namespace
 
+template <bool kBatch, int kBlock, int kFlush>
 __global__ __launch_bounds__(kBlock) void k_trajectories(TrajArgs a) {
-    __shared__ uint32_t s_tag[kWavesPerBlock][kTbl], s_cnt[kWavesPerBlock][kTbl], s_vmx[kWavesPerBlock][kTbl];
+    constexpr int kWaves = kBlock / kWave;
+    __shared__ uint32_t s_tag[kWaves][kTbl], s_cnt[kWaves][kTbl], s_vmx[kWaves][kTbl];
     const int lane = threadIdx.x & (kWave - 1);
     const int wv = threadIdx.x / kWave;
     uint32_t* const tag = s_tag[wv];
     uint32_t* const cnt = s_cnt[wv];
     uint32_t* const vmx = s_vmx[wv];
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
-    const uint64_t total = (uint64_t)(uint32_t)(*a.n_cells) * (uint64_t)a.P;
+    const uint64_t total = wave_bcast64(a.run_off[a.n_runs]);
     const int W = a.W, H = a.H;
     const float fW = (float)W, fH = (float)H;
     const uint32_t xcd = xcd_id();
-    const size_t n_cells_grid = (size_t)H * W;
-    uint32_t* const counts = a.counts + xcd * n_cells_grid;
-    uint32_t* const vmax2 = a.vmax2 + xcd * n_cells_grid;
+    uint32_t* const counts = a.counts + (size_t)xcd * a.xcd_stride;
+    uint32_t* const vmax2 = a.vmax2 + (size_t)xcd * a.xcd_stride;
 
     for (int k = lane; k < kTbl; k += kWave) {
         lds_st(tag + k, kEmpty);
@@ -167,26 +216,63 @@ __global__ __launch_bounds__(kBlock) void k_trajectories(TrajArgs a) {
         }
     };
 
-    // wave-uniform queue state: partition being drained, partitions found empty, slot reservoir
+    // constants of the run a lane works on: uniform for a single run, per lane in a batch
+    RunConst rc = uniform_run(a.runs[0]);
+    uint32_t b = 0;  // run index of the lane's particle (batched)
+
+    // per-lane statistics of run b
+    uint64_t st_steps = 0;
+    uint32_t st_exit = 0, st_stop = 0, st_limit = 0;
+    auto flush_stats = [&](bool has) {
+        // all lanes that have counters to flush belong to one run: reduce across the wave
+        const uint64_t m = __ballot(has);
+        if (!m) return;
+        const int leader = __ffsll((long long)m) - 1;
+        const uint32_t lb = __builtin_amdgcn_readlane(b, leader);
+        if (__ballot(has && b != lb) == 0) {
+            const uint64_t s0 = wave_sum64(has ? st_steps : 0);
+            const uint64_t s1 = wave_sum64(has ? st_exit : 0), s2 = wave_sum64(has ? st_stop : 0);
+            const uint64_t s3 = wave_sum64(has ? st_limit : 0);
+            if (lane == leader) {
+                unsigned long long* st = a.stats + 4 * (size_t)lb;
+                if (s0) atomicAdd(st + 0, (unsigned long long)s0);
+                if (s1) atomicAdd(st + 1, (unsigned long long)s1);
+                if (s2) atomicAdd(st + 2, (unsigned long long)s2);
+                if (s3) atomicAdd(st + 3, (unsigned long long)s3);
+            }
+        } else if (has) {
+            unsigned long long* st = a.stats + 4 * (size_t)b;
+            if (st_steps) atomicAdd(st + 0, (unsigned long long)st_steps);
+            if (st_exit) atomicAdd(st + 1, (unsigned long long)st_exit);
+            if (st_stop) atomicAdd(st + 2, (unsigned long long)st_stop);
+            if (st_limit) atomicAdd(st + 3, (unsigned long long)st_limit);
+        }
+        if (has) {
+            st_steps = 0;
+            st_exit = st_stop = st_limit = 0;
+        }
+    };
+
+    // wave-uniform queue state: partition being drained, partitions found empty, slot reservoir and
+    // the run its slots belong to
     uint32_t part = xcd;
     uint32_t tried = 0;
     bool queue_empty = (total == 0);
     uint64_t res_next = 0, res_end = 0;
+    uint32_t res_run = 0;
 
     // lane state
     bool alive = false;
     float x = 0, y = 0, z = 0, gx = 0, gy = 0, dx = 0, dy = 0, v2 = 0, x0 = 0, y0 = 0, zr = 0, cmax2 = 0;
     uint32_t n = 0, rep = 0, cell_id = 0, spare_x = 0, spare_y = 0, cur = 0;
     int my_slot = -1;  // table slot of the current cell, -1 if none
-    uint64_t lane_steps = 0;
-    uint32_t n_exit = 0, n_stop = 0, n_limit = 0;
 
     for (uint32_t iter = 1;; ++iter) {
         const uint64_t idle = __ballot(!alive);
         const int nidle = __popcll(idle);
         const bool drained = queue_empty && res_next >= res_end;
         if (nidle == kWave && drained) break;
-        if (iter % kFlushEvery == 0) {
+        if (iter % kFlush == 0) {
             flush();
             my_slot = -1;
         }
@@ -197,6 +283,7 @@ __global__ __launch_bounds__(kBlock) void k_trajectories(TrajArgs a) {
             const uint64_t avail = res_end - res_next;
             const int rank = __popcll(idle & below);
             uint64_t slot = ~0ull;
+            uint32_t srun = res_run;
             if (avail >= (uint64_t)nidle) {
                 slot = res_next + rank;
                 res_next += nidle;
@@ -204,7 +291,7 @@ __global__ __launch_bounds__(kBlock) void k_trajectories(TrajArgs a) {
                 uint64_t base = 0, cend = 0;
                 const int leader = __ffsll((long long)idle) - 1;
                 while (!queue_empty) {
-                    const uint64_t pb = total * part / kXcds, pe = total * (part + 1) / kXcds;
+                    const uint64_t pb = part_begin(total, part), pe = part_begin(total, part + 1);
                     uint64_t got = 0;
                     if (lane == leader) got = atomicAdd(a.queues + part, (unsigned long long)kChunk);
                     got = wave_bcast64(__shfl(got, leader, kWave));
@@ -216,24 +303,45 @@ __global__ __launch_bounds__(kBlock) void k_trajectories(TrajArgs a) {
                     part = (part + 1) % kXcds;
                     if (++tried >= (uint32_t)kXcds) queue_empty = true;
                 }
-                if ((uint64_t)rank < avail)
+                const uint32_t new_run = (kBatch && cend > base) ? find_run(a.run_off, a.n_runs, base) : 0u;
+                if ((uint64_t)rank < avail) {
                     slot = res_next + rank;
-                else if (base + (rank - avail) < cend)
+                } else if (base + (rank - avail) < cend) {
                     slot = base + (rank - avail);
+                    srun = new_run;
+                }
                 const uint64_t next = base + ((uint64_t)nidle - avail);
                 res_next = next < cend ? next : cend;
                 res_end = cend;
+                res_run = new_run;
             }
             if (!alive && slot < total) {
-                // release particle `slot`: cell list entry slot / P, replica slot % P
-                const uint64_t i = slot / a.P;
-                rep = (uint32_t)(slot - i * a.P);
-                cell_id = (uint32_t)a.cells[i];
+                const uint64_t local = kBatch ? slot - a.run_off[srun] : slot;
+                const uint64_t n_slots = kBatch ? a.runs[srun].n_slots : rc.n_slots;
+                const uint32_t P = kBatch ? a.runs[srun].P : rc.P;
+                const uint32_t cells_off = kBatch ? a.runs[srun].cells_off : rc.cells_off;
+                if (local < n_slots) {  // past n_slots: padding up to the next multiple of 64
+                    const uint64_t i = local / P;
+                    rep = (uint32_t)(local - i * P);
+                    cell_id = (uint32_t)a.cells[cells_off + i];
+                    fresh = true;
+                }
+            }
+            if (kBatch) {
+                // a lane's statistics belong to the run of its previous particle
+                flush_stats(fresh && srun != b);
+                if (fresh) {
+                    b = srun;
+                    rc = a.runs[b];
+                }
+            }
+            if (fresh) {
+                const float* dem = a.dem + rc.dem_off;
                 const int r = (int)(cell_id / (uint32_t)W);
                 const int c = (int)(cell_id - (uint32_t)r * (uint32_t)W);
                 x = (float)c + 0.5f;
                 y = (float)r + 0.5f;
-                const Sample s0 = bilinear(a.dem, H, W, x, y);
+                const Sample s0 = bilinear(dem, H, W, x, y);
                 z = s0.z;
                 gx = s0.gx;
                 gy = s0.gy;
@@ -252,9 +360,8 @@ __global__ __launch_bounds__(kBlock) void k_trajectories(TrajArgs a) {
                 v2 = 0.0f;
                 cmax2 = 0.0f;
                 n = 0;
-                cur = cell_id;
+                cur = rc.raster_off + cell_id;
                 alive = true;
-                fresh = true;
             }
         }
         if (fresh) {  // entry into the release cell
@@ -273,13 +380,13 @@ __global__ __launch_bounds__(kBlock) void k_trajectories(TrajArgs a) {
         if (alive) {
             bool ended = false;
             if (n >= a.S) {
-                ++n_limit;
+                ++st_limit;
                 ended = true;
             } else {
-                ++lane_steps;
+                ++st_steps;
                 uint32_t ux, uy;
                 if ((n & 1u) == 0u) {
-                    const uint4 o = philox4x32_10(n >> 1, rep, cell_id, a.run, a.key0, a.key1);
+                    const uint4 o = philox4x32_10(n >> 1, rep, cell_id, rc.run, rc.key0, rc.key1);
                     ux = o.x;
                     uy = o.y;
                     spare_x = o.z;
@@ -290,37 +397,37 @@ __global__ __launch_bounds__(kBlock) void k_trajectories(TrajArgs a) {
                 }
                 const float rx = signed_unit(ux), ry = signed_unit(uy);
                 const float gg = gx * gx + gy * gy;
-                const float t = gg > 0.0f ? a.Q / sqrtf(gg) : 0.0f;
-                const float wx = (a.per * dx - t * gx) + a.rnd * rx;
-                const float wy = (a.per * dy - t * gy) + a.rnd * ry;
+                const float t = gg > 0.0f ? rc.Q / sqrtf(gg) : 0.0f;
+                const float wx = (rc.per * dx - t * gx) + rc.rnd * rx;
+                const float wy = (rc.per * dy - t * gy) + rc.rnd * ry;
                 const float ww = wx * wx + wy * wy;
                 if (ww > 0.0f) {
                     const float inv = 1.0f / sqrtf(ww);
                     dx = wx * inv;
                     dy = wy * inv;
                 }
-                const float x1 = x + a.L * dx;
-                const float y1 = y + a.L * dy;
+                const float x1 = x + rc.L * dx;
+                const float y1 = y + rc.L * dy;
                 const float fc1 = floorf(x1), fr1 = floorf(y1);
                 if (!(fc1 >= 0.0f && fc1 < fW && fr1 >= 0.0f && fr1 < fH)) {
-                    ++n_exit;
+                    ++st_exit;
                     ended = true;
                 } else {
-                    const Sample s1 = bilinear(a.dem, H, W, x1, y1);
+                    const Sample s1 = bilinear(a.dem + rc.dem_off, H, W, x1, y1);
                     const float dz = z - s1.z;
-                    const float ds = sqrtf(a.dl2 + dz * dz);
-                    const float num = v2 + a.g2 * (dz - a.mdl);
+                    const float ds = sqrtf(rc.dl2 + dz * dz);
+                    const float num = v2 + a.g2 * (dz - rc.mdl);
                     bool stop = !(num > 0.0f);
                     float v2n = 0.0f;
                     if (!stop) {
-                        v2n = num / (1.0f + a.cd * ds);
-                        if (a.use_alpha) {
+                        v2n = num / (1.0f + rc.cd * ds);
+                        if (rc.use_alpha) {
                             const float hx = x1 - x0, hy = y1 - y0;
-                            stop = (zr - s1.z) < a.tca * sqrtf(hx * hx + hy * hy);
+                            stop = (zr - s1.z) < rc.tca * sqrtf(hx * hx + hy * hy);
                         }
                     }
                     if (stop) {
-                        ++n_stop;
+                        ++st_stop;
                         ended = true;
                     } else {
                         x = x1;
@@ -330,7 +437,8 @@ __global__ __launch_bounds__(kBlock) void k_trajectories(TrajArgs a) {
                         gy = s1.gy;
                         v2 = v2n;
                         ++n;
-                        const uint32_t nc = (uint32_t)(int)fr1 * (uint32_t)W + (uint32_t)(int)fc1;
+                        const uint32_t nc =
+                            rc.raster_off + (uint32_t)(int)fr1 * (uint32_t)W + (uint32_t)(int)fc1;
                         if (nc != cur) {
                             leave = cmax2 > 0.0f;
                             leave_bits = __float_as_uint(cmax2);
@@ -371,35 +479,162 @@ __global__ __launch_bounds__(kBlock) void k_trajectories(TrajArgs a) {
         }
     }
     flush();
-
-    // per-wave totals
-    const uint64_t s_steps = wave_sum64(lane_steps);
-    const uint64_t s_exit = wave_sum64(n_exit), s_stop = wave_sum64(n_stop), s_limit = wave_sum64(n_limit);
-    if (lane == 0) {
-        if (s_steps) atomicAdd(a.stats + 0, (unsigned long long)s_steps);
-        if (s_exit) atomicAdd(a.stats + 1, (unsigned long long)s_exit);
-        if (s_stop) atomicAdd(a.stats + 2, (unsigned long long)s_stop);
-        if (s_limit) atomicAdd(a.stats + 3, (unsigned long long)s_limit);
-    }
+    flush_stats(st_steps != 0 || st_exit != 0 || st_stop != 0 || st_limit != 0);
 }
 
-hipError_t launch_trajectories(const TrajArgs& a, const LaunchShape& shape, hipStream_t s) {
-    hipLaunchKernelGGL(k_trajectories, dim3(shape.grid), dim3(shape.block), 0, s, a);
+// ------------------------------------------------------------------------------------------ run table
+
+// One block: per run, derived constants and slot counts, then the exclusive scan of the padded slot
+// counts. A run with an index out of range or invalid parameters gets no slots and status != 0.
+__global__ __launch_bounds__(1024) void k_setup_runs(const RunSpec* __restrict__ specs,
+                                                     const ::avl_params* __restrict__ params, uint32_t n_params,
+                                                     RunSpec one_spec, ::avl_params one_param,
+                                                     const int32_t* __restrict__ n_cells_per_scen, uint32_t n_scen,
+                                                     uint32_t n_tiles, uint32_t n_runs, int32_t H, int32_t W,
+                                                     float cs, uint32_t P, int32_t batched,
+                                                     RunConst* __restrict__ runs,
+                                                     unsigned long long* __restrict__ run_off,
+                                                     int32_t* __restrict__ status) {
+    __shared__ unsigned long long wsum[1024 / kWave];
+    const uint32_t per_thread = (n_runs + 1023) / 1024;
+    const uint32_t b0 = threadIdx.x * per_thread;
+    const uint64_t HW = (uint64_t)H * W;
+    unsigned long long local = 0;
+    for (uint32_t k = 0; k < per_thread; ++k) {
+        const uint32_t r = b0 + k;
+        if (r >= n_runs) break;
+        const RunSpec sp = specs ? specs[r] : one_spec;
+        int32_t bad = 0;
+        if (sp.tile >= n_tiles || sp.scenario >= n_scen || (specs && sp.param >= n_params)) bad = 1;
+        ::avl_params p = one_param;
+        if (!bad && specs) p = params[sp.param];
+        if (!bad) {
+            const bool ok = __builtin_isfinite(p.mu) && p.mu >= 0.0f && !__builtin_isnan(p.xi) && p.xi > 0.0f &&
+                            __builtin_isfinite(p.flow_height) && p.flow_height > 0.0f && p.persistence >= 0.0f &&
+                            p.persistence <= 1.0f && __builtin_isfinite(p.randomness) && p.randomness >= 0.0f &&
+                            __builtin_isfinite(p.step_cells) && p.step_cells > 0.0f && p.step_cells <= 16.0f &&
+                            __builtin_isfinite(p.tan_alpha) && p.flags == 0u;
+            if (!ok) bad = 2;
+        }
+        RunConst c{};
+        // derived constants, binary32, in this order
+        const float g = 9.81f;
+        const float g2 = g + g;
+        c.per = p.persistence;
+        c.Q = 1.0f - c.per;
+        c.rnd = p.randomness;
+        c.L = p.step_cells;
+        const float dl = c.L * cs;
+        c.dl2 = dl * dl;
+        c.mdl = p.mu * dl;
+        c.cd = g2 / (p.xi * p.flow_height);
+        c.use_alpha = p.tan_alpha >= 0.0f ? 1u : 0u;
+        c.tca = p.tan_alpha * cs;
+        c.key0 = (uint32_t)sp.seed;
+        c.key1 = (uint32_t)(sp.seed >> 32);
+        c.run = sp.run_id;
+        c.dem_off = (uint32_t)(sp.tile * HW);
+        c.cells_off = (uint32_t)(sp.scenario * HW);
+        c.raster_off = batched ? (uint32_t)(r * HW) : 0u;
+        c.P = P;
+        c.n_slots = bad ? 0ull : (unsigned long long)(uint32_t)n_cells_per_scen[sp.scenario] * P;
+        runs[r] = c;
+        if (status) status[r] = bad;
+        local += (c.n_slots + kChunk - 1) / kChunk * kChunk;
+    }
+    // exclusive scan of the per-thread sums
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    unsigned long long inc = local;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const unsigned long long t = __shfl_up(inc, d, kWave);
+        if (lane >= d) inc += t;
+    }
+    if (lane == kWave - 1) wsum[wid] = inc;
+    __syncthreads();
+    unsigned long long before = 0, tot = 0;
+    for (int k = 0; k < 1024 / kWave; ++k) {
+        before += (k < wid) ? wsum[k] : 0ull;
+        tot += wsum[k];
+    }
+    unsigned long long run = before + inc - local;
+    for (uint32_t k = 0; k < per_thread; ++k) {
+        const uint32_t r = b0 + k;
+        if (r >= n_runs) break;
+        run_off[r] = run;
+        run += (runs[r].n_slots + kChunk - 1) / kChunk * kChunk;
+    }
+    if (threadIdx.x == 0) run_off[n_runs] = tot;
+}
+
+hipError_t launch_setup_runs(const RunSpec* specs, const ::avl_params* params, uint32_t n_params, RunSpec one_spec,
+                             ::avl_params one_param, const int32_t* n_cells_per_scen, uint32_t n_scen, uint32_t n_tiles,
+                             uint32_t n_runs, int32_t H, int32_t W, float cell_size, uint32_t P, bool batched,
+                             RunConst* runs, unsigned long long* run_off, int32_t* status, hipStream_t s) {
+    hipLaunchKernelGGL(k_setup_runs, dim3(1), dim3(1024), 0, s, specs, params, n_params, one_spec, one_param,
+                       n_cells_per_scen, n_scen, n_tiles, n_runs, H, W, cell_size, P, batched ? 1 : 0, runs, run_off,
+                       status);
     return hipGetLastError();
 }
 
-LaunchShape trajectory_shape() {
+// ------------------------------------------------------------------------------------------ variants
+
+namespace {
+
+struct Variant {
+    const void* single;
+    const void* batch;
+    int block;
+    void (*launch_single)(dim3, dim3, hipStream_t, const TrajArgs&);
+    void (*launch_batch)(dim3, dim3, hipStream_t, const TrajArgs&);
+};
+
+template <bool B, int Blk, int F>
+void launch_t(dim3 g, dim3 t, hipStream_t s, const TrajArgs& a) {
+    hipLaunchKernelGGL((k_trajectories<B, Blk, F>), g, t, 0, s, a);
+}
+
+template <int Blk, int F>
+constexpr Variant make_variant() {
+    return Variant{reinterpret_cast<const void*>(&k_trajectories<false, Blk, F>),
+                   reinterpret_cast<const void*>(&k_trajectories<true, Blk, F>), Blk, &launch_t<false, Blk, F>,
+                   &launch_t<true, Blk, F>};
+}
+
+// candidates of the autotuner: (threads per block, iterations between table flushes)
+const Variant kVariants[] = {
+    make_variant<256, 16>(), make_variant<256, 8>(), make_variant<256, 32>(), make_variant<128, 16>(),
+    make_variant<512, 16>(),
+};
+
+}  // namespace
+
+int trajectory_variants() { return (int)(sizeof(kVariants) / sizeof(kVariants[0])); }
+
+LaunchShape trajectory_shape(bool batched, int variant) {
+    if (variant < 0 || variant >= trajectory_variants()) variant = 0;
+    const Variant& v = kVariants[variant];
+    LaunchShape sh{v.block, 2048, variant};
     int dev = 0;
-    LaunchShape sh{kBlock, 2048};
     if (hipGetDevice(&dev) != hipSuccess) return sh;
     int cus = 0, per_cu = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) return sh;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k_trajectories),
-                                                     sh.block, 0) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batched ? v.batch : v.single, v.block, 0) !=
+            hipSuccess ||
         per_cu <= 0)
-        per_cu = 4;
+        per_cu = 1;
     sh.grid = cus * per_cu;
     return sh;
+}
+
+hipError_t launch_trajectories(const TrajArgs& a, bool batched, const LaunchShape& shape, hipStream_t s) {
+    const int vi = (shape.variant >= 0 && shape.variant < trajectory_variants()) ? shape.variant : 0;
+    const Variant& v = kVariants[vi];
+    if (batched)
+        v.launch_batch(dim3(shape.grid), dim3(v.block), s, a);
+    else
+        v.launch_single(dim3(shape.grid), dim3(v.block), s, a);
+    return hipGetLastError();
 }
 
 }  // namespace avl

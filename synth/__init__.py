@@ -229,3 +229,73 @@ def make_workload(name: str) -> Workload:
         p = dict(DEFAULT_PARAMS)
         return Workload(name, dem, 5.0, 30.0, 45.0, nearest_rank(dem, LARGE_Q), inf, 64, 8000, p, seed=3)
     raise KeyError(name)
+
+
+# --------------------------------------------------------------------------------------------- ensembles
+
+@dataclass
+class Ensemble:
+    """Batched workload: DEM tiles, one release scenario per tile, parameter sets and the run table
+    (tile, scenario, param, run_id, seed) crossing every scenario with every parameter set."""
+    dems: np.ndarray          # (n_tiles, H, W) float32
+    masks: np.ndarray         # (n_masks, H, W) uint8
+    params: list              # dicts of model parameters
+    runs: list                # (tile, scenario, param, run_id, seed)
+    cell_size: float
+    particles_per_cell: int
+    step_limit: int
+
+
+def slope_deg(dem: np.ndarray, cell_size: float) -> np.ndarray:
+    """Terrain slope in degrees from numpy.gradient (float64), for choosing scenario cells."""
+    gy, gx = np.gradient(dem.astype(np.float64), cell_size)
+    return np.degrees(np.arctan(np.hypot(gx, gy)))
+
+
+def grow_region(score: np.ndarray, n_cells: int, start: int) -> np.ndarray:
+    """Connected region of n_cells cells (4-neighbourhood) grown best-first from `start`: the frontier
+    cell with the highest score joins next. Returns a uint8 mask."""
+    import heapq
+    h, w = score.shape
+    flat = score.ravel()
+    out = np.zeros(h * w, dtype=np.uint8)
+    seen = np.zeros(h * w, dtype=bool)
+    heap = [(-float(flat[start]), start)]
+    seen[start] = True
+    taken = 0
+    while heap and taken < n_cells:
+        _, p = heapq.heappop(heap)
+        out[p] = 1
+        taken += 1
+        r, c = divmod(p, w)
+        for rr, cc in ((r - 1, c), (r + 1, c), (r, c - 1), (r, c + 1)):
+            if 0 <= rr < h and 0 <= cc < w:
+                q = rr * w + cc
+                if not seen[q]:
+                    seen[q] = True
+                    heapq.heappush(heap, (-float(flat[q]), q))
+    return out.reshape(h, w)
+
+
+def make_ensemble(n_tiles: int = 16, size: int = 1024, n_params: int = 64, particles_per_cell: int = 32,
+                  step_limit: int = 2000, relief_m: float = 2000.0, cell_size: float = 10.0,
+                  min_cells: int = 100, max_cells: int = 50000, seed: int = 12345) -> Ensemble:
+    """The ensemble sweep: n_tiles ridged-fBm tiles (seeds 100, 101, ...), each with one connected release
+    scenario of round(exp(U(ln min_cells, ln max_cells))) cells (sizes from seed 7): grown best-first
+    (closest to 37.5 degrees first) from a seeded start cell of 30-45 degrees in the upper half of the
+    elevations; crossed with n_params parameter sets mu ~ U[0.1, 0.4], xi ~ U[500, 3000], h ~ U[0.5, 3]
+    (seed 8); persistence 0.9, randomness 0.16."""
+    dems = np.stack([alpine_dem(size, relief_m, seed=100 + t) for t in range(n_tiles)])
+    rng = np.random.default_rng(7)
+    sizes = np.rint(np.exp(rng.uniform(math.log(min_cells), math.log(max_cells), n_tiles))).astype(int)
+    masks = []
+    for t in range(n_tiles):
+        sl = slope_deg(dems[t], cell_size)
+        cand = np.flatnonzero(((sl >= 30.0) & (sl <= 45.0) & (dems[t] >= np.median(dems[t]))).ravel())
+        start = int(cand[np.random.default_rng(1000 + t).integers(cand.size)])
+        masks.append(grow_region(-np.abs(sl - 37.5), int(sizes[t]), start))
+    masks = np.stack(masks)
+    ps = param_sets(n_params, 8)
+    params = [dict(DEFAULT_PARAMS, mu=float(m), xi=float(x), flow_height=float(h)) for m, x, h in ps]
+    runs = [(t, t, p, t * n_params + p, seed) for t in range(n_tiles) for p in range(n_params)]
+    return Ensemble(dems, masks, params, runs, cell_size, particles_per_cell, step_limit)

@@ -1,0 +1,180 @@
+"""GPU parity of the batched ensemble entry point (avl_trajectories_batched) and of the kernel variants.
+
+Every run of a batch is defined as the plain trajectory pass of its (tile, scenario, parameter set,
+seed, run id), so each run's rasters and statistics must equal the oracle's plain run bit for bit
+(max velocity within 1e-5 relative). Every autotuner variant must give identical results, and graph
+replays (with new parameter values written to device memory between replays) must match eager runs.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+INF = float("inf")
+
+
+@pytest.fixture(scope="module")
+def avl():
+    import paper_2506_23364_amd as m
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    yield m
+    m.set_tuning(-1, True)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def small_ensemble():
+    rng = np.random.default_rng(44)
+    dems = np.stack([synth.alpine_dem(128, 900.0, seed=60 + t)[:97, :83] for t in range(3)]).astype(np.float32)
+    masks = []
+    for t in range(3):
+        sl = synth.slope_deg(dems[t], 10.0)
+        m = ((sl >= 25) & (sl <= 50) & (dems[t] >= np.quantile(dems[t], 0.5))).astype(np.uint8)
+        keep = rng.random(m.shape) < [0.5, 0.2, 0.05][t]
+        masks.append((m & keep).astype(np.uint8))
+    masks.append(np.zeros_like(masks[0]))  # an empty scenario
+    masks = np.stack(masks)
+    params = [dict(synth.DEFAULT_PARAMS, mu=0.2, xi=2000.0),
+              dict(synth.DEFAULT_PARAMS, mu=0.12, xi=INF, randomness=0.3),
+              dict(synth.DEFAULT_PARAMS, mu=0.35, xi=600.0, flow_height=2.5, step_cells=0.7),
+              dict(synth.DEFAULT_PARAMS, mu=0.05, tan_alpha=0.45, persistence=0.6)]
+    runs = []
+    for t in range(3):
+        for s in range(4):
+            for p in range(4):
+                if (t + s + p) % 3 == 0:
+                    runs.append((t, s, p, 1000 + len(runs), 0x1234567890ABCDEF + t))
+    return dems, masks, params, runs
+
+
+def oracle_run(dems, masks, params, run, P, S):
+    t, s, p, run_id, seed = run
+    return oracle.trajectories(dems[t], masks[s], 10.0, oracle.make_params(**params[p]), P, S, seed, run_id)
+
+
+def check_batch(res, dems, masks, params, runs, P, S, label=""):
+    counts, vmax, stats, status = host(res.counts), host(res.vmax), host(res.stats), host(res.status)
+    for k, run in enumerate(runs):
+        ref = oracle_run(dems, masks, params, run, P, S)
+        assert status[k] == 0
+        assert np.array_equal(counts[k], ref.counts), f"{label} run {k}"
+        np.testing.assert_allclose(vmax[k], ref.vmax, rtol=1e-5, atol=0, err_msg=f"{label} run {k}")
+        assert list(stats[k]) == [ref.steps, ref.n_exit, ref.n_stop, ref.n_limit], f"{label} run {k}"
+
+
+def run_batch(avl, dems, masks, params, runs, P, S, out=None):
+    d = torch.from_numpy(dems).cuda()
+    m = torch.from_numpy(masks).cuda()
+    return avl.trajectories_batched(d, m, 10.0, avl.params_tensor(params, "cuda"), avl.runs_tensor(runs, "cuda"), P, S,
+                                    out)
+
+
+def test_batch_equals_plain_oracle_runs(avl):
+    dems, masks, params, runs = small_ensemble()
+    res = run_batch(avl, dems, masks, params, runs, 5, 300)
+    check_batch(res, dems, masks, params, runs, 5, 300, "eager default stream")
+
+
+def test_batch_bad_runs_are_flagged(avl):
+    dems, masks, params, runs = small_ensemble()
+    bad_params = params + [dict(synth.DEFAULT_PARAMS, mu=-1.0)]
+    runs2 = [runs[0], (7, 0, 0, 1, 1), (0, 9, 0, 1, 1), (0, 0, 11, 1, 1), (0, 0, 4, 1, 1), runs[1]]
+    res = run_batch(avl, dems, masks, bad_params, runs2, 3, 100)
+    status = host(res.status)
+    assert list(status) == [0, 1, 1, 1, 2, 0]
+    counts = host(res.counts)
+    assert counts[1:5].sum() == 0
+    for k in (0, 5):
+        ref = oracle_run(dems, masks, bad_params, runs2[k], 3, 100)
+        assert np.array_equal(counts[k], ref.counts)
+
+
+def test_every_variant_gives_identical_rasters(avl):
+    dems, masks, params, runs = small_ensemble()
+    w = synth.make_workload("tiny")
+    mask = oracle.release_mask(oracle.normals(w.dem, 10.0), w.dem, 30, 45, w.z_min, w.z_max)
+    dem_t, mask_t = torch.from_numpy(w.dem).cuda(), torch.from_numpy(mask).cuda()
+    ref_b = ref_p = None
+    try:
+        for v in range(avl.tuning_variants()):
+            avl.set_tuning(v, True)
+            res = run_batch(avl, dems, masks, params, runs, 4, 200)
+            got_b = [host(res.counts), host(res.vmax), host(res.stats)]
+            assert avl.last_variant() == v
+            r = avl.trajectories(dem_t, mask_t, 10.0, avl.Params.make(**w.params), 4, 500, 3)
+            got_p = [host(r.counts), host(r.vmax), host(r.stats)]
+            if ref_b is None:
+                ref_b, ref_p = got_b, got_p
+            for a, b in zip(got_b + got_p, ref_b + ref_p):
+                assert np.array_equal(a, b), f"variant {v}"
+    finally:
+        avl.set_tuning(-1, True)
+    ref = oracle.trajectories(w.dem, mask, 10.0, oracle.make_params(**w.params), 4, 500, 3)
+    assert np.array_equal(ref_p[0], ref.counts)
+
+
+def test_graph_replay_with_new_parameters(avl):
+    dems, masks, params, runs = small_ensemble()
+    d = torch.from_numpy(dems).cuda()
+    m = torch.from_numpy(masks).cuda()
+    ptab = avl.params_tensor(params, "cuda")
+    rtab = avl.runs_tensor(runs, "cuda")
+    stream = torch.cuda.Stream()
+    out = None
+    variants = [params,
+                [dict(p, mu=p["mu"] + 0.03) for p in params],
+                [dict(p, randomness=0.05) for p in params]]
+    with torch.cuda.stream(stream):
+        for rep in range(2):
+            for vi, pv in enumerate(variants):
+                ptab.copy_(avl.params_tensor(pv, "cuda"))
+                out = avl.trajectories_batched(d, m, 10.0, ptab, rtab, 4, 250, out)
+                stream.synchronize()
+                # unrelated eager work between replays
+                junk = torch.randn(1 << 20, device="cuda").sum()
+                check_batch(out, dems, masks, pv, runs, 4, 250, f"replay {rep} params {vi}")
+                del junk
+    # the same with graphs off
+    avl.set_tuning(-1, False)
+    try:
+        with torch.cuda.stream(stream):
+            res = avl.trajectories_batched(d, m, 10.0, avl.params_tensor(variants[1], "cuda"), rtab, 4, 250)
+            stream.synchronize()
+        check_batch(res, dems, masks, variants[1], runs, 4, 250, "graphs off")
+    finally:
+        avl.set_tuning(-1, True)
+
+
+def test_ensemble_full_size_sampled(avl):
+    """The full 16-tile x 64-parameter ensemble (1024 runs, 1024^2 tiles, 32 particles per cell, 2000 steps)
+    in the launch shape the benchmark times; the oracle checks the runs of the two smallest scenarios
+    under four parameter sets each, and the per-run statistics of all runs must add up to the batch's."""
+    e = synth.make_ensemble()
+    d = torch.from_numpy(e.dems).cuda()
+    m = torch.from_numpy(e.masks).cuda()
+    res = avl.trajectories_batched(d, m, e.cell_size, avl.params_tensor(e.params, "cuda"),
+                                   avl.runs_tensor(e.runs, "cuda"), e.particles_per_cell, e.step_limit)
+    stats = host(res.stats)
+    assert (host(res.status) == 0).all()
+    sizes = e.masks.sum(axis=(1, 2))
+    small = np.argsort(sizes)[:2]
+    for t in small:
+        for p in (0, 21, 42, 63):
+            k = int(t) * 64 + p
+            run = e.runs[k]
+            ref = oracle.trajectories(e.dems[run[0]], e.masks[run[1]], e.cell_size, oracle.make_params(**e.params[p]),
+                                      e.particles_per_cell, e.step_limit, run[4], run[3])
+            assert np.array_equal(host(res.counts[k]), ref.counts), k
+            np.testing.assert_allclose(host(res.vmax[k]), ref.vmax, rtol=1e-5, atol=0)
+            assert list(stats[k]) == [ref.steps, ref.n_exit, ref.n_stop, ref.n_limit]
+    # each run released exactly its scenario's particles
+    ends = stats[:, 1:].sum(axis=1)
+    expect = np.array([sizes[r[1]] * e.particles_per_cell for r in e.runs])
+    assert np.array_equal(ends, expect)
