@@ -159,3 +159,79 @@ def trace(dem: np.ndarray, cell_size: float, params: OracleParams, r: int, c: in
            ctypes.c_int(r), ctypes.c_int(c), ctypes.c_uint32(replica), ctypes.c_uint32(step_limit),
            ctypes.c_uint64(seed), ctypes.c_uint32(run), _ptr(buf), ctypes.byref(reason), ctypes.byref(steps))
     return Trace(buf[:n].copy(), int(reason.value), int(steps.value))
+
+
+@dataclass
+class SmoothResult:
+    dep_q: np.ndarray      # (H, W) int64 deposit in fixed point (units of 2^-24)
+    dep: np.ndarray        # (H, W) unquantised deposit in the working precision
+    vel_q: np.ndarray      # (H, W) int64 velocity splat (fixed point), zero unless requested
+    vel: np.ndarray
+    steps: int
+    n_exit: int
+    n_stop: int
+    n_limit: int
+
+
+def smooth_forward(dem, mask, cell_size, params: OracleParams, particles_per_cell, step_limit, seed, run=0,
+                   mass=None, vel_splat=False, prec="f32") -> SmoothResult:
+    dem = np.ascontiguousarray(dem, dtype=np.float32)
+    mask = np.ascontiguousarray(mask, dtype=np.uint8)
+    h, w = dem.shape
+    m = None if mass is None else np.ascontiguousarray(mass, dtype=np.float32)
+    dep_q = np.zeros((h, w), np.int64)
+    dep = np.zeros((h, w), _real(prec))
+    vel_q = np.zeros((h, w), np.int64)
+    vel = np.zeros((h, w), _real(prec))
+    stats = np.zeros(4, np.uint64)
+    getattr(_lib(prec), f"oracle_smooth_forward_{prec}")(
+        _ptr(dem), _ptr(mask), None if m is None else _ptr(m), ctypes.c_int(h), ctypes.c_int(w),
+        ctypes.c_float(cell_size), ctypes.byref(params), ctypes.c_uint32(particles_per_cell),
+        ctypes.c_uint32(step_limit), ctypes.c_uint64(seed), ctypes.c_uint32(run), ctypes.c_int(1 if vel_splat else 0),
+        _ptr(dep_q), _ptr(dep), _ptr(vel_q), _ptr(vel), _ptr(stats))
+    return SmoothResult(dep_q, dep, vel_q, vel, int(stats[0]), int(stats[1]), int(stats[2]), int(stats[3]))
+
+
+@dataclass
+class SmoothGrad:
+    dmu: float
+    dxi: float
+    dh: float
+    dmass: np.ndarray            # (H, W) float64
+    per_particle: np.ndarray     # (n_particles, 4): dmu, dxi, dh, sum gD w  (release order)
+
+
+def smooth_backward(dem, mask, cell_size, params: OracleParams, particles_per_cell, step_limit, seed, grad_dep,
+                    run=0, mass=None, prec="f32") -> SmoothGrad:
+    dem = np.ascontiguousarray(dem, dtype=np.float32)
+    mask = np.ascontiguousarray(mask, dtype=np.uint8)
+    g = np.ascontiguousarray(grad_dep, dtype=np.float32)
+    h, w = dem.shape
+    m = None if mass is None else np.ascontiguousarray(mass, dtype=np.float32)
+    gp = np.zeros(3, np.float64)
+    gm = np.zeros((h, w), np.float64)
+    pp = np.zeros((int(mask.astype(bool).sum()) * particles_per_cell, 4), _real(prec))
+    fn = getattr(_lib(prec), f"oracle_smooth_backward_{prec}")
+    rc = fn(_ptr(dem), _ptr(mask), None if m is None else _ptr(m), ctypes.c_int(h), ctypes.c_int(w),
+            ctypes.c_float(cell_size), ctypes.byref(params), ctypes.c_uint32(particles_per_cell),
+            ctypes.c_uint32(step_limit), ctypes.c_uint64(seed), ctypes.c_uint32(run), _ptr(g), _ptr(gp), _ptr(gm),
+            _ptr(pp) if pp.size else None)
+    assert rc == 0
+    return SmoothGrad(float(gp[0]), float(gp[1]), float(gp[2]), gm, pp)
+
+
+def smooth_tangent(dem, mask, cell_size, params: OracleParams, particles_per_cell, step_limit, seed, grad_dep,
+                   run=0, mass=None) -> tuple[float, float, float]:
+    """Forward-mode (mu, xi, h) gradient, binary64."""
+    dem = np.ascontiguousarray(dem, dtype=np.float32)
+    mask = np.ascontiguousarray(mask, dtype=np.uint8)
+    g = np.ascontiguousarray(grad_dep, dtype=np.float32)
+    h, w = dem.shape
+    m = None if mass is None else np.ascontiguousarray(mass, dtype=np.float32)
+    gp = np.zeros(3, np.float64)
+    rc = _lib("f64").oracle_smooth_tangent_f64(
+        _ptr(dem), _ptr(mask), None if m is None else _ptr(m), ctypes.c_int(h), ctypes.c_int(w),
+        ctypes.c_float(cell_size), ctypes.byref(params), ctypes.c_uint32(particles_per_cell),
+        ctypes.c_uint32(step_limit), ctypes.c_uint64(seed), ctypes.c_uint32(run), _ptr(g), _ptr(gp))
+    assert rc == 0
+    return float(gp[0]), float(gp[1]), float(gp[2])

@@ -22,6 +22,7 @@
 #include <math.h>
 #include <stddef.h>
 #include <stdint.h>
+#include <stdlib.h>
 #include <string.h>
 
 #ifdef AVL_F64
@@ -206,7 +207,17 @@ static void sample(const model* m, real x, real y, real* zz, real* gx, real* gy)
     *gy = bot - top;
 }
 
-enum { END_LIMIT = 0, END_EXIT = 1, END_STOP = 2 };
+enum { END_LIMIT = 0, END_EXIT = 1, END_STOP = 2, END_ANGLE = 3 };
+
+/* How a particle ended: the last position (x, y) with its v^2; for an energy stop, also the rejected
+ * step's target (x1, y1) and numerator num <= 0. */
+typedef struct {
+    int reason;
+    real x, y, v2;
+    real x1, y1, num;
+} end_info;
+
+static void splat(const model* m, int64_t* q, real* f, real x, real y, real val);
 
 #define TRACE_COLS 8 /* x, y, z, gx, gy, dx, dy, v2 */
 
@@ -215,7 +226,7 @@ enum { END_LIMIT = 0, END_EXIT = 1, END_STOP = 2 };
  * (S+1) rows, row 0 is the released state and row n+1 the state after step n. Returns the end reason;
  * *steps gets the number of steps entered (the terminating one included); *rows the trace rows. */
 static int particle(const model* m, int r, int c, uint32_t replica, uint32_t* counts, real* vmax2,
-                    uint64_t* steps, real* trace, int64_t* rows)
+                    uint64_t* steps, real* trace, int64_t* rows, end_info* ei, int64_t* vel_q, real* vel, real mp)
 {
     const int W = m->W, H = m->H;
     const uint32_t cell_id = (uint32_t)r * (uint32_t)W + (uint32_t)c;
@@ -263,17 +274,22 @@ static int particle(const model* m, int r, int c, uint32_t replica, uint32_t* co
         real y1 = y + m->L * dy;
         real fc = FLOOR(x1), fr = FLOOR(y1);
         if (!(fc >= 0 && fc < (real)W && fr >= 0 && fr < (real)H)) { reason = END_EXIT; break; }
+        real xs = x1, ys = y1; /* the rejected target, for an energy stop */
         real z1, gx1, gy1;
         sample(m, x1, y1, &z1, &gx1, &gy1);
         /* kinetic energy: gravity work minus Coulomb loss; Voellmy drag taken implicitly over the path */
         real dz = z - z1;
         real ds = SQRT(m->dl2 + dz * dz);
         real num = v2 + m->g2 * (dz - m->mdl);
-        if (!(num > 0)) { reason = END_STOP; break; }
+        if (!(num > 0)) {
+            reason = END_STOP;
+            if (ei) { ei->x1 = xs; ei->y1 = ys; ei->num = num; }
+            break;
+        }
         real v2n = num / (R(1) + m->cd * ds);
         if (m->use_alpha) {
             real hx = x1 - x0, hy = y1 - y0;
-            if ((zr - z1) < m->tca * SQRT(hx * hx + hy * hy)) { reason = END_STOP; break; }
+            if ((zr - z1) < m->tca * SQRT(hx * hx + hy * hy)) { reason = END_ANGLE; break; }
         }
         x = x1; y = y1; z = z1; gx = gx1; gy = gy1; v2 = v2n;
         int ri = (int)fr, ci = (int)fc;
@@ -282,6 +298,7 @@ static int particle(const model* m, int r, int c, uint32_t replica, uint32_t* co
             if (counts) counts[(size_t)cr * W + cc] += 1;
         }
         if (vmax2 && v2 > vmax2[(size_t)cr * W + cc]) vmax2[(size_t)cr * W + cc] = v2;
+        if (vel_q || vel) splat(m, vel_q, vel, x, y, mp * SQRT(v2));
         if (trace) {
             real* tr = trace + TRACE_COLS * nrow++;
             tr[0] = x; tr[1] = y; tr[2] = z; tr[3] = gx; tr[4] = gy; tr[5] = dx; tr[6] = dy; tr[7] = v2;
@@ -289,6 +306,7 @@ static int particle(const model* m, int r, int c, uint32_t replica, uint32_t* co
     }
     *steps += n_steps;
     if (rows) *rows = nrow;
+    if (ei) { ei->reason = reason; ei->x = x; ei->y = y; ei->v2 = v2; }
     return reason;
 }
 
@@ -309,8 +327,8 @@ int NAME(oracle_trajectories)(const float* dem, const uint8_t* mask, int H, int 
         for (int c = 0; c < W; ++c) {
             if (!mask[(size_t)r * W + c]) continue;
             for (uint32_t j = 0; j < particles_per_cell; ++j) {
-                int why = particle(&m, r, c, j, counts, vmax, &st[0], NULL, NULL);
-                st[why == END_EXIT ? 1 : (why == END_STOP ? 2 : 3)] += 1;
+                int why = particle(&m, r, c, j, counts, vmax, &st[0], NULL, NULL, NULL, NULL, NULL, 0);
+                st[why == END_EXIT ? 1 : (why == END_LIMIT ? 3 : 2)] += 1;
             }
         }
     for (size_t i = 0; i < N; ++i) vmax[i] = SQRT(vmax[i]);
@@ -328,7 +346,276 @@ int64_t NAME(oracle_trace)(const float* dem, int H, int W, float cell_size, cons
     model_init(&m, dem, H, W, cell_size, p, step_limit, seed, run);
     int64_t rows = 0;
     uint64_t st = 0;
-    *reason = particle(&m, r, c, replica, NULL, NULL, &st, trace, &rows);
+    *reason = particle(&m, r, c, replica, NULL, NULL, &st, trace, &rows, NULL, NULL, NULL, 0);
+    if (*reason == END_ANGLE) *reason = END_STOP;
     *steps = st;
     return rows;
 }
+
+/* ----------------------------------------------------------------------------------------------
+ * Smooth variant: deposit of the released mass where each particle comes to rest, and its gradient.
+ *
+ * Every particle of release cell c carries mp = mass[c] / P. It rests at p*:
+ *   - energy stop during step n: the numerator of the energy step falls linearly from v^2 > 0 at the
+ *     start of the step to num <= 0 at its end; its zero is at the fraction t* = v^2 / (v^2 - num) of
+ *     the step (t* = 0 when v^2 = 0), so p* = p + t* (p1 - p);
+ *   - runout-angle stop or step limit: p* = p;  leaving the grid: the mass is lost.
+ * The deposit is the bilinear splat of mp at p* (the same four texel centres and weights as the height
+ * sample; clamped corners merge), accumulated in fixed point q = rint(value * 2^24) as int64 so the raster
+ * does not depend on the order of accumulation; `dep` (nullable) gets the same sum unquantised. With
+ * vel_splat, every accepted step also splats mp * v at the particle's new position into vel_q / vel.
+ * ---------------------------------------------------------------------------------------------- */
+#ifdef AVL_F64
+#define RINT_Q(v) llrint((v) * 0x1p24)
+#else
+#define RINT_Q(v) llrintf((v) * 0x1p24f)
+#endif
+
+typedef struct {
+    int ca, cb, ra, rb;
+    real fx, fy;
+} corners;
+
+static corners corners_of(const model* m, real x, real y)
+{
+    corners k;
+    real sx = x - R(0.5), sy = y - R(0.5);
+    real fc = FLOOR(sx), fr = FLOOR(sy);
+    k.fx = sx - fc;
+    k.fy = sy - fr;
+    int c0 = (int)fc, r0 = (int)fr;
+    k.ca = clampi(c0, 0, m->W - 1);
+    k.cb = clampi(c0 + 1, 0, m->W - 1);
+    k.ra = clampi(r0, 0, m->H - 1);
+    k.rb = clampi(r0 + 1, 0, m->H - 1);
+    return k;
+}
+
+static void splat(const model* m, int64_t* q, real* f, real x, real y, real val)
+{
+    corners k = corners_of(m, x, y);
+    const real w[4] = {(R(1) - k.fx) * (R(1) - k.fy), k.fx * (R(1) - k.fy), (R(1) - k.fx) * k.fy, k.fx * k.fy};
+    const size_t idx[4] = {(size_t)k.ra * m->W + k.ca, (size_t)k.ra * m->W + k.cb, (size_t)k.rb * m->W + k.ca,
+                           (size_t)k.rb * m->W + k.cb};
+    for (int i = 0; i < 4; ++i) {
+        real v = val * w[i];
+        if (q) q[idx[i]] += (int64_t)RINT_Q(v);
+        if (f) f[idx[i]] += v;
+    }
+}
+
+/* resting point of a particle that ended with *e (energy stop: fractional step) */
+static void rest_point(const end_info* e, real* px, real* py, real* tstar)
+{
+    real t = 0;
+    if (e->reason == END_STOP && e->v2 > 0) t = e->v2 / (e->v2 - e->num);
+    *px = e->x + t * (e->x1 - e->x);
+    *py = e->y + t * (e->y1 - e->y);
+    *tstar = t;
+}
+
+static real mass_of(const float* mass, size_t cell) { return mass ? (real)mass[cell] : R(1); }
+
+int NAME(oracle_smooth_forward)(const float* dem, const uint8_t* mask, const float* mass, int H, int W,
+                                float cell_size, const oracle_params* p, uint32_t P, uint32_t step_limit,
+                                uint64_t seed, uint32_t run, int vel_splat, int64_t* dep_q, real* dep,
+                                int64_t* vel_q, real* vel, uint64_t* stats)
+{
+    model m;
+    model_init(&m, dem, H, W, cell_size, p, step_limit, seed, run);
+    const size_t N = (size_t)H * W;
+    memset(dep_q, 0, N * sizeof(int64_t));
+    if (dep) for (size_t i = 0; i < N; ++i) dep[i] = 0;
+    if (vel_q) memset(vel_q, 0, N * sizeof(int64_t));
+    if (vel) for (size_t i = 0; i < N; ++i) vel[i] = 0;
+    uint64_t st[4] = {0, 0, 0, 0};
+    for (int r = 0; r < H; ++r)
+        for (int c = 0; c < W; ++c) {
+            const size_t cell = (size_t)r * W + c;
+            if (!mask[cell]) continue;
+            const real mp = mass_of(mass, cell) / (real)P;
+            for (uint32_t j = 0; j < P; ++j) {
+                end_info e;
+                int why = particle(&m, r, c, j, NULL, NULL, &st[0], NULL, NULL, &e, vel_splat ? vel_q : NULL,
+                                   vel_splat ? vel : NULL, mp);
+                st[why == END_EXIT ? 1 : (why == END_LIMIT ? 3 : 2)] += 1;
+                if (why == END_EXIT) continue;
+                real px, py, t;
+                rest_point(&e, &px, &py, &t);
+                splat(&m, dep_q, dep, px, py, mp);
+            }
+        }
+    if (stats) memcpy(stats, st, sizeof st);
+    return 0;
+}
+
+/* ----------------------------------------------------------------------------------------------
+ * Gradient of a loss L(D) of the deposit, given gD = dL/dD per texel, with respect to mu, xi, h and
+ * the release mass of every cell.
+ *
+ * Paths do not depend on mu, xi, h or the mass (the direction never reads the speed), so for each
+ * particle only v^2 along its path and the fractional last step depend on (mu, xi, h):
+ *   dL/dp*  = mp * sum over the splat corners of gD * grad w;  dL/dt* = dL/dp* . (p1 - p);
+ *   t* = v2 / Dn with Dn = v2 - num = -2g (dz - mu dl), so dL/dv2_n = dL/dt* / Dn and the direct
+ *   term dL/dmu += -dL/dt* * v2 * (2g dl) / Dn^2;
+ *   reverse sweep of v2_{k+1} = (v2_k + 2g (dz_k - mu dl)) / (1 + a_k), a_k = 2g ds_k / (xi h):
+ *     dL/dmu += lam_{k+1} * (-(2g dl) / (1 + a_k)); dL/dxi += lam_{k+1} * v2_{k+1} a_k / (xi (1 + a_k));
+ *     dL/dh += lam_{k+1} * v2_{k+1} a_k / (h (1 + a_k)); lam_k = lam_{k+1} / (1 + a_k).
+ * The mass enters linearly: dL/dmass[c] = (1/P) sum over c's particles of sum gD * w(p*).
+ * A particle that stopped on the runout angle or the step limit rests at a point that does not move
+ * with (mu, xi, h); one that left the grid deposits nothing.
+ * Per-particle values (nullable, 4 reals per particle in release order: dmu, dxi, dh, sum gD w) are
+ * in the working precision; the totals are summed in binary64 in particle order.
+ * ---------------------------------------------------------------------------------------------- */
+typedef struct {
+    real gpx, gpy, gw; /* dL/dp* per unit mass (x, y) and sum gD * w at p* */
+} splat_grad;
+
+static splat_grad splat_gradient(const model* m, const float* gD, real px, real py)
+{
+    corners k = corners_of(m, px, py);
+    const real g00 = (real)gD[(size_t)k.ra * m->W + k.ca], g01 = (real)gD[(size_t)k.ra * m->W + k.cb];
+    const real g10 = (real)gD[(size_t)k.rb * m->W + k.ca], g11 = (real)gD[(size_t)k.rb * m->W + k.cb];
+    splat_grad s;
+    s.gpx = ((g01 - g00) * (R(1) - k.fy)) + ((g11 - g10) * k.fy);
+    s.gpy = ((g10 - g00) * (R(1) - k.fx)) + ((g11 - g01) * k.fx);
+    const real w00 = (R(1) - k.fx) * (R(1) - k.fy), w01 = k.fx * (R(1) - k.fy);
+    const real w10 = (R(1) - k.fx) * k.fy, w11 = k.fx * k.fy;
+    s.gw = ((g00 * w00) + (g01 * w01)) + ((g10 * w10) + (g11 * w11));
+    return s;
+}
+
+int NAME(oracle_smooth_backward)(const float* dem, const uint8_t* mask, const float* mass, int H, int W,
+                                 float cell_size, const oracle_params* p, uint32_t P, uint32_t step_limit,
+                                 uint64_t seed, uint32_t run, const float* gD, double* gparams, double* gmass,
+                                 real* per_particle)
+{
+    model m;
+    model_init(&m, dem, H, W, cell_size, p, step_limit, seed, run);
+    const size_t N = (size_t)H * W;
+    real* trace = (real*)malloc(sizeof(real) * TRACE_COLS * ((size_t)step_limit + 1));
+    if (!trace) return -1;
+    const real g2dl = m.g2 * (m.L * m.cs);
+    const real xi = (real)p->xi, h = (real)p->flow_height;
+    double gmu = 0, gxi = 0, gh = 0;
+    for (size_t i = 0; i < N; ++i) gmass[i] = 0;
+    size_t k_out = 0;
+    for (int r = 0; r < H; ++r)
+        for (int c = 0; c < W; ++c) {
+            const size_t cell = (size_t)r * W + c;
+            if (!mask[cell]) continue;
+            const real mp = mass_of(mass, cell) / (real)P;
+            double gm_sum = 0;
+            for (uint32_t j = 0; j < P; ++j) {
+                end_info e;
+                uint64_t st = 0;
+                int64_t rows = 0;
+                int why = particle(&m, r, c, j, NULL, NULL, &st, trace, &rows, &e, NULL, NULL, 0);
+                real dmu = 0, dxi = 0, dh = 0, gw = 0;
+                if (why != END_EXIT) {
+                    real px, py, t;
+                    rest_point(&e, &px, &py, &t);
+                    splat_grad sg = splat_gradient(&m, gD, px, py);
+                    gw = sg.gw;
+                    if (why == END_STOP) {
+                        const real gt = mp * ((sg.gpx * (e.x1 - e.x)) + (sg.gpy * (e.y1 - e.y)));
+                        const real Dn = e.v2 - e.num;
+                        real lam = 0;
+                        if (Dn > 0) {
+                            lam = gt / Dn;
+                            dmu = -((gt * (e.v2 / Dn)) * (g2dl / Dn));
+                        }
+                        /* reverse sweep over the accepted steps k = rows-2 .. 0 */
+                        for (int64_t k = rows - 2; k >= 0; --k) {
+                            const real* a0 = trace + TRACE_COLS * k;
+                            const real* a1 = trace + TRACE_COLS * (k + 1);
+                            const real dz = a0[2] - a1[2];
+                            const real ds = SQRT(m.dl2 + dz * dz);
+                            const real a = m.cd * ds;
+                            const real op = R(1) + a;
+                            const real v2n = a1[7];
+                            dmu = dmu - lam * (g2dl / op);
+                            dxi = dxi + lam * ((v2n * a) / (xi * op));
+                            dh = dh + lam * ((v2n * a) / (h * op));
+                            lam = lam / op;
+                        }
+                    }
+                }
+                gmu += (double)dmu;
+                gxi += (double)dxi;
+                gh += (double)dh;
+                gm_sum += (double)gw;
+                if (per_particle) {
+                    real* o = per_particle + 4 * k_out;
+                    o[0] = dmu; o[1] = dxi; o[2] = dh; o[3] = gw;
+                }
+                ++k_out;
+            }
+            gmass[cell] = gm_sum / (double)P;
+        }
+    free(trace);
+    gparams[0] = gmu;
+    gparams[1] = gxi;
+    gparams[2] = gh;
+    return 0;
+}
+
+/* Forward-mode derivation of the same (mu, xi, h) gradient, independent of the reverse sweep: the
+ * tangents dv2/dmu, dv2/dxi, dv2/dh are carried forward along each path,
+ *   dv2_{k+1}/dmu = (dv2_k/dmu - 2g dl) / (1 + a_k),
+ *   dv2_{k+1}/dxi = dv2_k/dxi / (1 + a_k) + v2_{k+1} a_k / (xi (1 + a_k))  (h likewise),
+ * and at an energy stop d(t*)/d(theta) = (dv2_n/d(theta)) / Dn (+ the direct -v2 (2g dl) / Dn^2 for mu);
+ * dL/d(theta) = sum over particles of dL/d(t*) times d(t*)/d(theta). Binary64 only. */
+#ifdef AVL_F64
+int oracle_smooth_tangent_f64(const float* dem, const uint8_t* mask, const float* mass, int H, int W,
+                              float cell_size, const oracle_params* p, uint32_t P, uint32_t step_limit,
+                              uint64_t seed, uint32_t run, const float* gD, double* gparams)
+{
+    model m;
+    model_init(&m, dem, H, W, cell_size, p, step_limit, seed, run);
+    real* trace = (real*)malloc(sizeof(real) * TRACE_COLS * ((size_t)step_limit + 1));
+    if (!trace) return -1;
+    const real g2dl = m.g2 * (m.L * m.cs);
+    const real xi = (real)p->xi, h = (real)p->flow_height;
+    double out[3] = {0, 0, 0};
+    for (int r = 0; r < H; ++r)
+        for (int c = 0; c < W; ++c) {
+            const size_t cell = (size_t)r * W + c;
+            if (!mask[cell]) continue;
+            const real mp = mass_of(mass, cell) / (real)P;
+            for (uint32_t j = 0; j < P; ++j) {
+                end_info e;
+                uint64_t st = 0;
+                int64_t rows = 0;
+                int why = particle(&m, r, c, j, NULL, NULL, &st, trace, &rows, &e, NULL, NULL, 0);
+                if (why != END_STOP) continue;
+                double tmu = 0, txi = 0, th = 0; /* tangents of v2 */
+                for (int64_t k = 0; k + 1 < rows; ++k) {
+                    const real* a0 = trace + TRACE_COLS * k;
+                    const real* a1 = trace + TRACE_COLS * (k + 1);
+                    const double dz = a0[2] - a1[2];
+                    const double ds = sqrt(m.dl2 + dz * dz);
+                    const double a = m.cd * ds;
+                    const double v2n = a1[7];
+                    tmu = (tmu - g2dl) / (1 + a);
+                    txi = txi / (1 + a) + v2n * a / (xi * (1 + a));
+                    th = th / (1 + a) + v2n * a / (h * (1 + a));
+                }
+                const double Dn = e.v2 - e.num;
+                if (!(Dn > 0)) continue;
+                real px, py, t;
+                rest_point(&e, &px, &py, &t);
+                splat_grad sg = splat_gradient(&m, gD, px, py);
+                const double gt = mp * (sg.gpx * (e.x1 - e.x) + sg.gpy * (e.y1 - e.y));
+                out[0] += gt * (tmu / Dn - e.v2 * g2dl / (Dn * Dn));
+                out[1] += gt * (txi / Dn);
+                out[2] += gt * (th / Dn);
+            }
+        }
+    free(trace);
+    gparams[0] = out[0];
+    gparams[1] = out[1];
+    gparams[2] = out[2];
+    return 0;
+}
+#endif
