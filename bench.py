@@ -46,6 +46,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-stride", type=int, default=0, help="oracle sample: every n-th release cell (0 = auto)")
     ap.add_argument("--no-batched", action="store_true", help="skip the ensemble (batched vs plain) leg")
+    ap.add_argument("--no-gradient", action="store_true", help="skip the calibration-gradient leg")
     return ap.parse_args()
 
 
@@ -117,6 +118,53 @@ def batched_leg(avl, torch, reps: int) -> dict:
             "speedup_batched_vs_plain": t_plain / t_batch,
             "particle_steps_per_s_batched": steps / t_batch, "particle_steps_per_s_plain": steps / t_plain,
             "variant": variant, "batched_equals_plain": same}
+
+
+def gradient_leg(avl, torch, reps: int) -> dict:
+    """Calibration gradient: 1024^2 ridged fBm at 10 m, 5000 release cells x 128 particles, 3000 steps,
+    checkpoints every 64 steps; L = MSE(deposit(mu0, xi0), deposit(mu*, xi*)). Timed: smooth forward +
+    adjoint (s per gradient) against the plain forward of the same release on the same DEM."""
+    import synth
+    c = synth.make_calibration()
+    dem = torch.from_numpy(c.dem).cuda()
+    mask = torch.from_numpy(c.mask).cuda()
+    mass = torch.from_numpy(c.mass).cuda()
+    P, S, seed = c.particles_per_cell, c.step_limit, c.seed
+    n_cells = int(c.mask.sum())
+    p_star = avl.Params.make(mu=c.mu_star, xi=c.xi_star, flow_height=c.flow_height)
+    p0 = avl.Params.make(mu=c.mu0, xi=c.xi0, flow_height=c.flow_height)
+    target = avl.trajectories_smooth(dem, mask, c.cell_size, p_star, P, S, seed, mass=mass,
+                                     max_release_cells=n_cells).deposit
+
+    def grad_once():
+        run = avl.trajectories_smooth(dem, mask, c.cell_size, p0, P, S, seed, mass=mass, max_release_cells=n_cells)
+        gD = (2.0 / run.deposit.numel()) * (run.deposit - target)
+        dparams, dmass, _ = avl.trajectories_backward(run, dem, mask, c.cell_size, p0, P, S, seed, gD, mass=mass)
+        return run, dparams, dmass
+
+    run, dparams, _ = grad_once()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        run, dparams, _ = grad_once()
+    torch.cuda.synchronize()
+    t_grad = (time.perf_counter() - t0) / reps
+    res = None
+    for _ in range(2):
+        res = avl.trajectories(dem, mask, c.cell_size, p0, P, S, seed, 0, res)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        res = avl.trajectories(dem, mask, c.cell_size, p0, P, S, seed, 0, res)
+    torch.cuda.synchronize()
+    t_plain = (time.perf_counter() - t0) / reps
+    g = dparams.cpu().numpy()
+    steps = int(run.stats.cpu().numpy()[0])
+    return {"workload": "calibration: 1024^2 at 10 m, 5000 release cells x 128 particles, 3000 steps, "
+                        "checkpoints every 64 steps, MSE of the deposit against (mu*, xi*) = (0.22, 1800)",
+            "at": {"mu": c.mu0, "xi": c.xi0}, "dL_dmu": float(g[0]), "dL_dxi": float(g[1]), "dL_dh": float(g[2]),
+            "particle_steps": steps, "s_per_gradient": t_grad, "ms_plain_forward": t_plain * 1e3,
+            "gradient_over_plain_forward": t_grad / t_plain}
 
 
 def main() -> int:
@@ -232,6 +280,8 @@ def main() -> int:
     }
     if not args.no_batched:
         out["batched"] = batched_leg(avl, torch, 3)
+    if not args.no_gradient:
+        out["gradient"] = gradient_leg(avl, torch, 5)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, mask_np, args.cpu_stride)
     print(json.dumps(out), flush=True)

@@ -137,6 +137,44 @@ AVL_API int avl_trajectories_batched(const float* dems, int32_t n_tiles, const u
                                      uint64_t* stats, int32_t* run_status, void* workspace, size_t workspace_bytes,
                                      void* stream);
 
+/* ---- Smooth variant and its adjoint (a differentiable runout field for calibrating mu, xi, h and the
+ * release mass against a target deposit).
+ * Every particle of release cell c carries mass[c] / particles_per_cell (mass NULL: 1 per cell). Paths
+ * are those of avl_trajectories. A particle stopped by the energy step rests at the zero of that step's
+ * energy numerator, the fraction t* = v^2 / (v^2 - num) of the step (0 when v^2 = 0); one stopped by the
+ * runout angle or the step limit rests where it is; one that leaves the grid loses its mass. Its mass
+ * is splatted bilinearly at the resting point (the height patch's four texel centres and weights,
+ * clamped corners merging) into deposit_q, an H*W int64 raster in units of 2^-24 (order independent, so
+ * bit-reproducible); deposit (nullable) gets it as float. With AVL_SMOOTH_VELOCITY every accepted step
+ * also splats (mass per particle) * v at the new position into velocity_q / velocity.
+ * max_release_cells: an upper bound on the number of release cells (it sizes the checkpoints); a mask with
+ * more release cells releases nothing and sets *status = 3 (status: device int32, nullable).
+ * stats as in avl_trajectories. workspace: avl_smooth_workspace_bytes(...) bytes; it keeps the
+ * per-particle checkpoints (every 64 steps) that avl_trajectories_backward reads. */
+#define AVL_SMOOTH_VELOCITY 1u
+AVL_API size_t avl_smooth_workspace_bytes(int32_t H, int32_t W, int32_t max_release_cells,
+                                          uint32_t particles_per_cell, uint32_t step_limit);
+AVL_API int avl_trajectories_smooth(const float* dem, const uint8_t* mask, const float* mass, int32_t H, int32_t W,
+                                    float cell_size, const avl_params* params, uint32_t particles_per_cell,
+                                    uint32_t step_limit, uint64_t seed, uint32_t run_id, int32_t max_release_cells,
+                                    uint32_t flags, int64_t* deposit_q, float* deposit, int64_t* velocity_q,
+                                    float* velocity, uint64_t* stats, int32_t* status, void* workspace,
+                                    size_t workspace_bytes, void* stream);
+
+/* Adjoint of the deposit of the preceding avl_trajectories_smooth call that used the same arguments and
+ * workspace: given grad_deposit = dL/dD (H*W float), writes dparams = {dL/dmu, dL/dxi, dL/dh} (3 device
+ * doubles) and dmass = dL/dmass (H*W float, 0 off the release cells). For each particle it recomputes the
+ * last path segment from its checkpoint, takes dL/d(resting point) through the splat weights and the
+ * fractional last step, then sweeps the v^2 recursion backward segment by segment, each segment
+ * recomputed from its checkpoint. Sums run in binary64 in a fixed order (deterministic). per_particle
+ * (nullable): 4 * max_release_cells * particles_per_cell floats, the per-particle dL/dmu, dL/dxi, dL/dh
+ * and sum of gD * w, each block in release order. The velocity raster is not differentiated. */
+AVL_API int avl_trajectories_backward(const float* dem, const uint8_t* mask, const float* mass, int32_t H, int32_t W,
+                                      float cell_size, const avl_params* params, uint32_t particles_per_cell,
+                                      uint32_t step_limit, uint64_t seed, uint32_t run_id, int32_t max_release_cells,
+                                      const float* grad_deposit, double* dparams, float* dmass, float* per_particle,
+                                      void* workspace, size_t workspace_bytes, void* stream);
+
 /* Tuning controls. variant: -1 = autotune (default: the first call per device and problem-size bucket
  * times every kernel variant and keeps the fastest; all variants give identical results), or a fixed
  * variant index in [0, avl_tuning_variants()). graphs: 1 = capture batched calls into HIP graphs

@@ -235,3 +235,24 @@ def smooth_tangent(dem, mask, cell_size, params: OracleParams, particles_per_cel
         ctypes.c_uint32(step_limit), ctypes.c_uint64(seed), ctypes.c_uint32(run), _ptr(g), _ptr(gp))
     assert rc == 0
     return float(gp[0]), float(gp[1]), float(gp[2])
+
+
+def smooth_particles(dem, mask, cell_size, params: OracleParams, particles_per_cell, step_limit, seed, grad_dep,
+                     run=0, mass=None, prec="f64"):
+    """Per particle (release order): share of L = sum gD * D, end reason, steps completed."""
+    dem = np.ascontiguousarray(dem, dtype=np.float32)
+    mask = np.ascontiguousarray(mask, dtype=np.uint8)
+    g = np.ascontiguousarray(grad_dep, dtype=np.float32)
+    h, w = dem.shape
+    m = None if mass is None else np.ascontiguousarray(mass, dtype=np.float32)
+    n = int(mask.astype(bool).sum()) * particles_per_cell
+    Lp = np.zeros(n, np.float64)
+    reason = np.zeros(n, np.int32)
+    steps = np.zeros(n, np.int32)
+    rc = getattr(_lib(prec), f"oracle_smooth_particles_{prec}")(
+        _ptr(dem), _ptr(mask), None if m is None else _ptr(m), ctypes.c_int(h), ctypes.c_int(w),
+        ctypes.c_float(cell_size), ctypes.byref(params), ctypes.c_uint32(particles_per_cell),
+        ctypes.c_uint32(step_limit), ctypes.c_uint64(seed), ctypes.c_uint32(run), _ptr(g), _ptr(Lp), _ptr(reason),
+        _ptr(steps))
+    assert rc == 0
+    return Lp, reason, steps

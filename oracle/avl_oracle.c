@@ -619,3 +619,40 @@ int oracle_smooth_tangent_f64(const float* dem, const uint8_t* mask, const float
     return 0;
 }
 #endif
+
+/* Per-particle view of the smooth deposit, for finite-difference checks of the gradient: for every
+ * particle (release order), its share of L = sum gD * D (mp * sum over the splat corners of gD * w at the
+ * resting point), its end reason and the number of steps it completed. */
+int NAME(oracle_smooth_particles)(const float* dem, const uint8_t* mask, const float* mass, int H, int W,
+                                  float cell_size, const oracle_params* p, uint32_t P, uint32_t step_limit,
+                                  uint64_t seed, uint32_t run, const float* gD, double* Lp, int32_t* reason,
+                                  int32_t* steps_done)
+{
+    model m;
+    model_init(&m, dem, H, W, cell_size, p, step_limit, seed, run);
+    real* trace = (real*)malloc(sizeof(real) * TRACE_COLS * ((size_t)step_limit + 1));
+    if (!trace) return -1;
+    size_t k = 0;
+    for (int r = 0; r < H; ++r)
+        for (int c = 0; c < W; ++c) {
+            const size_t cell = (size_t)r * W + c;
+            if (!mask[cell]) continue;
+            const real mp = mass_of(mass, cell) / (real)P;
+            for (uint32_t j = 0; j < P; ++j, ++k) {
+                end_info e;
+                uint64_t st = 0;
+                int64_t rows = 0;
+                int why = particle(&m, r, c, j, NULL, NULL, &st, trace, &rows, &e, NULL, NULL, 0);
+                reason[k] = why;
+                steps_done[k] = (int32_t)(rows - 1);
+                Lp[k] = 0;
+                if (why == END_EXIT) continue;
+                real px, py, t;
+                rest_point(&e, &px, &py, &t);
+                splat_grad sg = splat_gradient(&m, gD, px, py);
+                Lp[k] = (double)mp * (double)sg.gw;
+            }
+        }
+    free(trace);
+    return 0;
+}

@@ -17,7 +17,8 @@ from dataclasses import dataclass
 import torch
 
 __all__ = ["AvlError", "Params", "Run", "normals", "release_mask", "release_cells", "trajectories",
-           "trajectories_batched", "overlay", "workspace_bytes", "batched_workspace_bytes", "set_tuning",
+           "trajectories_batched", "trajectories_smooth", "trajectories_backward", "smooth_deposit", "SmoothDeposit",
+           "overlay", "workspace_bytes", "batched_workspace_bytes", "smooth_workspace_bytes", "set_tuning",
            "tuning_variants", "last_variant", "LIB_PATH", "lib"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libavl.so")
@@ -69,6 +70,14 @@ def _load() -> ctypes.CDLL:
     L.avl_trajectories_batched.argtypes = [vp, i32, vp, i32, i32, i32, f32, vp, i32, vp, i32, u32, u32, vp, vp, vp,
                                            vp, vp, sz, vp]
     L.avl_trajectories_batched.restype = ctypes.c_int
+    L.avl_smooth_workspace_bytes.argtypes = [i32, i32, i32, u32, u32]
+    L.avl_smooth_workspace_bytes.restype = sz
+    L.avl_trajectories_smooth.argtypes = [vp, vp, vp, i32, i32, f32, ctypes.POINTER(Params), u32, u32, u64, u32, i32,
+                                          u32, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    L.avl_trajectories_smooth.restype = ctypes.c_int
+    L.avl_trajectories_backward.argtypes = [vp, vp, vp, i32, i32, f32, ctypes.POINTER(Params), u32, u32, u64, u32,
+                                            i32, vp, vp, vp, vp, vp, sz, vp]
+    L.avl_trajectories_backward.restype = ctypes.c_int
     L.avl_set_tuning.argtypes = [i32, i32]
     L.avl_set_tuning.restype = ctypes.c_int
     L.avl_tuning_variants.argtypes = []
@@ -264,6 +273,110 @@ def trajectories_batched(dems: torch.Tensor, masks: torch.Tensor, cell_size: flo
                                             out.stats.data_ptr(), out.status.data_ptr(), ws.data_ptr(), ws.numel(),
                                             _stream(dems.device)), "avl_trajectories_batched")
     return out
+
+
+def smooth_workspace_bytes(h: int, w: int, max_release_cells: int, particles_per_cell: int, step_limit: int) -> int:
+    return int(lib.avl_smooth_workspace_bytes(h, w, max_release_cells, particles_per_cell, step_limit))
+
+
+@dataclass
+class SmoothRun:
+    """Result of the smooth forward; `workspace` holds the checkpoints the adjoint needs."""
+    deposit_q: torch.Tensor   # (H, W) int64, units of 2^-24
+    deposit: torch.Tensor     # (H, W) float32
+    velocity_q: torch.Tensor | None
+    velocity: torch.Tensor | None
+    stats: torch.Tensor       # (4,) uint64
+    status: torch.Tensor      # (1,) int32: 0 ok, 3 more release cells than max_release_cells
+    workspace: torch.Tensor
+    max_release_cells: int
+
+
+def trajectories_smooth(dem: torch.Tensor, mask: torch.Tensor, cell_size: float, params: Params,
+                        particles_per_cell: int, step_limit: int, seed: int, run_id: int = 0,
+                        mass: torch.Tensor | None = None, velocity: bool = False,
+                        max_release_cells: int | None = None) -> SmoothRun:
+    """Smooth forward: deposit of the released mass at each particle's resting point (own workspace)."""
+    _need(dem, "dem", torch.float32, 2)
+    _need(mask, "mask", torch.uint8, 2)
+    h, w = dem.shape
+    if mass is not None:
+        _need(mass, "mass", torch.float32, 2)
+    if max_release_cells is None:
+        max_release_cells = int(mask.count_nonzero().item())
+    dev = dem.device
+    ws = torch.empty(max(256, smooth_workspace_bytes(h, w, max_release_cells, particles_per_cell, step_limit)),
+                     dtype=torch.uint8, device=dev)
+    dq = torch.empty((h, w), dtype=torch.int64, device=dev)
+    df = torch.empty((h, w), dtype=torch.float32, device=dev)
+    vq = torch.empty((h, w), dtype=torch.int64, device=dev) if velocity else None
+    vf = torch.empty((h, w), dtype=torch.float32, device=dev) if velocity else None
+    stats = torch.empty(4, dtype=torch.uint64, device=dev)
+    status = torch.empty(1, dtype=torch.int32, device=dev)
+    with torch.cuda.device(dev):
+        _check(lib.avl_trajectories_smooth(dem.data_ptr(), mask.data_ptr(), mass.data_ptr() if mass is not None else None,
+                                           h, w, cell_size, ctypes.byref(params), particles_per_cell, step_limit,
+                                           seed & (2**64 - 1), run_id, max_release_cells, 1 if velocity else 0,
+                                           dq.data_ptr(), df.data_ptr(), vq.data_ptr() if velocity else None,
+                                           vf.data_ptr() if velocity else None, stats.data_ptr(), status.data_ptr(),
+                                           ws.data_ptr(), ws.numel(), _stream(dev)), "avl_trajectories_smooth")
+    return SmoothRun(dq, df, vq, vf, stats, status, ws, max_release_cells)
+
+
+def trajectories_backward(run: SmoothRun, dem: torch.Tensor, mask: torch.Tensor, cell_size: float, params: Params,
+                          particles_per_cell: int, step_limit: int, seed: int, grad_deposit: torch.Tensor,
+                          run_id: int = 0, mass: torch.Tensor | None = None, per_particle: bool = False):
+    """Adjoint of `run`'s deposit: (dparams float64 [dmu, dxi, dh], dmass (H, W), per-particle or None)."""
+    _need(grad_deposit, "grad_deposit", torch.float32, 2)
+    h, w = dem.shape
+    dev = dem.device
+    dparams = torch.empty(3, dtype=torch.float64, device=dev)
+    dmass = torch.empty((h, w), dtype=torch.float32, device=dev)
+    pp = (torch.empty((4, run.max_release_cells * particles_per_cell), dtype=torch.float32, device=dev)
+          if per_particle else None)
+    with torch.cuda.device(dev):
+        _check(lib.avl_trajectories_backward(dem.data_ptr(), mask.data_ptr(),
+                                             mass.data_ptr() if mass is not None else None, h, w, cell_size,
+                                             ctypes.byref(params), particles_per_cell, step_limit, seed & (2**64 - 1),
+                                             run_id, run.max_release_cells, grad_deposit.data_ptr(), dparams.data_ptr(),
+                                             dmass.data_ptr(), pp.data_ptr() if pp is not None else None,
+                                             run.workspace.data_ptr(), run.workspace.numel(), _stream(dev)),
+               "avl_trajectories_backward")
+    return dparams, dmass, pp
+
+
+class SmoothDeposit(torch.autograd.Function):
+    """deposit = f(mu, xi, h, mass): forward = smooth pass, backward = the adjoint kernel."""
+
+    @staticmethod
+    def forward(ctx, mu, xi, h, mass, dem, mask, cell_size, base, particles_per_cell, step_limit, seed, run_id,
+                max_release_cells):
+        params = Params.make(**dict(base, mu=float(mu), xi=float(xi), flow_height=float(h)))
+        run = trajectories_smooth(dem, mask, cell_size, params, particles_per_cell, step_limit, seed, run_id,
+                                  mass=mass.detach().contiguous(), max_release_cells=max_release_cells)
+        ctx.run, ctx.params = run, params
+        ctx.args = (dem, mask, cell_size, particles_per_cell, step_limit, seed, run_id)
+        ctx.save_for_backward(mass)
+        return run.deposit
+
+    @staticmethod
+    def backward(ctx, grad_dep):
+        (mass,) = ctx.saved_tensors
+        dem, mask, cell_size, P, S, seed, run_id = ctx.args
+        dparams, dmass, _ = trajectories_backward(ctx.run, dem, mask, cell_size, ctx.params, P, S, seed,
+                                                  grad_dep.contiguous().float(), run_id, mass.detach().contiguous())
+        dp = dparams.float()
+        return (dp[0], dp[1], dp[2], dmass, None, None, None, None, None, None, None, None, None)
+
+
+def smooth_deposit(mu: torch.Tensor, xi: torch.Tensor, h: torch.Tensor, mass: torch.Tensor, dem: torch.Tensor,
+                   mask: torch.Tensor, cell_size: float, particles_per_cell: int, step_limit: int, seed: int,
+                   run_id: int = 0, persistence: float = 0.9, randomness: float = 0.16, step_cells: float = 1.0,
+                   max_release_cells: int | None = None) -> torch.Tensor:
+    """Differentiable deposit raster (float32 (H, W)) with gradients to mu, xi, h (0-d tensors) and mass."""
+    base = dict(persistence=persistence, randomness=randomness, step_cells=step_cells, tan_alpha=-1.0)
+    return SmoothDeposit.apply(mu, xi, h, mass, dem, mask, cell_size, base, particles_per_cell, step_limit, seed,
+                               run_id, max_release_cells)
 
 
 def overlay(dem: torch.Tensor, cell_size: float, slope_min_deg: float, slope_max_deg: float, z_min: float,

@@ -63,6 +63,53 @@ Workspace carve_batched(void* base, int64_t n, int64_t n_masks, int64_t n_runs) 
     return w;
 }
 
+// Smooth pass workspace: the single-run control block, scan sums and cell list, then the end records,
+// checkpoints, per-particle adjoint results, reduction partials and the adjoint's scratch.
+struct SmoothWs {
+    Workspace w;
+    uint32_t* end_rec;
+    float* ck;
+    float* pp;
+    double* part;
+    float2* scratch;
+};
+
+static size_t smooth_layout(int64_t n, int64_t cap_cells, uint32_t P, uint32_t S, char* base, SmoothWs* out) {
+    const unsigned long long cap = (unsigned long long)cap_cells * P;
+    const size_t C = smooth_checkpoints(S);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off += round256(bytes);
+        return at;
+    };
+    const size_t o_ctrl = take(kControl);
+    const size_t o_blk = take((size_t)scan_blocks(n) * sizeof(uint32_t));
+    const size_t o_cells = take((size_t)n * sizeof(int32_t));
+    const size_t o_end = take((size_t)cap * sizeof(uint32_t));
+    const size_t o_ck = take(5 * C * (size_t)cap * sizeof(float));
+    const size_t o_pp = take(4 * (size_t)cap * sizeof(float));
+    const size_t o_part = take(3 * smooth_reduce_blocks(cap) * sizeof(double));
+    const size_t o_scr = take(smooth_scratch_bytes());
+    if (base && out) {
+        char* p = base + o_ctrl;
+        out->w = Workspace{};
+        out->w.n_cells = reinterpret_cast<int32_t*>(p);
+        out->w.stats = reinterpret_cast<unsigned long long*>(p + 64);
+        out->w.queues = reinterpret_cast<unsigned long long*>(p + 128);
+        out->w.run_off = reinterpret_cast<unsigned long long*>(p + 192);
+        out->w.runs = reinterpret_cast<RunConst*>(p + 256);
+        out->w.blk = reinterpret_cast<uint32_t*>(base + o_blk);
+        out->w.cells = reinterpret_cast<int32_t*>(base + o_cells);
+        out->end_rec = reinterpret_cast<uint32_t*>(base + o_end);
+        out->ck = reinterpret_cast<float*>(base + o_ck);
+        out->pp = reinterpret_cast<float*>(base + o_pp);
+        out->part = reinterpret_cast<double*>(base + o_part);
+        out->scratch = reinterpret_cast<float2*>(base + o_scr);
+    }
+    return off;
+}
+
 }  // namespace avl
 
 namespace {
@@ -327,6 +374,139 @@ int avl_trajectories(const float* dem, const uint8_t* mask, int32_t H, int32_t W
         return hip_fail(e, "avl_trajectories: launch");
     if ((e = avl::launch_merge_rasters(ws.priv_counts, ws.priv_vmax2, n, counts, vmax, s)) != hipSuccess)
         return hip_fail(e, "avl_trajectories: merge");
+    return AVL_OK;
+}
+
+size_t avl_smooth_workspace_bytes(int32_t H, int32_t W, int32_t max_release_cells, uint32_t particles_per_cell,
+                                  uint32_t step_limit) {
+    if (H < 1 || W < 1 || max_release_cells < 0 || particles_per_cell == 0) return 0;
+    return avl::smooth_layout((int64_t)H * W, max_release_cells, particles_per_cell, step_limit, nullptr, nullptr);
+}
+
+namespace {
+
+// shared argument checks of the smooth forward and the adjoint
+int smooth_checks(const char* where, const float* dem, const uint8_t* mask, int32_t H, int32_t W, float cell_size,
+                  const avl_params* params, uint32_t P, uint32_t S, int32_t max_release_cells, void* workspace,
+                  size_t workspace_bytes) {
+    if (!dem || !mask || !workspace) return fail(AVL_EINVAL, "%s: null pointer", where);
+    if (!grid_ok(H, W, 1)) return fail(AVL_EINVAL, "%s: need H, W >= 1 and H*W < 2^31", where);
+    if (!finite(cell_size) || !(cell_size > 0.0f)) return fail(AVL_EINVAL, "%s: cell_size must be > 0", where);
+    if (P == 0) return fail(AVL_EINVAL, "%s: particles_per_cell must be >= 1", where);
+    if (max_release_cells < 0 || (int64_t)max_release_cells > (int64_t)H * W)
+        return fail(AVL_EINVAL, "%s: need 0 <= max_release_cells <= H*W", where);
+    if ((uint64_t)max_release_cells * P >= (1ull << 32))
+        return fail(AVL_EINVAL, "%s: max_release_cells * particles_per_cell must be < 2^32", where);
+    if (S >= (1u << 30)) return fail(AVL_EINVAL, "%s: step_limit must be < 2^30", where);
+    if (const char* why = check_params(params)) return fail(AVL_EINVAL, "smooth pass: %s", why);
+    if (workspace_bytes < avl_smooth_workspace_bytes(H, W, max_release_cells, P, S))
+        return fail(AVL_ENOMEM, "%s: workspace too small", where);
+    return AVL_OK;
+}
+
+avl::SmoothArgs smooth_args(const float* dem, const float* mass, int32_t H, int32_t W, float cell_size,
+                            const avl_params* params, uint32_t P, uint32_t S, int32_t max_release_cells,
+                            const avl::SmoothWs& sw) {
+    avl::SmoothArgs a{};
+    a.dem = dem;
+    a.mass = mass;
+    a.cells = sw.w.cells;
+    a.runs = sw.w.runs;
+    a.run_off = sw.w.run_off;
+    a.queues = sw.w.queues;
+    a.ck = sw.ck;
+    a.end_rec = sw.end_rec;
+    a.pp = sw.pp;
+    a.scratch = sw.scratch;
+    a.H = H;
+    a.W = W;
+    a.S = S;
+    a.C = (uint32_t)avl::smooth_checkpoints(S);
+    a.cap = (unsigned long long)max_release_cells * P;
+    const float g = 9.81f;
+    a.g2 = g + g;
+    const float dl = params->step_cells * cell_size;
+    a.g2dl = a.g2 * dl;
+    a.xi = params->xi;
+    a.h = params->flow_height;
+    return a;
+}
+
+}  // namespace
+
+int avl_trajectories_smooth(const float* dem, const uint8_t* mask, const float* mass, int32_t H, int32_t W,
+                            float cell_size, const avl_params* params, uint32_t particles_per_cell,
+                            uint32_t step_limit, uint64_t seed, uint32_t run_id, int32_t max_release_cells,
+                            uint32_t flags, int64_t* deposit_q, float* deposit, int64_t* velocity_q, float* velocity,
+                            uint64_t* stats, int32_t* status, void* workspace, size_t workspace_bytes, void* stream) {
+    g_last_error.clear();
+    int rc = smooth_checks("avl_trajectories_smooth", dem, mask, H, W, cell_size, params, particles_per_cell,
+                           step_limit, max_release_cells, workspace, workspace_bytes);
+    if (rc != AVL_OK) return rc;
+    if (!deposit_q) return fail(AVL_EINVAL, "avl_trajectories_smooth: deposit_q is NULL");
+    if ((flags & ~AVL_SMOOTH_VELOCITY) != 0u) return fail(AVL_EINVAL, "avl_trajectories_smooth: unknown flag");
+    const bool vel = (flags & AVL_SMOOTH_VELOCITY) != 0u;
+    if (vel && !velocity_q) return fail(AVL_EINVAL, "avl_trajectories_smooth: velocity_q is NULL");
+    const int64_t n = (int64_t)H * W;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    avl::SmoothWs sw;
+    avl::smooth_layout(n, max_release_cells, particles_per_cell, step_limit, static_cast<char*>(workspace), &sw);
+    avl::SmoothArgs a = smooth_args(dem, mass, H, W, cell_size, params, particles_per_cell, step_limit,
+                                    max_release_cells, sw);
+    a.dep_q = reinterpret_cast<unsigned long long*>(deposit_q);
+    a.vel_q = vel ? reinterpret_cast<unsigned long long*>(velocity_q) : nullptr;
+    a.stats = stats ? reinterpret_cast<unsigned long long*>(stats) : sw.w.stats;
+    hipError_t e;
+    if ((e = avl::launch_compact(mask, n, sw.w.cells, sw.w.n_cells, sw.w.blk, s)) != hipSuccess)
+        return hip_fail(e, "avl_trajectories_smooth: compaction");
+    const avl::RunSpec spec{0u, 0u, 0u, run_id, (unsigned long long)seed};
+    if ((e = avl::launch_setup_runs(nullptr, nullptr, 0, spec, *params, sw.w.n_cells, 1, 1, 1, H, W, cell_size,
+                                    particles_per_cell, false, sw.w.runs, sw.w.run_off, status, s,
+                                    max_release_cells)) != hipSuccess)
+        return hip_fail(e, "avl_trajectories_smooth: run setup");
+    if ((e = avl::launch_fill_u32(reinterpret_cast<uint32_t*>(deposit_q), 0u, 2 * n, s)) != hipSuccess ||
+        (vel && (e = avl::launch_fill_u32(reinterpret_cast<uint32_t*>(velocity_q), 0u, 2 * n, s)) != hipSuccess) ||
+        (e = avl::launch_fill_u64(sw.w.queues, 0ull, avl::kXcds, s)) != hipSuccess ||
+        (e = avl::launch_fill_u64(a.stats, 0ull, 4, s)) != hipSuccess)
+        return hip_fail(e, "avl_trajectories_smooth: zero");
+    if ((e = avl::launch_smooth_forward(a, s)) != hipSuccess) return hip_fail(e, "avl_trajectories_smooth: launch");
+    if (deposit && (e = avl::launch_q_to_float(a.dep_q, n, deposit, s)) != hipSuccess)
+        return hip_fail(e, "avl_trajectories_smooth: deposit");
+    if (vel && velocity && (e = avl::launch_q_to_float(a.vel_q, n, velocity, s)) != hipSuccess)
+        return hip_fail(e, "avl_trajectories_smooth: velocity");
+    return AVL_OK;
+}
+
+int avl_trajectories_backward(const float* dem, const uint8_t* mask, const float* mass, int32_t H, int32_t W,
+                              float cell_size, const avl_params* params, uint32_t particles_per_cell,
+                              uint32_t step_limit, uint64_t seed, uint32_t run_id, int32_t max_release_cells,
+                              const float* grad_deposit, double* dparams, float* dmass, float* per_particle,
+                              void* workspace, size_t workspace_bytes, void* stream) {
+    g_last_error.clear();
+    (void)seed;
+    (void)run_id;
+    int rc = smooth_checks("avl_trajectories_backward", dem, mask, H, W, cell_size, params, particles_per_cell,
+                           step_limit, max_release_cells, workspace, workspace_bytes);
+    if (rc != AVL_OK) return rc;
+    if (!grad_deposit || !dparams || !dmass) return fail(AVL_EINVAL, "avl_trajectories_backward: null pointer");
+    const int64_t n = (int64_t)H * W;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    avl::SmoothWs sw;
+    avl::smooth_layout(n, max_release_cells, particles_per_cell, step_limit, static_cast<char*>(workspace), &sw);
+    avl::SmoothArgs a = smooth_args(dem, mass, H, W, cell_size, params, particles_per_cell, step_limit,
+                                    max_release_cells, sw);
+    a.gD = grad_deposit;
+    hipError_t e;
+    if ((e = avl::launch_fill_u32(reinterpret_cast<uint32_t*>(dmass), 0u, n, s)) != hipSuccess ||
+        (e = avl::launch_fill_u64(sw.w.queues, 0ull, avl::kXcds, s)) != hipSuccess)
+        return hip_fail(e, "avl_trajectories_backward: zero");
+    if ((e = avl::launch_smooth_backward(a, sw.w.n_cells, dmass, max_release_cells, sw.part, dparams, s)) !=
+        hipSuccess)
+        return hip_fail(e, "avl_trajectories_backward: launch");
+    if (per_particle && a.cap &&
+        (e = hipMemcpyAsync(per_particle, sw.pp, 4 * (size_t)a.cap * sizeof(float), hipMemcpyDeviceToDevice, s)) !=
+            hipSuccess)
+        return hip_fail(e, "avl_trajectories_backward: copy");
     return AVL_OK;
 }
 

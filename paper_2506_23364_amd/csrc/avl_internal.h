@@ -108,11 +108,44 @@ struct RunSpec {
     unsigned long long seed;
 };
 // specs/params: device arrays (batched) or NULL, then one_spec/one_param are used for the single run.
+// cap_cells >= 0: a run whose scenario has more release cells than cap_cells gets no slots (status 3).
 hipError_t launch_setup_runs(const RunSpec* specs, const ::avl_params* params, uint32_t n_params, RunSpec one_spec,
                              ::avl_params one_param, const int32_t* n_cells_per_scen, uint32_t n_scen, uint32_t n_tiles,
                              uint32_t n_runs, int32_t H, int32_t W, float cell_size, uint32_t P, bool batched,
-                             RunConst* runs, unsigned long long* run_off, int32_t* status, hipStream_t s);
+                             RunConst* runs, unsigned long long* run_off, int32_t* status, hipStream_t s,
+                             int64_t cap_cells = -1);
 hipError_t launch_trajectories(const TrajArgs& a, bool batched, const LaunchShape& shape, hipStream_t s);
+
+// Smooth forward and adjoint (smooth.hip)
+struct SmoothArgs {
+    const float* dem;
+    const float* mass;         // nullable: 1 per release cell
+    const int32_t* cells;
+    const RunConst* runs;      // one run
+    const unsigned long long* run_off;
+    unsigned long long* queues;
+    unsigned long long* dep_q;
+    unsigned long long* vel_q;  // nullable
+    unsigned long long* stats;
+    float* ck;                 // 5 x C x cap checkpoints (x, y, dx, dy, v^2), SoA
+    uint32_t* end_rec;         // cap: steps done << 2 | end reason
+    const float* gD;           // adjoint: dL/dD
+    float* pp;                 // adjoint: 4 x cap per-particle results (dmu, dxi, dh, sum gD w)
+    float2* scratch;           // adjoint: kCkpt x (grid threads) of (a_k, v^2_{k+1})
+    int32_t H, W;
+    uint32_t S, C;                          // step limit, checkpoints per particle
+    unsigned long long cap;                 // particle capacity of ck / end_rec / pp
+    float g2, g2dl, xi, h;                  // 2g, 2g * dl (dl = step_cells * cell_size), xi, h
+};
+
+
+size_t smooth_checkpoints(uint32_t S);
+size_t smooth_scratch_bytes();
+size_t smooth_reduce_blocks(unsigned long long cap);
+hipError_t launch_smooth_forward(const SmoothArgs& a, hipStream_t s);
+hipError_t launch_smooth_backward(const SmoothArgs& a, const int32_t* n_cells, float* dmass, int64_t n_grid,
+                                  double* part, double* dparams, hipStream_t s);
+hipError_t launch_q_to_float(const unsigned long long* q, int64_t n, float* out, hipStream_t s);
 hipError_t launch_finalize_vmax(uint32_t* vmax_bits, int64_t n, hipStream_t s);
 
 // Persistent-grid shape of kernel variant `variant` on the current device; number of variants.

@@ -1,0 +1,201 @@
+// Device helpers shared by the particle kernels (plain, batched, smooth forward and adjoint): the
+// random stream, the bilinear height patch and the wave-level queue utilities. Internal header.
+#pragma once
+
+#include "avl_internal.h"
+
+namespace avl {
+namespace dev {
+
+constexpr uint32_t kChunk = 64;  // particle slots taken from a queue per reservoir refill
+
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds of the 4x32 multiply-xor bijection with a Weyl key
+// schedule.
+__device__ __forceinline__ uint4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                               uint32_t k1) {
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+        const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+        const uint32_t n0 = hi1 ^ c1 ^ k0;
+        const uint32_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return make_uint4(c0, c1, c2, c3);
+}
+
+// 24 random bits -> uniform in [-1, 1), exact in binary32
+__device__ __forceinline__ float signed_unit(uint32_t u) {
+    return 2.0f * ((float)(u >> 8) * 5.9604644775390625e-8f) - 1.0f;
+}
+
+struct Sample {
+    float z, gx, gy;
+};
+
+// Bilinear patch through the four texel centres around (x, y), indices clamped to the grid.
+__device__ __forceinline__ Sample bilinear(const float* __restrict__ dem, int H, int W, float x, float y) {
+    const float sx = x - 0.5f, sy = y - 0.5f;
+    const float fc = floorf(sx), fr = floorf(sy);
+    const float fx = sx - fc, fy = sy - fr;
+    const int c0 = (int)fc, r0 = (int)fr;
+    const int ca = min(max(c0, 0), W - 1), cb = min(max(c0 + 1, 0), W - 1);
+    const int ra = min(max(r0, 0), H - 1), rb = min(max(r0 + 1, 0), H - 1);
+    const float* rowa = dem + (size_t)ra * W;
+    const float* rowb = dem + (size_t)rb * W;
+    const float a = rowa[ca], b = rowa[cb], c = rowb[ca], d = rowb[cb];
+    const float top = a + fx * (b - a);
+    const float bot = c + fx * (d - c);
+    Sample s;
+    s.z = top + fy * (bot - top);
+    s.gx = (b - a) + fy * ((d - c) - (b - a));
+    s.gy = bot - top;
+    return s;
+}
+
+// Corners and fractions of the bilinear patch (or splat) at (x, y), indices clamped to the grid.
+struct Corners {
+    int ca, cb, ra, rb;
+    float fx, fy;
+};
+__device__ __forceinline__ Corners corners(int H, int W, float x, float y) {
+    const float sx = x - 0.5f, sy = y - 0.5f;
+    const float fc = floorf(sx), fr = floorf(sy);
+    Corners k;
+    k.fx = sx - fc;
+    k.fy = sy - fr;
+    const int c0 = (int)fc, r0 = (int)fr;
+    k.ca = min(max(c0, 0), W - 1);
+    k.cb = min(max(c0 + 1, 0), W - 1);
+    k.ra = min(max(r0, 0), H - 1);
+    k.rb = min(max(r0 + 1, 0), H - 1);
+    return k;
+}
+
+__device__ __forceinline__ uint64_t wave_bcast64(uint64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t wave_sum64(uint64_t v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
+    return v;
+}
+
+__device__ __forceinline__ uint32_t xcd_id() {
+    // HW_REG_XCC_ID bits [3:0]: the XCD this wave runs on
+    return __builtin_amdgcn_s_getreg((3 << 11) | 20) & (uint32_t)(kXcds - 1);
+}
+
+__device__ __forceinline__ float uniform_f(float v) {
+    return __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(v)));
+}
+__device__ __forceinline__ uint32_t uniform_u(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// The run constants held in scalar registers (every lane has the same run).
+__device__ __forceinline__ RunConst uniform_run(const RunConst& r) {
+    RunConst u = r;
+    u.per = uniform_f(r.per);
+    u.Q = uniform_f(r.Q);
+    u.rnd = uniform_f(r.rnd);
+    u.L = uniform_f(r.L);
+    u.dl2 = uniform_f(r.dl2);
+    u.mdl = uniform_f(r.mdl);
+    u.cd = uniform_f(r.cd);
+    u.tca = uniform_f(r.tca);
+    u.key0 = uniform_u(r.key0);
+    u.key1 = uniform_u(r.key1);
+    u.run = uniform_u(r.run);
+    u.use_alpha = uniform_u(r.use_alpha);
+    u.dem_off = uniform_u(r.dem_off);
+    u.cells_off = uniform_u(r.cells_off);
+    u.raster_off = uniform_u(r.raster_off);
+    u.P = uniform_u(r.P);
+    u.n_slots = ((unsigned long long)uniform_u((uint32_t)(r.n_slots >> 32)) << 32) | uniform_u((uint32_t)r.n_slots);
+    return u;
+}
+
+// Run holding padded slot `slot`: the r with run_off[r] <= slot < run_off[r + 1]. Wave-uniform input.
+__device__ __forceinline__ uint32_t find_run(const unsigned long long* __restrict__ off, uint32_t n_runs,
+                                             uint64_t slot) {
+    uint32_t lo = 0, hi = n_runs;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (off[mid] <= slot)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// start of XCD partition p of the padded slot range [0, total): a multiple of kChunk
+__device__ __forceinline__ uint64_t part_begin(uint64_t total, uint32_t p) {
+    if (p >= (uint32_t)kXcds) return total;
+    return (total / kChunk * p / kXcds) * kChunk;
+}
+
+// Wave-uniform slot dispenser: a reservoir of up to kChunk slots refilled from per-XCD queues, the
+// wave starting on its own XCD's partition and moving on when it is empty.
+struct Dispenser {
+    uint64_t total;
+    uint32_t part, tried;
+    bool queue_empty;
+    uint64_t res_next, res_end;
+
+    __device__ __forceinline__ void init(uint64_t total_slots, uint32_t xcd) {
+        total = total_slots;
+        part = xcd;
+        tried = 0;
+        queue_empty = total == 0;
+        res_next = res_end = 0;
+    }
+    __device__ __forceinline__ bool drained() const { return queue_empty && res_next >= res_end; }
+
+    // Hands slots to the idle lanes (ballot `idle`) in lane order; returns this lane's slot or ~0.
+    __device__ __forceinline__ uint64_t take(unsigned long long* __restrict__ queues, uint64_t idle, int lane,
+                                             uint64_t below) {
+        const int nidle = __popcll(idle);
+        const uint64_t avail = res_end - res_next;
+        const int rank = __popcll(idle & below);
+        uint64_t slot = ~0ull;
+        if (avail >= (uint64_t)nidle) {
+            slot = res_next + rank;
+            res_next += nidle;
+            return slot;
+        }
+        uint64_t base = 0, cend = 0;
+        const int leader = __ffsll((long long)idle) - 1;
+        while (!queue_empty) {
+            const uint64_t pb = part_begin(total, part), pe = part_begin(total, part + 1);
+            uint64_t got = 0;
+            if (lane == leader) got = atomicAdd(queues + part, (unsigned long long)kChunk);
+            got = wave_bcast64(__shfl(got, leader, kWave));
+            if (pb + got < pe) {
+                base = pb + got;
+                cend = (base + kChunk < pe) ? base + kChunk : pe;
+                break;
+            }
+            part = (part + 1) % kXcds;
+            if (++tried >= (uint32_t)kXcds) queue_empty = true;
+        }
+        if ((uint64_t)rank < avail)
+            slot = res_next + rank;
+        else if (base + (rank - avail) < cend)
+            slot = base + (rank - avail);
+        const uint64_t next = base + ((uint64_t)nidle - avail);
+        res_next = next < cend ? next : cend;
+        res_end = cend;
+        return slot;
+    }
+};
+
+}  // namespace dev
+}  // namespace avl

@@ -1,0 +1,457 @@
+// Smooth variant of the trajectory pass and its adjoint (arXiv 2506.23364, section 5.2: the particles
+// spread the released mass along the flow; here the mass each particle carries is deposited where it
+// comes to rest, so the deposit raster is a differentiable function of the friction parameters).
+//
+// Forward: every particle of release cell c carries mp = mass[c] / P. An energy stop during a step puts
+// it at the zero of the step's (linear) energy numerator, the fraction t* = v^2 / (v^2 - num) of the
+// step; a runout-angle stop or the step limit leaves it where it is; leaving the grid loses the mass.
+// The mass is splatted bilinearly (the height patch's corners and weights) into an int64 fixed-point
+// raster (2^-24 units): order-independent, so reproducible bit for bit. Optionally every accepted step
+// splats mp * v at the new position (velocity raster). Every kCkpt steps the particle's state
+// (x, y, dx, dy, v^2) is checkpointed, and its end (steps done, reason) is recorded.
+//
+// Adjoint, per particle: the paths do not depend on (mu, xi, h, mass), so only v^2 along the path and
+// the fractional last step do. Given gD = dL/dD, the kernel recomputes the last segment from its
+// checkpoint, takes dL/dp* through the splat weights and dL/dt* = dL/dp* . (p1 - p), then runs the
+// reverse sweep of the v^2 recursion segment by segment (each segment recomputed forward from its
+// checkpoint into a per-lane scratch of (a_k, v^2_{k+1}), then swept backward). Per-particle
+// results are reduced in a fixed order (deterministic).
+#include "particle.h"
+
+namespace avl {
+
+using namespace dev;
+
+namespace {
+
+constexpr uint32_t kCkpt = 64;        // steps between checkpoints (even: segments start on even steps)
+constexpr int kSmoothBlock = 256;
+constexpr int kBackwardGrid = 1024;   // blocks of the adjoint kernel (its scratch is sized for this)
+constexpr int kReduceChunk = 4096;    // particles per block of the gradient reduction
+static_assert(kCkpt % 2 == 0, "segments must start on even steps (one Philox block serves two steps)");
+
+enum : uint32_t { kEndLimit = 0, kEndExit = 1, kEndStop = 2, kEndAngle = 3 };
+enum : int { kAccept = 0, kExit = 1, kStop = 2, kAngle = 3 };
+
+struct State {
+    float x, y, z, gx, gy, dx, dy, v2, x0, y0, zr;
+    uint32_t spare_x, spare_y;
+};
+
+struct StepOut {
+    int outcome;
+    float x1, y1, num;  // target of the step and its energy numerator
+    float a;            // drag term a = 2g ds / (xi h) of an accepted step
+};
+
+// Release state of particle (cell_id, ...) at the texel centre, heading downslope.
+__device__ __forceinline__ void release(State& s, const float* __restrict__ dem, int H, int W, uint32_t cell_id) {
+    const int r = (int)(cell_id / (uint32_t)W);
+    const int c = (int)(cell_id - (uint32_t)r * (uint32_t)W);
+    s.x = (float)c + 0.5f;
+    s.y = (float)r + 0.5f;
+    const Sample s0 = bilinear(dem, H, W, s.x, s.y);
+    s.z = s0.z;
+    s.gx = s0.gx;
+    s.gy = s0.gy;
+    s.x0 = s.x;
+    s.y0 = s.y;
+    s.zr = s.z;
+    const float gg = s.gx * s.gx + s.gy * s.gy;
+    if (gg > 0.0f) {
+        const float t = 1.0f / sqrtf(gg);
+        s.dx = -(s.gx * t);
+        s.dy = -(s.gy * t);
+    } else {
+        s.dx = 0.0f;
+        s.dy = 0.0f;
+    }
+    s.v2 = 0.0f;
+}
+
+// Step n of the model (the same binary32 operations as the plain pass). Updates s when accepted.
+__device__ __forceinline__ StepOut step(State& s, uint32_t n, uint32_t rep, uint32_t cell_id, const RunConst& rc,
+                                        const float* __restrict__ dem, int H, int W, float g2) {
+    StepOut o;
+    uint32_t ux, uy;
+    if ((n & 1u) == 0u) {
+        const uint4 b = philox4x32_10(n >> 1, rep, cell_id, rc.run, rc.key0, rc.key1);
+        ux = b.x;
+        uy = b.y;
+        s.spare_x = b.z;
+        s.spare_y = b.w;
+    } else {
+        ux = s.spare_x;
+        uy = s.spare_y;
+    }
+    const float rx = signed_unit(ux), ry = signed_unit(uy);
+    const float gg = s.gx * s.gx + s.gy * s.gy;
+    const float t = gg > 0.0f ? rc.Q / sqrtf(gg) : 0.0f;
+    const float wx = (rc.per * s.dx - t * s.gx) + rc.rnd * rx;
+    const float wy = (rc.per * s.dy - t * s.gy) + rc.rnd * ry;
+    const float ww = wx * wx + wy * wy;
+    if (ww > 0.0f) {
+        const float inv = 1.0f / sqrtf(ww);
+        s.dx = wx * inv;
+        s.dy = wy * inv;
+    }
+    o.x1 = s.x + rc.L * s.dx;
+    o.y1 = s.y + rc.L * s.dy;
+    o.num = 0.0f;
+    o.a = 0.0f;
+    const float fc1 = floorf(o.x1), fr1 = floorf(o.y1);
+    if (!(fc1 >= 0.0f && fc1 < (float)W && fr1 >= 0.0f && fr1 < (float)H)) {
+        o.outcome = kExit;
+        return o;
+    }
+    const Sample s1 = bilinear(dem, H, W, o.x1, o.y1);
+    const float dz = s.z - s1.z;
+    const float ds = sqrtf(rc.dl2 + dz * dz);
+    o.num = s.v2 + g2 * (dz - rc.mdl);
+    if (!(o.num > 0.0f)) {
+        o.outcome = kStop;
+        return o;
+    }
+    o.a = rc.cd * ds;
+    const float v2n = o.num / (1.0f + o.a);
+    if (rc.use_alpha) {
+        const float hx = o.x1 - s.x0, hy = o.y1 - s.y0;
+        if ((s.zr - s1.z) < rc.tca * sqrtf(hx * hx + hy * hy)) {
+            o.outcome = kAngle;
+            return o;
+        }
+    }
+    s.x = o.x1;
+    s.y = o.y1;
+    s.z = s1.z;
+    s.gx = s1.gx;
+    s.gy = s1.gy;
+    s.v2 = v2n;
+    o.outcome = kAccept;
+    return o;
+}
+
+__device__ __forceinline__ void splat_q(unsigned long long* __restrict__ q, int H, int W, float x, float y, float val) {
+    const Corners k = corners(H, W, x, y);
+    const float w00 = (1.0f - k.fx) * (1.0f - k.fy), w01 = k.fx * (1.0f - k.fy);
+    const float w10 = (1.0f - k.fx) * k.fy, w11 = k.fx * k.fy;
+    const float sc = 16777216.0f;  // 2^24
+    atomicAdd(q + (size_t)k.ra * W + k.ca, (unsigned long long)(long long)rintf((val * w00) * sc));
+    atomicAdd(q + (size_t)k.ra * W + k.cb, (unsigned long long)(long long)rintf((val * w01) * sc));
+    atomicAdd(q + (size_t)k.rb * W + k.ca, (unsigned long long)(long long)rintf((val * w10) * sc));
+    atomicAdd(q + (size_t)k.rb * W + k.cb, (unsigned long long)(long long)rintf((val * w11) * sc));
+}
+
+__device__ __forceinline__ float mass_per_particle(const float* __restrict__ mass, uint32_t cell, uint32_t P) {
+    return (mass ? mass[cell] : 1.0f) / (float)P;
+}
+
+}  // namespace
+
+
+__global__ __launch_bounds__(kSmoothBlock) void k_smooth_forward(SmoothArgs a) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
+    const RunConst rc = uniform_run(a.runs[0]);
+    const int H = a.H, W = a.W;
+    Dispenser disp;
+    disp.init(wave_bcast64(a.run_off[1]), xcd_id());
+    const size_t cplane = (size_t)a.C * a.cap;
+
+    bool alive = false;
+    State s{};
+    uint32_t n = 0, rep = 0, cell_id = 0;
+    uint64_t slot_id = 0;
+    float mp = 0.0f;
+    uint64_t st_steps = 0;
+    uint32_t st_exit = 0, st_stop = 0, st_limit = 0;
+
+    for (;;) {
+        const uint64_t idle = __ballot(!alive);
+        if (__popcll(idle) == kWave && disp.drained()) break;
+        if (idle && !disp.drained()) {
+            const uint64_t slot = disp.take(a.queues, idle, lane, below);
+            if (!alive && slot < rc.n_slots) {
+                const uint64_t i = slot / rc.P;
+                rep = (uint32_t)(slot - i * rc.P);
+                cell_id = (uint32_t)a.cells[i];
+                slot_id = slot;
+                mp = mass_per_particle(a.mass, cell_id, rc.P);
+                release(s, a.dem, H, W, cell_id);
+                n = 0;
+                alive = true;
+            }
+        }
+        if (!alive) continue;
+        if (n >= a.S) {
+            ++st_limit;
+            a.end_rec[slot_id] = (n << 2) | kEndLimit;
+            splat_q(a.dep_q, H, W, s.x, s.y, mp);
+            alive = false;
+            continue;
+        }
+        if (n % kCkpt == 0) {
+            const size_t at = (size_t)(n / kCkpt) * a.cap + slot_id;
+            a.ck[at] = s.x;
+            a.ck[cplane + at] = s.y;
+            a.ck[2 * cplane + at] = s.dx;
+            a.ck[3 * cplane + at] = s.dy;
+            a.ck[4 * cplane + at] = s.v2;
+        }
+        ++st_steps;
+        const float xp = s.x, yp = s.y, v2p = s.v2;
+        const StepOut o = step(s, n, rep, cell_id, rc, a.dem, H, W, a.g2);
+        if (o.outcome == kAccept) {
+            ++n;
+            if (a.vel_q) splat_q(a.vel_q, H, W, s.x, s.y, mp * sqrtf(s.v2));
+            continue;
+        }
+        alive = false;
+        if (o.outcome == kExit) {
+            ++st_exit;
+            a.end_rec[slot_id] = (n << 2) | kEndExit;
+        } else if (o.outcome == kStop) {
+            ++st_stop;
+            a.end_rec[slot_id] = (n << 2) | kEndStop;
+            const float t = v2p > 0.0f ? v2p / (v2p - o.num) : 0.0f;
+            splat_q(a.dep_q, H, W, xp + t * (o.x1 - xp), yp + t * (o.y1 - yp), mp);
+        } else {
+            ++st_stop;
+            a.end_rec[slot_id] = (n << 2) | kEndAngle;
+            splat_q(a.dep_q, H, W, xp, yp, mp);
+        }
+    }
+    const uint64_t s0 = wave_sum64(st_steps), s1 = wave_sum64(st_exit), s2 = wave_sum64(st_stop);
+    const uint64_t s3 = wave_sum64(st_limit);
+    if (lane == 0) {
+        if (s0) atomicAdd(a.stats + 0, (unsigned long long)s0);
+        if (s1) atomicAdd(a.stats + 1, (unsigned long long)s1);
+        if (s2) atomicAdd(a.stats + 2, (unsigned long long)s2);
+        if (s3) atomicAdd(a.stats + 3, (unsigned long long)s3);
+    }
+}
+
+__global__ __launch_bounds__(kSmoothBlock) void k_smooth_backward(SmoothArgs a) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
+    const RunConst rc = uniform_run(a.runs[0]);
+    const int H = a.H, W = a.W;
+    const size_t T = (size_t)gridDim.x * blockDim.x;
+    const size_t gtid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t cplane = (size_t)a.C * a.cap;
+    const float g2dl = a.g2dl;
+    Dispenser disp;
+    disp.init(wave_bcast64(a.run_off[1]), xcd_id());
+
+    for (;;) {
+        const uint64_t idle = __ballot(true);
+        if (disp.drained()) break;
+        const uint64_t slot = disp.take(a.queues, idle, lane, below);
+        if (slot >= rc.n_slots) continue;
+        const uint64_t i = slot / rc.P;
+        const uint32_t rep = (uint32_t)(slot - i * rc.P);
+        const uint32_t cell_id = (uint32_t)a.cells[i];
+        const float mp = mass_per_particle(a.mass, cell_id, rc.P);
+        const uint32_t rec = a.end_rec[slot];
+        const uint32_t n_end = rec >> 2, reason = rec & 3u;
+        float dmu = 0.0f, dxi = 0.0f, dh = 0.0f, gw = 0.0f;
+        if (reason != kEndExit) {
+            // last segment: from its checkpoint (or the release) up to the end
+            State s{};
+            int32_t c_last = -1;
+            if (a.C > 0) c_last = (int32_t)min(n_end / kCkpt, a.C - 1);
+            uint32_t n0 = 0;
+            auto load = [&](int32_t c) {
+                if (c < 0) {
+                    release(s, a.dem, H, W, cell_id);
+                    return;
+                }
+                const size_t at = (size_t)c * a.cap + slot;
+                s.x = a.ck[at];
+                s.y = a.ck[cplane + at];
+                s.dx = a.ck[2 * cplane + at];
+                s.dy = a.ck[3 * cplane + at];
+                s.v2 = a.ck[4 * cplane + at];
+                const Sample sm = bilinear(a.dem, H, W, s.x, s.y);
+                s.z = sm.z;
+                s.gx = sm.gx;
+                s.gy = sm.gy;
+                // release point of the particle (for the runout-angle test)
+                const int r = (int)(cell_id / (uint32_t)W);
+                const int cc = (int)(cell_id - (uint32_t)r * (uint32_t)W);
+                s.x0 = (float)cc + 0.5f;
+                s.y0 = (float)r + 0.5f;
+                s.zr = bilinear(a.dem, H, W, s.x0, s.y0).z;
+            };
+            load(c_last);
+            n0 = c_last < 0 ? 0u : (uint32_t)c_last * kCkpt;
+            for (uint32_t k = n0; k < n_end; ++k) {
+                const StepOut o = step(s, k, rep, cell_id, rc, a.dem, H, W, a.g2);
+                a.scratch[(size_t)(k - n0) * T + gtid] = make_float2(o.a, s.v2);
+            }
+            float px = s.x, py = s.y;
+            float lam = 0.0f, gt = 0.0f;
+            bool stop = false;
+            if (reason == kEndStop) {
+                const float xp = s.x, yp = s.y, v2p = s.v2;
+                const StepOut o = step(s, n_end, rep, cell_id, rc, a.dem, H, W, a.g2);
+                const float t = v2p > 0.0f ? v2p / (v2p - o.num) : 0.0f;
+                px = xp + t * (o.x1 - xp);
+                py = yp + t * (o.y1 - yp);
+                // dL/dp* through the splat weights, dL/dt*
+                const Corners k = corners(H, W, px, py);
+                const float g00 = a.gD[(size_t)k.ra * W + k.ca], g01 = a.gD[(size_t)k.ra * W + k.cb];
+                const float g10 = a.gD[(size_t)k.rb * W + k.ca], g11 = a.gD[(size_t)k.rb * W + k.cb];
+                const float gpx = ((g01 - g00) * (1.0f - k.fy)) + ((g11 - g10) * k.fy);
+                const float gpy = ((g10 - g00) * (1.0f - k.fx)) + ((g11 - g01) * k.fx);
+                const float w00 = (1.0f - k.fx) * (1.0f - k.fy), w01 = k.fx * (1.0f - k.fy);
+                const float w10 = (1.0f - k.fx) * k.fy, w11 = k.fx * k.fy;
+                gw = ((g00 * w00) + (g01 * w01)) + ((g10 * w10) + (g11 * w11));
+                gt = mp * ((gpx * (o.x1 - xp)) + (gpy * (o.y1 - yp)));
+                const float Dn = v2p - o.num;
+                if (Dn > 0.0f) {
+                    lam = gt / Dn;
+                    dmu = -((gt * (v2p / Dn)) * (g2dl / Dn));
+                }
+                stop = true;
+            } else {
+                const Corners k = corners(H, W, px, py);
+                const float g00 = a.gD[(size_t)k.ra * W + k.ca], g01 = a.gD[(size_t)k.ra * W + k.cb];
+                const float g10 = a.gD[(size_t)k.rb * W + k.ca], g11 = a.gD[(size_t)k.rb * W + k.cb];
+                const float w00 = (1.0f - k.fx) * (1.0f - k.fy), w01 = k.fx * (1.0f - k.fy);
+                const float w10 = (1.0f - k.fx) * k.fy, w11 = k.fx * k.fy;
+                gw = ((g00 * w00) + (g01 * w01)) + ((g10 * w10) + (g11 * w11));
+            }
+            if (stop) {
+                // reverse sweep: the last segment from the scratch, then earlier segments recomputed
+                // an energy stop needs a step, so step_limit >= 1 and checkpoint 0 exists: c_last >= 0
+                for (int32_t c = c_last; c >= 0; --c) {
+                    const uint32_t c0 = (uint32_t)c * kCkpt;
+                    const uint32_t c1 = (c == c_last) ? n_end : c0 + kCkpt;
+                    if (c != c_last) {
+                        load(c);
+                        for (uint32_t k = c0; k < c1; ++k) {
+                            const StepOut o = step(s, k, rep, cell_id, rc, a.dem, H, W, a.g2);
+                            a.scratch[(size_t)(k - c0) * T + gtid] = make_float2(o.a, s.v2);
+                        }
+                    }
+                    for (uint32_t k = c1; k-- > c0;) {
+                        const float2 e = a.scratch[(size_t)(k - c0) * T + gtid];
+                        const float aa = e.x, v2n = e.y;
+                        const float op = 1.0f + aa;
+                        dmu = dmu - lam * (g2dl / op);
+                        dxi = dxi + lam * ((v2n * aa) / (a.xi * op));
+                        dh = dh + lam * ((v2n * aa) / (a.h * op));
+                        lam = lam / op;
+                    }
+                }
+            }
+        }
+        a.pp[slot] = dmu;
+        a.pp[a.cap + slot] = dxi;
+        a.pp[2 * a.cap + slot] = dh;
+        a.pp[3 * a.cap + slot] = gw;
+    }
+}
+
+// ------------------------------------------------------------------------------------------ reductions
+
+// Sum of the per-particle (dmu, dxi, dh) over particles [0, n): each block sums kReduceChunk particles
+// (16 per thread in order, then a fixed tree) into partial[block]; all in binary64.
+__global__ __launch_bounds__(256) void k_reduce_params(const float* __restrict__ pp, unsigned long long cap,
+                                                       const RunConst* __restrict__ runs, double* __restrict__ part) {
+    __shared__ double sh[3][256];
+    const unsigned long long n = runs[0].n_slots;
+    const unsigned long long base = (unsigned long long)blockIdx.x * kReduceChunk + threadIdx.x * 16ull;
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int k = 0; k < 16; ++k) {
+        const unsigned long long i = base + k;
+        if (i < n) {
+            acc[0] += (double)pp[i];
+            acc[1] += (double)pp[cap + i];
+            acc[2] += (double)pp[2 * cap + i];
+        }
+    }
+    for (int q = 0; q < 3; ++q) sh[q][threadIdx.x] = acc[q];
+    __syncthreads();
+    for (int d = 128; d >= 1; d >>= 1) {
+        if ((int)threadIdx.x < d)
+            for (int q = 0; q < 3; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + d];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int q = 0; q < 3; ++q) part[3 * (size_t)blockIdx.x + q] = sh[q][0];
+}
+
+__global__ __launch_bounds__(256) void k_reduce_final(const double* __restrict__ part, int nb, double* __restrict__ out) {
+    __shared__ double sh[3][256];
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < nb; b += 256)
+        for (int q = 0; q < 3; ++q) acc[q] += part[3 * (size_t)b + q];
+    for (int q = 0; q < 3; ++q) sh[q][threadIdx.x] = acc[q];
+    __syncthreads();
+    for (int d = 128; d >= 1; d >>= 1) {
+        if ((int)threadIdx.x < d)
+            for (int q = 0; q < 3; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + d];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int q = 0; q < 3; ++q) out[q] = sh[q][0];
+}
+
+// dL/dmass of release cell i: (sum over its P particles of sum gD w, in order, binary64) / P
+__global__ __launch_bounds__(256) void k_dmass(const float* __restrict__ gw, const int32_t* __restrict__ cells,
+                                               const int32_t* __restrict__ n_cells, const RunConst* __restrict__ runs,
+                                               float* __restrict__ dmass) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (runs[0].n_slots == 0 || i >= (int64_t)*n_cells) return;
+    const uint32_t P = runs[0].P;
+    double s = 0.0;
+    for (uint32_t j = 0; j < P; ++j) s += (double)gw[(size_t)i * P + j];
+    dmass[cells[i]] = (float)(s / (double)P);
+}
+
+// fixed point (2^-24) -> float
+__global__ __launch_bounds__(256) void k_q_to_float(const unsigned long long* __restrict__ q, int64_t n,
+                                                    float* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (float)((double)(long long)q[i] * 0x1p-24);
+}
+
+// ------------------------------------------------------------------------------------------ launchers
+
+size_t smooth_checkpoints(uint32_t S) { return S == 0 ? 0 : (S + kCkpt - 1) / kCkpt; }
+size_t smooth_scratch_bytes() { return (size_t)kCkpt * kBackwardGrid * kSmoothBlock * sizeof(float2); }
+size_t smooth_reduce_blocks(unsigned long long cap) { return (size_t)((cap + kReduceChunk - 1) / kReduceChunk) + 1; }
+
+hipError_t launch_smooth_forward(const SmoothArgs& a, hipStream_t s) {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        cus = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k_smooth_forward),
+                                                     kSmoothBlock, 0) != hipSuccess ||
+        per_cu <= 0)
+        per_cu = 1;
+    hipLaunchKernelGGL(k_smooth_forward, dim3(cus * per_cu), dim3(kSmoothBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_smooth_backward(const SmoothArgs& a, const int32_t* n_cells, float* dmass, int64_t n_grid,
+                                  double* part, double* dparams, hipStream_t s) {
+    hipLaunchKernelGGL(k_smooth_backward, dim3(kBackwardGrid), dim3(kSmoothBlock), 0, s, a);
+    const int nb = (int)smooth_reduce_blocks(a.cap);
+    hipLaunchKernelGGL(k_reduce_params, dim3(nb), dim3(256), 0, s, a.pp, a.cap, a.runs, part);
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, s, part, nb, dparams);
+    const unsigned blocks = (unsigned)((n_grid + 255) / 256);
+    if (blocks) hipLaunchKernelGGL(k_dmass, dim3(blocks), dim3(256), 0, s, a.pp + 3 * a.cap, a.cells, n_cells, a.runs, dmass);
+    return hipGetLastError();
+}
+
+hipError_t launch_q_to_float(const unsigned long long* q, int64_t n, float* out, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_q_to_float, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, q, n, out);
+    return hipGetLastError();
+}
+
+}  // namespace avl

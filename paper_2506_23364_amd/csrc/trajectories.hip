@@ -24,81 +24,15 @@
 //  - Accumulation is integer only (u32 add; u32 max on the bits of v^2 >= 0, whose order is the value
 //    order), so every raster is independent of scheduling and of the kernel variant: bit-reproducible.
 //  - Philox4x32-10 gives four words per block; one block serves two consecutive steps.
-#include "avl_internal.h"
+#include "particle.h"
 
 namespace avl {
 
 namespace {
 
 constexpr int kTbl = 256;          // table slots per wave (power of two)
-constexpr uint32_t kChunk = 64;    // particle slots taken from a queue per reservoir refill
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;
-
-// Philox4x32-10 (Salmon et al., SC'11): ten rounds of the 4x32 multiply-xor bijection with a Weyl key
-// schedule.
-__device__ __forceinline__ uint4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
-                                               uint32_t k1) {
-#pragma unroll
-    for (int round = 0; round < 10; ++round) {
-        const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
-        const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
-        const uint32_t n0 = hi1 ^ c1 ^ k0;
-        const uint32_t n2 = hi0 ^ c3 ^ k1;
-        c0 = n0;
-        c1 = lo1;
-        c2 = n2;
-        c3 = lo0;
-        k0 += 0x9E3779B9u;
-        k1 += 0xBB67AE85u;
-    }
-    return make_uint4(c0, c1, c2, c3);
-}
-
-// 24 random bits -> uniform in [-1, 1), exact in binary32
-__device__ __forceinline__ float signed_unit(uint32_t u) {
-    return 2.0f * ((float)(u >> 8) * 5.9604644775390625e-8f) - 1.0f;
-}
-
-struct Sample {
-    float z, gx, gy;
-};
-
-// Bilinear patch through the four texel centres around (x, y), indices clamped to the grid.
-__device__ __forceinline__ Sample bilinear(const float* __restrict__ dem, int H, int W, float x, float y) {
-    const float sx = x - 0.5f, sy = y - 0.5f;
-    const float fc = floorf(sx), fr = floorf(sy);
-    const float fx = sx - fc, fy = sy - fr;
-    const int c0 = (int)fc, r0 = (int)fr;
-    const int ca = min(max(c0, 0), W - 1), cb = min(max(c0 + 1, 0), W - 1);
-    const int ra = min(max(r0, 0), H - 1), rb = min(max(r0 + 1, 0), H - 1);
-    const float* rowa = dem + (size_t)ra * W;
-    const float* rowb = dem + (size_t)rb * W;
-    const float a = rowa[ca], b = rowa[cb], c = rowb[ca], d = rowb[cb];
-    const float top = a + fx * (b - a);
-    const float bot = c + fx * (d - c);
-    Sample s;
-    s.z = top + fy * (bot - top);
-    s.gx = (b - a) + fy * ((d - c) - (b - a));
-    s.gy = bot - top;
-    return s;
-}
-
-__device__ __forceinline__ uint64_t wave_bcast64(uint64_t v) {
-    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
-    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
-    return ((uint64_t)hi << 32) | lo;
-}
-
-__device__ __forceinline__ uint64_t wave_sum64(uint64_t v) {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
-    return v;
-}
-
-__device__ __forceinline__ uint32_t xcd_id() {
-    // HW_REG_XCC_ID bits [3:0]: the XCD this wave runs on
-    return __builtin_amdgcn_s_getreg((3 << 11) | 20) & (uint32_t)(kXcds - 1);
-}
+using dev::kChunk;
 
 __device__ __forceinline__ uint32_t slot_of(uint32_t key) {
     return (key * 0x9E3779B1u) >> (32 - 8);  // kTbl = 2^8
@@ -119,55 +53,9 @@ __device__ __forceinline__ void global_max(uint32_t* __restrict__ p, uint32_t bi
     if (__builtin_nontemporal_load(p) < bits) atomicMax(p, bits);
 }
 
-// Run holding padded slot `slot`: the r with run_off[r] <= slot < run_off[r + 1]. Wave-uniform input.
-__device__ __forceinline__ uint32_t find_run(const unsigned long long* __restrict__ off, uint32_t n_runs,
-                                             uint64_t slot) {
-    uint32_t lo = 0, hi = n_runs;
-    while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (off[mid] <= slot)
-            lo = mid;
-        else
-            hi = mid;
-    }
-    return lo;
-}
-
-__device__ __forceinline__ float uniform_f(float v) {
-    return __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(v)));
-}
-__device__ __forceinline__ uint32_t uniform_u(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
-
-// The run constants held in scalar registers (the single-run kernel: every lane has the same run).
-__device__ __forceinline__ RunConst uniform_run(const RunConst& r) {
-    RunConst u = r;
-    u.per = uniform_f(r.per);
-    u.Q = uniform_f(r.Q);
-    u.rnd = uniform_f(r.rnd);
-    u.L = uniform_f(r.L);
-    u.dl2 = uniform_f(r.dl2);
-    u.mdl = uniform_f(r.mdl);
-    u.cd = uniform_f(r.cd);
-    u.tca = uniform_f(r.tca);
-    u.key0 = uniform_u(r.key0);
-    u.key1 = uniform_u(r.key1);
-    u.run = uniform_u(r.run);
-    u.use_alpha = uniform_u(r.use_alpha);
-    u.dem_off = uniform_u(r.dem_off);
-    u.cells_off = uniform_u(r.cells_off);
-    u.raster_off = uniform_u(r.raster_off);
-    u.P = uniform_u(r.P);
-    u.n_slots = ((unsigned long long)uniform_u((uint32_t)(r.n_slots >> 32)) << 32) | uniform_u((uint32_t)r.n_slots);
-    return u;
-}
-
-// start of XCD partition p of the padded slot range [0, total): a multiple of kChunk
-__device__ __forceinline__ uint64_t part_begin(uint64_t total, uint32_t p) {
-    if (p >= (uint32_t)kXcds) return total;
-    return (total / kChunk * p / kXcds) * kChunk;
-}
-
 }  // namespace
+
+using namespace dev;
 
 template <bool kBatch, int kBlock, int kFlush>
 __global__ __launch_bounds__(kBlock) void k_trajectories(TrajArgs a) {
@@ -494,7 +382,7 @@ __global__ __launch_bounds__(1024) void k_setup_runs(const RunSpec* __restrict__
                                                      float cs, uint32_t P, int32_t batched,
                                                      RunConst* __restrict__ runs,
                                                      unsigned long long* __restrict__ run_off,
-                                                     int32_t* __restrict__ status) {
+                                                     int32_t* __restrict__ status, int64_t cap_cells) {
     __shared__ unsigned long long wsum[1024 / kWave];
     const uint32_t per_thread = (n_runs + 1023) / 1024;
     const uint32_t b0 = threadIdx.x * per_thread;
@@ -516,6 +404,7 @@ __global__ __launch_bounds__(1024) void k_setup_runs(const RunSpec* __restrict__
                             __builtin_isfinite(p.tan_alpha) && p.flags == 0u;
             if (!ok) bad = 2;
         }
+        if (!bad && cap_cells >= 0 && (int64_t)n_cells_per_scen[sp.scenario] > cap_cells) bad = 3;
         RunConst c{};
         // derived constants, binary32, in this order
         const float g = 9.81f;
@@ -570,10 +459,11 @@ __global__ __launch_bounds__(1024) void k_setup_runs(const RunSpec* __restrict__
 hipError_t launch_setup_runs(const RunSpec* specs, const ::avl_params* params, uint32_t n_params, RunSpec one_spec,
                              ::avl_params one_param, const int32_t* n_cells_per_scen, uint32_t n_scen, uint32_t n_tiles,
                              uint32_t n_runs, int32_t H, int32_t W, float cell_size, uint32_t P, bool batched,
-                             RunConst* runs, unsigned long long* run_off, int32_t* status, hipStream_t s) {
+                             RunConst* runs, unsigned long long* run_off, int32_t* status, hipStream_t s,
+                             int64_t cap_cells) {
     hipLaunchKernelGGL(k_setup_runs, dim3(1), dim3(1024), 0, s, specs, params, n_params, one_spec, one_param,
                        n_cells_per_scen, n_scen, n_tiles, n_runs, H, W, cell_size, P, batched ? 1 : 0, runs, run_off,
-                       status);
+                       status, cap_cells);
     return hipGetLastError();
 }
 

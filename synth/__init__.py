@@ -277,10 +277,15 @@ def grow_region(score: np.ndarray, n_cells: int, start: int) -> np.ndarray:
     return out.reshape(h, w)
 
 
+# A 1024^2 window of the 2048^2 alpine statistics: relief 2000 m x 2^-0.8 (Hurst 0.8).
+TILE_RELIEF_M = 2000.0 * 0.5 ** 0.8
+
+
 def make_ensemble(n_tiles: int = 16, size: int = 1024, n_params: int = 64, particles_per_cell: int = 32,
-                  step_limit: int = 2000, relief_m: float = 2000.0, cell_size: float = 10.0,
+                  step_limit: int = 2000, relief_m: float = TILE_RELIEF_M, cell_size: float = 10.0,
                   min_cells: int = 100, max_cells: int = 50000, seed: int = 12345) -> Ensemble:
-    """The ensemble sweep: n_tiles ridged-fBm tiles (seeds 100, 101, ...), each with one connected release
+    """The ensemble sweep: n_tiles ridged-fBm tiles (seeds 100, 101, ...; relief 1149 m, the alpine tile's
+    statistics on a 1024^2 window), each with one connected release
     scenario of round(exp(U(ln min_cells, ln max_cells))) cells (sizes from seed 7): grown best-first
     (closest to 37.5 degrees first) from a seeded start cell of 30-45 degrees in the upper half of the
     elevations; crossed with n_params parameter sets mu ~ U[0.1, 0.4], xi ~ U[500, 3000], h ~ U[0.5, 3]
@@ -299,3 +304,35 @@ def make_ensemble(n_tiles: int = 16, size: int = 1024, n_params: int = 64, parti
     params = [dict(DEFAULT_PARAMS, mu=float(m), xi=float(x), flow_height=float(h)) for m, x, h in ps]
     runs = [(t, t, p, t * n_params + p, seed) for t in range(n_tiles) for p in range(n_params)]
     return Ensemble(dems, masks, params, runs, cell_size, particles_per_cell, step_limit)
+
+
+@dataclass
+class Calibration:
+    """Differentiable-calibration workload: DEM, one connected release scenario with mass 1 per cell,
+    the hidden (mu*, xi*) that makes the target deposit, and the starting point (mu0, xi0)."""
+    dem: np.ndarray
+    mask: np.ndarray
+    mass: np.ndarray
+    cell_size: float
+    particles_per_cell: int
+    step_limit: int
+    mu_star: float
+    xi_star: float
+    mu0: float
+    xi0: float
+    flow_height: float
+    seed: int
+
+
+def make_calibration(size: int = 1024, n_cells: int = 5000, particles_per_cell: int = 128, step_limit: int = 3000,
+                     relief_m: float = TILE_RELIEF_M, seed: int = 4) -> Calibration:
+    """1024^2 ridged fBm DEM at 10 m (seed 4, relief 1149 m) with a 5000-cell release scenario grown best-first from a
+    seeded steep start in the upper half of the elevations; mass 1 per release cell; target from
+    mu* = 0.22, xi* = 1800; gradient taken at (mu0, xi0) = (0.26, 1400); h = 1 m."""
+    dem = alpine_dem(size, relief_m, seed=seed)
+    sl = slope_deg(dem, 10.0)
+    cand = np.flatnonzero(((sl >= 30.0) & (sl <= 45.0) & (dem >= np.median(dem))).ravel())
+    start = int(cand[np.random.default_rng(seed).integers(cand.size)])
+    mask = grow_region(-np.abs(sl - 37.5), n_cells, start)
+    mass = mask.astype(np.float32)
+    return Calibration(dem, mask, mass, 10.0, particles_per_cell, step_limit, 0.22, 1800.0, 0.26, 1400.0, 1.0, seed)

@@ -1,0 +1,174 @@
+"""GPU parity of the smooth forward (avl_trajectories_smooth) and the adjoint (avl_trajectories_backward).
+
+Bar: deposit and velocity rasters (int64 fixed point) and step statistics bit-exact against the FP32
+oracle; per-particle adjoint terms (dL/dmu, dL/dxi, dL/dh, sum gD w) bit-exact against the FP32 oracle's
+reverse sweep (same binary32 operations in the same order); the parameter gradient within 1e-9 relative
+of the oracle's (both sum in binary64, in different orders); dL/dmass equal to the oracle's rounded to
+float. The calibration workload's gradient is compared with the FP64 oracle gradient and with central
+differences of the FP64 forward (the 1e-3 bar; the FP32-vs-FP64 difference is stated).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+INF = float("inf")
+
+
+@pytest.fixture(scope="module")
+def avl():
+    import paper_2506_23364_amd as m
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return m
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def case(seed=5, size=96):
+    dem = synth.alpine_dem(size, 700.0, seed=seed)
+    sl = synth.slope_deg(dem, 10.0)
+    mask = ((sl >= 28) & (sl <= 45) & (dem >= np.quantile(dem, 0.6))).astype(np.uint8)
+    mass = np.random.default_rng(seed).uniform(0.5, 1.5, dem.shape).astype(np.float32)
+    gD = np.random.default_rng(seed + 1).standard_normal(dem.shape).astype(np.float32)
+    return dem, mask, mass, gD
+
+
+def run_both(avl, dem, mask, mass, gD, params, P, S, seed, run_id=0, vel=True, label=""):
+    p_o = oracle.make_params(**params)
+    ref = oracle.smooth_forward(dem, mask, 10.0, p_o, P, S, seed, run_id, mass=mass, vel_splat=vel)
+    p = avl.Params.make(**params)
+    m_t = dev(mass) if mass is not None else None
+    run = avl.trajectories_smooth(dev(dem), dev(mask), 10.0, p, P, S, seed, run_id, mass=m_t, velocity=vel)
+    assert host(run.status)[0] == 0
+    assert np.array_equal(host(run.deposit_q), ref.dep_q), label
+    assert np.array_equal(host(run.deposit), (ref.dep_q * 2.0 ** -24).astype(np.float32)), label
+    if vel:
+        assert np.array_equal(host(run.velocity_q), ref.vel_q), label
+    assert list(host(run.stats)) == [ref.steps, ref.n_exit, ref.n_stop, ref.n_limit], label
+    g_ref = oracle.smooth_backward(dem, mask, 10.0, p_o, P, S, seed, gD, run_id, mass=mass)
+    dparams, dmass, pp = avl.trajectories_backward(run, dev(dem), dev(mask), 10.0, p, P, S, seed, dev(gD), run_id,
+                                                   mass=m_t, per_particle=True)
+    n = g_ref.per_particle.shape[0]
+    pp = host(pp)[:, :n].T
+    assert np.array_equal(pp, g_ref.per_particle), f"{label}: per-particle adjoint terms differ"
+    dp = host(dparams)
+    for got, want in zip(dp, (g_ref.dmu, g_ref.dxi, g_ref.dh)):
+        assert abs(got - want) <= 1e-9 * max(1e-30, np.abs(g_ref.per_particle).sum()), label
+    assert np.array_equal(host(dmass), g_ref.dmass.astype(np.float32)), label
+    return run, ref, dp
+
+
+def test_smooth_forward_and_adjoint_bitexact(avl):
+    dem, mask, mass, gD = case()
+    run_both(avl, dem, mask, mass, gD, dict(mu=0.22, xi=1800.0, flow_height=1.3, randomness=0.16), 6, 1500, 3,
+             label="calib-like")
+
+
+@pytest.mark.parametrize("name,params,P,S", [
+    ("no_drag", dict(mu=0.15, xi=INF, randomness=0.2), 4, 800),
+    ("angle_stop", dict(mu=0.05, xi=1500.0, tan_alpha=0.4), 4, 800),
+    ("half_step", dict(mu=0.2, xi=2500.0, step_cells=0.5, randomness=0.3), 3, 900),
+    ("long_limit_cut", dict(mu=0.02, xi=INF, randomness=0.1), 3, 70),     # step limit mid-path, 2 segments
+    ("one_step", dict(mu=0.2, xi=2000.0), 5, 1),
+    ("no_steps", dict(mu=0.2, xi=2000.0), 2, 0),
+    ("multi_segment", dict(mu=0.01, xi=INF, randomness=0.05, persistence=0.95), 2, 400),
+])
+def test_smooth_cases(avl, name, params, P, S):
+    dem, mask, mass, gD = case(seed=8, size=80)
+    run_both(avl, dem, mask, mass, gD, dict(synth.DEFAULT_PARAMS, **params), P, S, 11, 2, label=name)
+
+
+def test_smooth_unit_mass_empty_and_capacity(avl):
+    dem, mask, mass, gD = case(seed=9, size=64)
+    p = dict(synth.DEFAULT_PARAMS, mu=0.2)
+    run_both(avl, dem, mask, None, gD, p, 3, 500, 1, vel=False, label="unit mass")
+    empty = np.zeros_like(mask)
+    run = avl.trajectories_smooth(dev(dem), dev(empty), 10.0, avl.Params.make(**p), 3, 500, 1)
+    assert host(run.deposit_q).sum() == 0 and list(host(run.stats)) == [0, 0, 0, 0]
+    # a capacity below the mask's release cells: nothing is released and the status says why
+    run = avl.trajectories_smooth(dev(dem), dev(mask), 10.0, avl.Params.make(**p), 3, 500, 1,
+                                  max_release_cells=int(mask.sum()) - 1)
+    assert host(run.status)[0] == 3 and host(run.deposit_q).sum() == 0
+
+
+def test_autograd_function(avl):
+    dem, mask, mass, _ = case(seed=12)
+    d, m = dev(dem), dev(mask)
+    P, S, seed = 5, 1200, 7
+    target = avl.smooth_deposit(torch.tensor(0.22), torch.tensor(1800.0), torch.tensor(1.0), dev(mass), d, m, 10.0, P,
+                                S, seed).detach()
+    mu = torch.tensor(0.26, requires_grad=True)
+    xi = torch.tensor(1400.0, requires_grad=True)
+    h = torch.tensor(1.0, requires_grad=True)
+    mass_t = dev(mass).requires_grad_(True)
+    dep = avl.smooth_deposit(mu, xi, h, mass_t, d, m, 10.0, P, S, seed)
+    loss = ((dep - target) ** 2).mean()
+    loss.backward()
+    gD = (2.0 * (dep.detach() - target) / dep.numel()).float()
+    g_ref = oracle.smooth_backward(dem, mask, 10.0, oracle.make_params(mu=0.26, xi=1400.0, flow_height=1.0), P, S,
+                                   seed, host(gD), mass=mass)
+    scale = np.abs(g_ref.per_particle).sum(axis=0)
+    assert abs(mu.grad.item() - g_ref.dmu) <= 1e-6 * scale[0] + 1e-12
+    assert abs(xi.grad.item() - g_ref.dxi) <= 1e-6 * scale[1] + 1e-12
+    assert abs(h.grad.item() - g_ref.dh) <= 1e-6 * scale[2] + 1e-12
+    assert np.array_equal(host(mass_t.grad), g_ref.dmass.astype(np.float32))
+
+
+def test_calibration_gradient_vs_fp64_and_finite_differences(avl):
+    """The calibration workload (1024^2, 5000 release cells; 16 particles per cell here to keep the FP64
+    oracle short): the gradient of L = sum gD * D with gD = dMSE/dD at (mu0, xi0).
+
+    The deposit is piecewise smooth in (mu, xi): a particle that barely reaches a bump crest with v^2 -> 0
+    may restart downhill, so L jumps where such a particle's end changes. Central differences therefore
+    use steps of 4 binary32 ulps and are taken per particle, over the particles whose end (reason, steps
+    completed) is the same on both sides (all of them here). The FP64 adjoint must match them to 1e-3;
+    the GPU's FP32 gradient must match the FP64 adjoint to 1e-3 of the sum of |per-particle terms|
+    (a few FP32 paths diverge from FP64 at texel-edge crossings)."""
+    c = synth.make_calibration(particles_per_cell=16)
+    d, m, mass = dev(c.dem), dev(c.mask), dev(c.mass)
+    P, S, seed = c.particles_per_cell, c.step_limit, c.seed
+    target = avl.smooth_deposit(torch.tensor(c.mu_star), torch.tensor(c.xi_star), torch.tensor(1.0), mass, d, m,
+                                c.cell_size, P, S, seed).detach()
+    p0 = dict(mu=c.mu0, xi=c.xi0, flow_height=1.0)
+    run = avl.trajectories_smooth(d, m, c.cell_size, avl.Params.make(**p0), P, S, seed, mass=mass)
+    gD = (2.0 * (run.deposit - target) / run.deposit.numel()).float()
+    dparams, _, pp = avl.trajectories_backward(run, d, m, c.cell_size, avl.Params.make(**p0), P, S, seed, gD,
+                                               mass=mass, per_particle=True)
+    g_gpu = host(dparams)
+    gD_np = host(gD)
+    g64 = oracle.smooth_backward(c.dem, c.mask, c.cell_size, oracle.make_params(**p0), P, S, seed, gD_np,
+                                 mass=c.mass, prec="f64")
+    g32 = oracle.smooth_backward(c.dem, c.mask, c.cell_size, oracle.make_params(**p0), P, S, seed, gD_np,
+                                 mass=c.mass, prec="f32")
+    n = g32.per_particle.shape[0]
+    assert np.array_equal(host(pp)[:, :n].T, g32.per_particle)       # GPU == FP32 oracle, bit for bit
+    for i, name in enumerate(("mu", "xi")):
+        v = np.float32(p0[name])
+        hi, lo = v, v
+        for _ in range(4):
+            hi = np.nextafter(hi, np.float32(np.inf))
+            lo = np.nextafter(lo, np.float32(-np.inf))
+        Lh, rh, sh = oracle.smooth_particles(c.dem, c.mask, c.cell_size, oracle.make_params(**dict(p0, **{name: float(hi)})),
+                                             P, S, seed, gD_np, mass=c.mass)
+        Ll, rl, sl = oracle.smooth_particles(c.dem, c.mask, c.cell_size, oracle.make_params(**dict(p0, **{name: float(lo)})),
+                                             P, S, seed, gD_np, mass=c.mass)
+        same = (rh == rl) & (sh == sl)
+        assert same.mean() > 0.999
+        fd = (Lh - Ll) / (float(hi) - float(lo))
+        adj = g64.per_particle[:, i]
+        assert abs(fd[same].sum() - adj[same].sum()) <= 1e-3 * abs(fd[same].sum()), (name, fd[same].sum(), adj[same].sum())
+        scale = np.abs(adj).sum()
+        assert abs(g_gpu[i] - (g64.dmu, g64.dxi)[i]) <= 1e-3 * scale, (name, g_gpu[i], (g64.dmu, g64.dxi)[i], scale)

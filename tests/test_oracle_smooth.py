@@ -146,24 +146,32 @@ def _loss(dem, mask, mass, gD, P, **kw):
 
 @pytest.mark.parametrize("name", ["mu", "xi", "flow_height"])
 def test_adjoint_matches_central_differences(name):
+    """Central differences of the binary64 forward with steps of a few binary32 ulps (parameters are
+    binary32 at the boundary), per particle, over the particles whose end (reason, steps completed) is
+    the same on both sides: the loss is piecewise smooth (a particle that barely reaches a crest may
+    restart downhill), and the adjoint is the derivative of the smooth pieces."""
     dem, mask, mass, gD, P = _calib_case()
     base = dict(mu=0.22, xi=1800.0, flow_height=1.3, randomness=0.16)
     g = oracle.smooth_backward(dem, mask, 10.0, oracle.make_params(**base), P, 1500, 3, gD, mass=mass, prec="f64")
-    adj = {"mu": g.dmu, "xi": g.dxi, "flow_height": g.dh}[name]
-    # parameters are binary32 at the boundary: step by whole float32 ulps around the value
-    v = np.float32(base[name])
-    best = None
-    for ulps in (64, 256, 1024):
-        hi = np.float32(v)
-        lo = np.float32(v)
+    col = {"mu": 0, "xi": 1, "flow_height": 2}[name]
+    for ulps in (4, 16):
+        v = np.float32(base[name])
+        hi, lo = v, v
         for _ in range(ulps):
             hi = np.nextafter(hi, np.float32(np.inf))
             lo = np.nextafter(lo, np.float32(-np.inf))
-        fd = (_loss(dem, mask, mass, gD, P, **dict(base, **{name: float(hi)}))
-              - _loss(dem, mask, mass, gD, P, **dict(base, **{name: float(lo)}))) / (float(hi) - float(lo))
-        err = abs(fd - adj) / abs(adj)
-        best = err if best is None else min(best, err)
-    assert best < 1e-3, (name, adj, best)
+        Lh, rh, sh = oracle.smooth_particles(dem, mask, 10.0, oracle.make_params(**dict(base, **{name: float(hi)})), P,
+                                             1500, 3, gD, mass=mass)
+        Ll, rl, sl = oracle.smooth_particles(dem, mask, 10.0, oracle.make_params(**dict(base, **{name: float(lo)})), P,
+                                             1500, 3, gD, mass=mass)
+        same = (rh == rl) & (sh == sl)
+        assert same.mean() > 0.99
+        fd = (Lh - Ll) / (float(hi) - float(lo))
+        adj = g.per_particle[:, col]
+        assert abs(fd[same].sum() - adj[same].sum()) <= 1e-3 * abs(adj[same].sum()), (name, ulps)
+        # particle by particle, too
+        big = same & (np.abs(adj) > 1e-6 * np.abs(adj).max())
+        assert np.allclose(fd[big], adj[big], rtol=1e-3, atol=1e-6 * np.abs(adj).max())
 
 
 def test_mass_gradient_is_exact_linear_response():
