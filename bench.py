@@ -35,6 +35,36 @@ ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # DEM gather (2x2 texels, 16 B) and the two 4-byte atomics per step; HBM3E peak 8 TB/s
 BYTES_PER_STEP = 24
 HBM_PEAK_GBS = 8000.0
+# HBM traffic of the trajectory kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE runs, recorded with the
+# hash of the kernel sources it was measured on; reported only while the sources are unchanged.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_trajectories_alpine_traffic.md")
+KERNEL_SOURCES = ["paper_2506_23364_amd/csrc/trajectories.hip", "paper_2506_23364_amd/csrc/particle.h",
+                  "paper_2506_23364_amd/csrc/avl_internal.h"]
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic():
+    """(bytes per launch, source hash) from the committed counter summary, or None."""
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    vals = {}
+    for line in text.splitlines():
+        if line.startswith("traffic_bytes_per_launch:") or line.startswith("source_sha256:"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if "traffic_bytes_per_launch" not in vals or vals.get("source_sha256") != kernel_source_hash():
+        return None
+    return float(vals["traffic_bytes_per_launch"])
 
 
 def parse():
@@ -47,6 +77,8 @@ def parse():
     ap.add_argument("--cpu-stride", type=int, default=0, help="oracle sample: every n-th release cell (0 = auto)")
     ap.add_argument("--no-batched", action="store_true", help="skip the ensemble (batched vs plain) leg")
     ap.add_argument("--no-gradient", action="store_true", help="skip the calibration-gradient leg")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="copy 256 MiB once first: a plain copy of known size that calibrates HBM byte counters")
     return ap.parse_args()
 
 
@@ -182,6 +214,12 @@ def main() -> int:
         print(json.dumps({"error": "no GPU visible"}))
         return 1
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        src = torch.ones(256 << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     w = synth.make_workload(args.workload)
     h, wd = w.dem.shape
     dem = torch.from_numpy(w.dem).cuda()
@@ -271,7 +309,7 @@ def main() -> int:
             "peak": ALU_PEAK_TOPS,
             "unit": "TFLOP/s",
             "frac": achieved_tops / ALU_PEAK_TOPS,
-            "traffic": None,
+            "traffic": recorded_traffic() if args.workload == "alpine" else None,
             "ops_per_particle_step": OPS_PER_STEP,
             "hbm_view": {"bytes_per_particle_step": BYTES_PER_STEP,
                          "achieved_GBs": BYTES_PER_STEP * steps_per_pass / traj_s / 1e9,
