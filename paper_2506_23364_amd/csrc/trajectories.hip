@@ -7,20 +7,23 @@
 // Design for gfx950 (measured choices; the alternatives are recorded in the design notes):
 //  - One persistent grid sized to the chip's occupancy; one lane carries one particle at a time and its
 //    whole state stays in VGPRs. A lane whose particle ended takes the next particle slot in the same
-//    iteration, from a per-wave reservoir refilled 64 slots at a time from a device-wide counter.
+//    iteration, from a per-wave reservoir refilled 64 slots at a time.
 //  - Slots are ordered replica-major within a release cell and run-major across runs; every run starts
-//    at a multiple of 64, so a 64-slot chunk belongs to one run. The 64 lanes of a wave mostly carry
-//    replicas of one release cell: their 2x2 DEM gathers hit the same L2 lines, and their paths enter
-//    the same cells.
-//  - The slot range is split into one partition per XCD; a wave starts on its own XCD's partition and
-//    moves on to the others only when it is empty. Each XCD's L2 then holds its own band of the DEM and
-//    rasters (or its own runs) instead of all eight caching the same band.
-//  - Hit counts and per-cell max v^2 go first into a wave-private direct-mapped table in LDS (tag,
-//    count, max), flushed to the rasters every kFlush iterations. Replicas on overlapping paths then
-//    cost one global atomic per cell and flush period instead of one per entry. A cell whose slot is
-//    held by another cell goes straight to the global raster.
-//  - A single run accumulates into private per-XCD rasters (merged after the kernel), so no two XCDs
-//    update one line; a batch writes each run's own rasters, which the XCD partition already separates.
+//    at a multiple of 64, so a 64-slot chunk belongs to one run. Release cells are in row-major order,
+//    so consecutive slots start at the same or neighbouring cells and their paths share most cells.
+//  - Device-scope atomics on the rasters are performed beyond L2 (at the memory side), so they are the
+//    cost to cut. Entry counts and per-cell max v^2 go first into a table in LDS shared by the whole
+//    workgroup (tag, count, max; linear probing), flushed to the rasters at epoch boundaries (a pair of
+//    barriers every kFlush iterations). A cell whose probes are all held by other cells goes straight to
+//    the raster.
+//  - The waves of a workgroup share a window of consecutive slots (two ranges of 2 x kBlock slots, topped
+//    up at epoch boundaries), so the table sees the paths of neighbouring release cells together. A wave
+//    that runs the window dry mid-epoch takes 64-slot chunks from the queues directly.
+//  - The slot range is split into one partition per XCD; windows and chunks come from the XCD's own
+//    partition first and from the others only when it is empty. Each XCD's L2 then holds its own band
+//    of the DEM (or its own runs).
+//  - A single run accumulates into private per-XCD rasters (merged after the kernel); a batch writes
+//    each run's own rasters.
 //  - Accumulation is integer only (u32 add; u32 max on the bits of v^2 >= 0, whose order is the value
 //    order), so every raster is independent of scheduling and of the kernel variant: bit-reproducible.
 //  - Philox4x32-10 gives four words per block; one block serves two consecutive steps.
@@ -30,21 +33,13 @@ namespace avl {
 
 namespace {
 
-constexpr int kTbl = 256;          // table slots per wave (power of two)
+constexpr int kProbes = 4;  // linear probes per table lookup
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;
 using dev::kChunk;
-
-__device__ __forceinline__ uint32_t slot_of(uint32_t key) {
-    return (key * 0x9E3779B1u) >> (32 - 8);  // kTbl = 2^8
-}
-static_assert(kTbl == 256, "slot_of assumes 256 slots");
 
 // LDS table accesses are relaxed atomics: lanes of the wave update slots concurrently.
 __device__ __forceinline__ uint32_t lds_ld(uint32_t* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-__device__ __forceinline__ void lds_st(uint32_t* p, uint32_t v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 // Max into a global raster cell. v^2 only grows, so a stale read that is already >= v proves the
@@ -57,15 +52,31 @@ __device__ __forceinline__ void global_max(uint32_t* __restrict__ p, uint32_t bi
 
 using namespace dev;
 
-template <bool kBatch, int kBlock, int kFlush>
-__global__ __launch_bounds__(kBlock) void k_trajectories(TrajArgs a) {
-    constexpr int kWaves = kBlock / kWave;
-    __shared__ uint32_t s_tag[kWaves][kTbl], s_cnt[kWaves][kTbl], s_vmx[kWaves][kTbl];
+// Workgroup-shared accumulation table: kTbl slots of (cell key, entry count, max v^2 bits) in LDS,
+// open addressing with kProbes linear probes. Cleared at every epoch boundary after its flush.
+template <int kTbl>
+struct Table {
+    static_assert((kTbl & (kTbl - 1)) == 0, "table size must be a power of two");
+    uint32_t tag[kTbl], cnt[kTbl], vmx[kTbl];
+};
+
+// Workgroup control block in LDS. The window is a range of consecutive slots that the workgroup's waves
+// share; it changes only between the barriers of an epoch boundary.
+struct Control {
+    unsigned long long base[2];   // the window: two ranges of consecutive slots, taken in order
+    uint32_t len[2];              // their lengths (multiples of 64)
+    uint32_t take;                // window slots handed out this epoch (grows by 64 per take)
+    uint32_t busy[2];             // waves with work left, per epoch parity
+    uint32_t part, tried, empty;  // the window's own walk over the XCD partitions
+};
+
+template <bool kBatch, int kBlock, int kFlush, int kTbl>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((!kBatch || kBlock >= 1024) ? 8 : 1)))
+void k_trajectories(TrajArgs a) {
+    constexpr uint32_t kSuper = 2u * kBlock;  // slots per window refill
+    __shared__ Table<kTbl> tb;
+    __shared__ Control ctl;
     const int lane = threadIdx.x & (kWave - 1);
-    const int wv = threadIdx.x / kWave;
-    uint32_t* const tag = s_tag[wv];
-    uint32_t* const cnt = s_cnt[wv];
-    uint32_t* const vmx = s_vmx[wv];
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
     const uint64_t total = wave_bcast64(a.run_off[a.n_runs]);
     const int W = a.W, H = a.H;
@@ -74,35 +85,81 @@ __global__ __launch_bounds__(kBlock) void k_trajectories(TrajArgs a) {
     uint32_t* const counts = a.counts + (size_t)xcd * a.xcd_stride;
     uint32_t* const vmax2 = a.vmax2 + (size_t)xcd * a.xcd_stride;
 
-    for (int k = lane; k < kTbl; k += kWave) {
-        lds_st(tag + k, kEmpty);
-        lds_st(cnt + k, 0u);
-        lds_st(vmx + k, 0u);
+    for (int k = threadIdx.x; k < kTbl; k += kBlock) {
+        tb.tag[k] = kEmpty;
+        tb.cnt[k] = 0u;
+        tb.vmx[k] = 0u;
     }
 
-    // table slot of `key`, claimed if empty; -1 if the slot belongs to another cell
-    auto claim = [&](uint32_t key) -> int {
-        const uint32_t sl = slot_of(key);
-        uint32_t t = lds_ld(tag + sl);
-        if (t == kEmpty) {
-            const uint32_t old = atomicCAS(tag + sl, kEmpty, key);
-            t = (old == kEmpty) ? key : old;
-        }
-        return t == key ? (int)sl : -1;
-    };
-    auto flush = [&]() {
-        for (int k = lane; k < kTbl; k += kWave) {
-            const uint32_t t = lds_ld(tag + k);
-            if (t != kEmpty) {
-                const uint32_t c = lds_ld(cnt + k), v = lds_ld(vmx + k);
-                if (c) atomicAdd(counts + t, c);
-                if (v) global_max(vmax2 + t, v);
-                lds_st(cnt + k, 0u);
-                lds_st(vmx + k, 0u);
-                lds_st(tag + k, kEmpty);
+    // Takes up to `len` consecutive slots from the XCD queues, starting with this XCD's partition and
+    // moving on when it is empty; [base, end) is empty once every partition is. Single lane.
+    auto take_global = [&](uint32_t& part, uint32_t& tried, uint32_t& empty, uint32_t len, uint64_t& base,
+                           uint64_t& end) {
+        base = end = 0;
+        while (!empty) {
+            const uint64_t pb = part_begin(total, part), pe = part_begin(total, part + 1);
+            const uint64_t got = atomicAdd(a.queues + part, (unsigned long long)len);
+            if (pb + got < pe) {
+                base = pb + got;
+                end = (base + len < pe) ? base + len : pe;
+                return;
             }
+            part = (part + 1) % kXcds;
+            if (++tried >= (uint32_t)kXcds) empty = 1u;
         }
     };
+
+    // table slot of `key`, claimed if a probe finds an empty slot first; -1 if every probe is held by
+    // another cell. Slots are only filled within an epoch, so a key's first probe that is empty or
+    // holds it is the same for every lane.
+    auto claim = [&](uint32_t key) -> int {
+        const uint32_t h = (key * 0x9E3779B1u) >> (32 - __builtin_ctz(kTbl));
+#pragma unroll
+        for (int q = 0; q < kProbes; ++q) {
+            const uint32_t sl = (h + (uint32_t)q) & (uint32_t)(kTbl - 1);
+            uint32_t t = lds_ld(tb.tag + sl);
+            if (t == kEmpty) {
+                const uint32_t old = atomicCAS(tb.tag + sl, kEmpty, key);
+                t = (old == kEmpty) ? key : old;
+            }
+            if (t == key) return (int)sl;
+        }
+        return -1;
+    };
+
+    // Shifts the window past the slots handed out in the epoch that ended and tops it up with a new
+    // range when the second range has been reached. Thread 0, between the barriers of a boundary.
+    auto refill_window = [&](bool first) {
+        if (first) {
+            ctl.base[0] = ctl.base[1] = 0;
+            ctl.len[0] = ctl.len[1] = 0;
+            ctl.take = 0;
+            ctl.busy[0] = ctl.busy[1] = 0;
+            ctl.part = xcd;
+            ctl.tried = 0;
+            ctl.empty = total == 0 ? 1u : 0u;
+        }
+        const uint32_t l0 = ctl.len[0], l1 = ctl.len[1];
+        const uint32_t t = min(ctl.take, l0 + l1);
+        if (t >= l0) {
+            ctl.base[0] = ctl.base[1] + (t - l0);
+            ctl.len[0] = l1 - (t - l0);
+            ctl.base[1] = 0;
+            ctl.len[1] = 0;
+        } else {
+            ctl.base[0] += t;
+            ctl.len[0] = l0 - t;
+        }
+        ctl.take = 0;
+        if (ctl.len[1] == 0u) {
+            uint64_t wb = 0, we = 0;
+            take_global(ctl.part, ctl.tried, ctl.empty, kSuper, wb, we);
+            ctl.base[1] = wb;
+            ctl.len[1] = (uint32_t)(we - wb);
+        }
+    };
+    if (threadIdx.x == 0) refill_window(true);
+    __syncthreads();
 
     // constants of the run a lane works on: uniform for a single run, per lane in a batch
     RunConst rc = uniform_run(a.runs[0]);
@@ -141,11 +198,9 @@ __global__ __launch_bounds__(kBlock) void k_trajectories(TrajArgs a) {
         }
     };
 
-    // wave-uniform queue state: partition being drained, partitions found empty, slot reservoir and
-    // the run its slots belong to
-    uint32_t part = xcd;
-    uint32_t tried = 0;
-    bool queue_empty = (total == 0);
+    // wave-uniform slot state: this wave's own walk over the XCD partitions (once the window is spent),
+    // and a reservoir of up to 64 slots with the run they belong to
+    uint32_t part = xcd, tried = 0, queue_empty = (total == 0) ? 1u : 0u;
     uint64_t res_next = 0, res_end = 0;
     uint32_t res_run = 0;
 
@@ -153,220 +208,256 @@ __global__ __launch_bounds__(kBlock) void k_trajectories(TrajArgs a) {
     bool alive = false;
     float x = 0, y = 0, z = 0, gx = 0, gy = 0, dx = 0, dy = 0, v2 = 0, x0 = 0, y0 = 0, zr = 0, cmax2 = 0;
     uint32_t n = 0, rep = 0, cell_id = 0, spare_x = 0, spare_y = 0, cur = 0;
-    int my_slot = -1;  // table slot of the current cell, -1 if none
+    int my_slot = -1;  // table slot of the current cell in this epoch, -1 if none
 
-    for (uint32_t iter = 1;; ++iter) {
-        const uint64_t idle = __ballot(!alive);
-        const int nidle = __popcll(idle);
-        const bool drained = queue_empty && res_next >= res_end;
-        if (nidle == kWave && drained) break;
-        if (iter % kFlush == 0) {
-            flush();
-            my_slot = -1;
-        }
+    auto count_entry = [&](bool e) {
+        if (!e) return;
+        my_slot = claim(cur);
+        if (my_slot >= 0)
+            atomicAdd(tb.cnt + my_slot, 1u);
+        else
+            atomicAdd(counts + cur, 1u);
+    };
 
-        // ---- hand slots to idle lanes in lane order: reservoir first, then a new chunk
-        bool fresh = false;
-        if (nidle > 0 && !drained) {
-            const uint64_t avail = res_end - res_next;
-            const int rank = __popcll(idle & below);
-            uint64_t slot = ~0ull;
-            uint32_t srun = res_run;
-            if (avail >= (uint64_t)nidle) {
-                slot = res_next + rank;
-                res_next += nidle;
-            } else {
-                uint64_t base = 0, cend = 0;
-                const int leader = __ffsll((long long)idle) - 1;
-                while (!queue_empty) {
-                    const uint64_t pb = part_begin(total, part), pe = part_begin(total, part + 1);
-                    uint64_t got = 0;
-                    if (lane == leader) got = atomicAdd(a.queues + part, (unsigned long long)kChunk);
-                    got = wave_bcast64(__shfl(got, leader, kWave));
-                    if (pb + got < pe) {
-                        base = pb + got;
-                        cend = (base + kChunk < pe) ? base + kChunk : pe;
-                        break;
-                    }
-                    part = (part + 1) % kXcds;
-                    if (++tried >= (uint32_t)kXcds) queue_empty = true;
-                }
-                const uint32_t new_run = (kBatch && cend > base) ? find_run(a.run_off, a.n_runs, base) : 0u;
-                if ((uint64_t)rank < avail) {
+    for (uint32_t epoch = 0;; ++epoch) {
+        // the window of this epoch
+        const uint64_t wb0 = wave_bcast64(ctl.base[0]), wb1 = wave_bcast64(ctl.base[1]);
+        const uint32_t wl0 = uniform_u(ctl.len[0]), wl1 = uniform_u(ctl.len[1]);
+        bool win_out = wl0 + wl1 == 0u;
+        bool finished = false;
+
+        for (int it = 0; it < kFlush; ++it) {
+            const uint64_t idle = __ballot(!alive);
+            const int nidle = __popcll(idle);
+            const bool drained = win_out && queue_empty && res_next >= res_end;
+            if (nidle == kWave && drained) {
+                finished = true;
+                break;
+            }
+
+            // ---- hand slots to idle lanes in lane order: reservoir, then the window, then the queues
+            bool fresh = false;
+            if (nidle > 0 && !drained) {
+                const uint64_t avail = res_end - res_next;
+                const int rank = __popcll(idle & below);
+                uint64_t slot = ~0ull;
+                uint32_t srun = res_run;
+                if (avail >= (uint64_t)nidle) {
                     slot = res_next + rank;
-                } else if (base + (rank - avail) < cend) {
-                    slot = base + (rank - avail);
-                    srun = new_run;
+                    res_next += nidle;
+                } else {
+                    uint64_t base = 0, cend = 0;
+                    const int leader = __ffsll((long long)idle) - 1;
+                    if (!win_out) {
+                        uint32_t v = 0;
+                        if (lane == leader) v = atomicAdd(&ctl.take, kChunk);
+                        v = __builtin_amdgcn_readlane(v, leader);
+                        // the ranges are multiples of 64 long, so a chunk never straddles them
+                        if (v < wl0) {
+                            base = wb0 + v;
+                            cend = base + min(wl0 - v, kChunk);
+                        } else if (v - wl0 < wl1) {
+                            base = wb1 + (v - wl0);
+                            cend = base + min(wl1 - (v - wl0), kChunk);
+                        } else {
+                            win_out = true;
+                        }
+                    }
+                    if (cend == base && !queue_empty) {
+                        uint64_t gb = 0, ge = 0;
+                        if (lane == leader) take_global(part, tried, queue_empty, kChunk, gb, ge);
+                        base = wave_bcast64(__shfl(gb, leader, kWave));
+                        cend = wave_bcast64(__shfl(ge, leader, kWave));
+                        queue_empty = __builtin_amdgcn_readlane(queue_empty, leader);
+                        part = __builtin_amdgcn_readlane(part, leader);
+                        tried = __builtin_amdgcn_readlane(tried, leader);
+                    }
+                    const uint32_t new_run = (kBatch && cend > base) ? find_run(a.run_off, a.n_runs, base) : 0u;
+                    if ((uint64_t)rank < avail) {
+                        slot = res_next + rank;
+                    } else if (base + (rank - avail) < cend) {
+                        slot = base + (rank - avail);
+                        srun = new_run;
+                    }
+                    const uint64_t next = base + ((uint64_t)nidle - avail);
+                    res_next = next < cend ? next : cend;
+                    res_end = cend;
+                    res_run = new_run;
                 }
-                const uint64_t next = base + ((uint64_t)nidle - avail);
-                res_next = next < cend ? next : cend;
-                res_end = cend;
-                res_run = new_run;
-            }
-            if (!alive && slot < total) {
-                const uint64_t local = kBatch ? slot - a.run_off[srun] : slot;
-                const uint64_t n_slots = kBatch ? a.runs[srun].n_slots : rc.n_slots;
-                const uint32_t P = kBatch ? a.runs[srun].P : rc.P;
-                const uint32_t cells_off = kBatch ? a.runs[srun].cells_off : rc.cells_off;
-                if (local < n_slots) {  // past n_slots: padding up to the next multiple of 64
-                    const uint64_t i = local / P;
-                    rep = (uint32_t)(local - i * P);
-                    cell_id = (uint32_t)a.cells[cells_off + i];
-                    fresh = true;
+                if (!alive && slot < total) {
+                    const uint64_t local = kBatch ? slot - a.run_off[srun] : slot;
+                    const uint64_t n_slots = kBatch ? a.runs[srun].n_slots : rc.n_slots;
+                    const uint32_t P = kBatch ? a.runs[srun].P : rc.P;
+                    const uint32_t cells_off = kBatch ? a.runs[srun].cells_off : rc.cells_off;
+                    if (local < n_slots) {  // past n_slots: padding up to the next multiple of 64
+                        const uint64_t i = local / P;
+                        rep = (uint32_t)(local - i * P);
+                        cell_id = (uint32_t)a.cells[cells_off + i];
+                        fresh = true;
+                    }
                 }
-            }
-            if (kBatch) {
-                // a lane's statistics belong to the run of its previous particle
-                flush_stats(fresh && srun != b);
+                if (kBatch) {
+                    // a lane's statistics belong to the run of its previous particle
+                    flush_stats(fresh && srun != b);
+                    if (fresh) {
+                        b = srun;
+                        rc = a.runs[b];
+                    }
+                }
                 if (fresh) {
-                    b = srun;
-                    rc = a.runs[b];
+                    const float* dem = a.dem + rc.dem_off;
+                    const int r = (int)(cell_id / (uint32_t)W);
+                    const int c = (int)(cell_id - (uint32_t)r * (uint32_t)W);
+                    x = (float)c + 0.5f;
+                    y = (float)r + 0.5f;
+                    const Sample s0 = bilinear(dem, H, W, x, y);
+                    z = s0.z;
+                    gx = s0.gx;
+                    gy = s0.gy;
+                    x0 = x;
+                    y0 = y;
+                    zr = z;
+                    const float gg = gx * gx + gy * gy;
+                    if (gg > 0.0f) {
+                        const float t = 1.0f / sqrtf(gg);
+                        dx = -(gx * t);
+                        dy = -(gy * t);
+                    } else {
+                        dx = 0.0f;
+                        dy = 0.0f;
+                    }
+                    v2 = 0.0f;
+                    cmax2 = 0.0f;
+                    n = 0;
+                    cur = rc.raster_off + cell_id;
+                    alive = true;
                 }
             }
-            if (fresh) {
-                const float* dem = a.dem + rc.dem_off;
-                const int r = (int)(cell_id / (uint32_t)W);
-                const int c = (int)(cell_id - (uint32_t)r * (uint32_t)W);
-                x = (float)c + 0.5f;
-                y = (float)r + 0.5f;
-                const Sample s0 = bilinear(dem, H, W, x, y);
-                z = s0.z;
-                gx = s0.gx;
-                gy = s0.gy;
-                x0 = x;
-                y0 = y;
-                zr = z;
-                const float gg = gx * gx + gy * gy;
-                if (gg > 0.0f) {
-                    const float t = 1.0f / sqrtf(gg);
-                    dx = -(gx * t);
-                    dy = -(gy * t);
-                } else {
-                    dx = 0.0f;
-                    dy = 0.0f;
-                }
-                v2 = 0.0f;
-                cmax2 = 0.0f;
-                n = 0;
-                cur = rc.raster_off + cell_id;
-                alive = true;
-            }
-        }
-        if (fresh) {  // entry into the release cell
-            my_slot = claim(cur);
-            if (my_slot >= 0)
-                atomicAdd(cnt + my_slot, 1u);
-            else
-                atomicAdd(counts + cur, 1u);
-        }
+            count_entry(fresh);  // entry into the release cell
 
-        // ---- one step of every live particle
-        bool leave = false, entered = false;
-        uint32_t leave_bits = 0;
-        int leave_slot = -1;
-        uint32_t leave_key = 0;
-        if (alive) {
-            bool ended = false;
-            if (n >= a.S) {
-                ++st_limit;
-                ended = true;
-            } else {
-                ++st_steps;
-                uint32_t ux, uy;
-                if ((n & 1u) == 0u) {
-                    const uint4 o = philox4x32_10(n >> 1, rep, cell_id, rc.run, rc.key0, rc.key1);
-                    ux = o.x;
-                    uy = o.y;
-                    spare_x = o.z;
-                    spare_y = o.w;
-                } else {
-                    ux = spare_x;
-                    uy = spare_y;
-                }
-                const float rx = signed_unit(ux), ry = signed_unit(uy);
-                const float gg = gx * gx + gy * gy;
-                const float t = gg > 0.0f ? rc.Q / sqrtf(gg) : 0.0f;
-                const float wx = (rc.per * dx - t * gx) + rc.rnd * rx;
-                const float wy = (rc.per * dy - t * gy) + rc.rnd * ry;
-                const float ww = wx * wx + wy * wy;
-                if (ww > 0.0f) {
-                    const float inv = 1.0f / sqrtf(ww);
-                    dx = wx * inv;
-                    dy = wy * inv;
-                }
-                const float x1 = x + rc.L * dx;
-                const float y1 = y + rc.L * dy;
-                const float fc1 = floorf(x1), fr1 = floorf(y1);
-                if (!(fc1 >= 0.0f && fc1 < fW && fr1 >= 0.0f && fr1 < fH)) {
-                    ++st_exit;
+            // ---- one step of every live particle
+            bool leave = false, entered = false;
+            uint32_t leave_bits = 0;
+            int leave_slot = -1;
+            uint32_t leave_key = 0;
+            if (alive) {
+                bool ended = false;
+                if (n >= a.S) {
+                    ++st_limit;
                     ended = true;
                 } else {
-                    const Sample s1 = bilinear(a.dem + rc.dem_off, H, W, x1, y1);
-                    const float dz = z - s1.z;
-                    const float ds = sqrtf(rc.dl2 + dz * dz);
-                    const float num = v2 + a.g2 * (dz - rc.mdl);
-                    bool stop = !(num > 0.0f);
-                    float v2n = 0.0f;
-                    if (!stop) {
-                        v2n = num / (1.0f + rc.cd * ds);
-                        if (rc.use_alpha) {
-                            const float hx = x1 - x0, hy = y1 - y0;
-                            stop = (zr - s1.z) < rc.tca * sqrtf(hx * hx + hy * hy);
-                        }
+                    ++st_steps;
+                    uint32_t ux, uy;
+                    if ((n & 1u) == 0u) {
+                        const uint4 o = philox4x32_10(n >> 1, rep, cell_id, rc.run, rc.key0, rc.key1);
+                        ux = o.x;
+                        uy = o.y;
+                        spare_x = o.z;
+                        spare_y = o.w;
+                    } else {
+                        ux = spare_x;
+                        uy = spare_y;
                     }
-                    if (stop) {
-                        ++st_stop;
+                    const float rx = signed_unit(ux), ry = signed_unit(uy);
+                    const float gg = gx * gx + gy * gy;
+                    const float t = gg > 0.0f ? rc.Q / sqrtf(gg) : 0.0f;
+                    const float wx = (rc.per * dx - t * gx) + rc.rnd * rx;
+                    const float wy = (rc.per * dy - t * gy) + rc.rnd * ry;
+                    const float ww = wx * wx + wy * wy;
+                    if (ww > 0.0f) {
+                        const float inv = 1.0f / sqrtf(ww);
+                        dx = wx * inv;
+                        dy = wy * inv;
+                    }
+                    const float x1 = x + rc.L * dx;
+                    const float y1 = y + rc.L * dy;
+                    const float fc1 = floorf(x1), fr1 = floorf(y1);
+                    if (!(fc1 >= 0.0f && fc1 < fW && fr1 >= 0.0f && fr1 < fH)) {
+                        ++st_exit;
                         ended = true;
                     } else {
-                        x = x1;
-                        y = y1;
-                        z = s1.z;
-                        gx = s1.gx;
-                        gy = s1.gy;
-                        v2 = v2n;
-                        ++n;
-                        const uint32_t nc =
-                            rc.raster_off + (uint32_t)(int)fr1 * (uint32_t)W + (uint32_t)(int)fc1;
-                        if (nc != cur) {
-                            leave = cmax2 > 0.0f;
-                            leave_bits = __float_as_uint(cmax2);
-                            leave_slot = my_slot;
-                            leave_key = cur;
-                            cur = nc;
-                            cmax2 = v2;
-                            entered = true;
-                        } else if (v2 > cmax2) {
-                            cmax2 = v2;
+                        const Sample s1 = bilinear(a.dem + rc.dem_off, H, W, x1, y1);
+                        const float dz = z - s1.z;
+                        const float ds = sqrtf(rc.dl2 + dz * dz);
+                        const float num = v2 + a.g2 * (dz - rc.mdl);
+                        bool stop = !(num > 0.0f);
+                        float v2n = 0.0f;
+                        if (!stop) {
+                            v2n = num / (1.0f + rc.cd * ds);
+                            if (rc.use_alpha) {
+                                const float hx = x1 - x0, hy = y1 - y0;
+                                stop = (zr - s1.z) < rc.tca * sqrtf(hx * hx + hy * hy);
+                            }
+                        }
+                        if (stop) {
+                            ++st_stop;
+                            ended = true;
+                        } else {
+                            x = x1;
+                            y = y1;
+                            z = s1.z;
+                            gx = s1.gx;
+                            gy = s1.gy;
+                            v2 = v2n;
+                            ++n;
+                            const uint32_t nc =
+                                rc.raster_off + (uint32_t)(int)fr1 * (uint32_t)W + (uint32_t)(int)fc1;
+                            if (nc != cur) {
+                                leave = cmax2 > 0.0f;
+                                leave_bits = __float_as_uint(cmax2);
+                                leave_slot = my_slot;
+                                leave_key = cur;
+                                cur = nc;
+                                cmax2 = v2;
+                                entered = true;
+                            } else if (v2 > cmax2) {
+                                cmax2 = v2;
+                            }
                         }
                     }
                 }
+                if (ended) {
+                    leave = cmax2 > 0.0f;
+                    leave_bits = __float_as_uint(cmax2);
+                    leave_slot = my_slot;
+                    leave_key = cur;
+                    alive = false;
+                }
             }
-            if (ended) {
-                leave = cmax2 > 0.0f;
-                leave_bits = __float_as_uint(cmax2);
-                leave_slot = my_slot;
-                leave_key = cur;
-                alive = false;
+            // ---- accumulate: max of the cell left, entry count of the cell entered
+            if (leave) {
+                int sl = leave_slot;
+                if (sl < 0) sl = claim(leave_key);
+                if (sl >= 0)
+                    atomicMax(tb.vmx + sl, leave_bits);
+                else
+                    global_max(vmax2 + leave_key, leave_bits);
+            }
+            count_entry(entered);
+        }
+
+        // ---- epoch boundary: count the waves with work left, flush the table, refill the window
+        if (lane == 0 && !finished) atomicAdd(&ctl.busy[epoch & 1u], 1u);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            ctl.busy[(epoch + 1) & 1u] = 0u;
+            refill_window(false);
+        }
+        for (int k = threadIdx.x; k < kTbl; k += kBlock) {
+            const uint32_t t = tb.tag[k];
+            if (t != kEmpty) {
+                const uint32_t c = tb.cnt[k], v = tb.vmx[k];
+                if (c) atomicAdd(counts + t, c);
+                if (v) global_max(vmax2 + t, v);
+                tb.cnt[k] = 0u;
+                tb.vmx[k] = 0u;
+                tb.tag[k] = kEmpty;
             }
         }
-        // ---- accumulate: max of the cell left, entry count of the cell entered
-        if (leave) {
-            int sl = leave_slot;
-            if (sl < 0) sl = claim(leave_key);
-            if (sl >= 0)
-                atomicMax(vmx + sl, leave_bits);
-            else
-                global_max(vmax2 + leave_key, leave_bits);
-        }
-        if (entered) {
-            my_slot = claim(cur);
-            if (my_slot >= 0)
-                atomicAdd(cnt + my_slot, 1u);
-            else
-                atomicAdd(counts + cur, 1u);
-        }
+        my_slot = -1;
+        __syncthreads();
+        if (ctl.busy[epoch & 1u] == 0u) break;
     }
-    flush();
     flush_stats(st_steps != 0 || st_exit != 0 || st_stop != 0 || st_limit != 0);
 }
 
@@ -479,22 +570,22 @@ struct Variant {
     void (*launch_batch)(dim3, dim3, hipStream_t, const TrajArgs&);
 };
 
-template <bool B, int Blk, int F>
+template <bool B, int Blk, int F, int T>
 void launch_t(dim3 g, dim3 t, hipStream_t s, const TrajArgs& a) {
-    hipLaunchKernelGGL((k_trajectories<B, Blk, F>), g, t, 0, s, a);
+    hipLaunchKernelGGL((k_trajectories<B, Blk, F, T>), g, t, 0, s, a);
 }
 
-template <int Blk, int F>
+template <int Blk, int F, int T>
 constexpr Variant make_variant() {
-    return Variant{reinterpret_cast<const void*>(&k_trajectories<false, Blk, F>),
-                   reinterpret_cast<const void*>(&k_trajectories<true, Blk, F>), Blk, &launch_t<false, Blk, F>,
-                   &launch_t<true, Blk, F>};
+    return Variant{reinterpret_cast<const void*>(&k_trajectories<false, Blk, F, T>),
+                   reinterpret_cast<const void*>(&k_trajectories<true, Blk, F, T>), Blk, &launch_t<false, Blk, F, T>,
+                   &launch_t<true, Blk, F, T>};
 }
 
-// candidates of the autotuner: (threads per block, iterations between table flushes)
+// candidates of the autotuner: (threads per block, iterations per epoch, table slots per block)
 const Variant kVariants[] = {
-    make_variant<256, 16>(), make_variant<256, 8>(), make_variant<256, 32>(), make_variant<128, 16>(),
-    make_variant<512, 16>(),
+    make_variant<1024, 16, 4096>(), make_variant<1024, 32, 4096>(), make_variant<512, 16, 2048>(),
+    make_variant<512, 32, 2048>(), make_variant<256, 8, 1024>(),
 };
 
 }  // namespace
