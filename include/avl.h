@@ -98,7 +98,8 @@ AVL_API int avl_release_cells(const uint8_t* mask, int32_t H, int32_t W, int32_t
  *   per particle). vmax: H*W float, the maximum speed (m/s) reached in each texel (0 if none).
  * stats (nullable): 4 uint64 on the device: {steps, particles that left the grid, that stopped, that
  *   reached step_limit}; "steps" counts every step entered, the terminating one included.
- * particles_per_cell >= 1; dem, mask, counts, vmax as above; H, W >= 1; H*W < 2^31;
+ * particles_per_cell >= 1; dem, mask, counts, vmax as above; H, W >= 1; (H + 2) (W + 2) < 2^30 (the
+ * kernel reads a copy of the DEM with a one-texel border through 32-bit byte offsets);
  * workspace: avl_workspace_bytes(H, W) bytes of device memory, owned by the caller, not retained. */
 AVL_API int avl_trajectories(const float* dem, const uint8_t* mask, int32_t H, int32_t W, float cell_size,
                      const avl_params* params, uint32_t particles_per_cell, uint32_t step_limit, uint64_t seed,

@@ -13,12 +13,15 @@
 
 namespace avl {
 
-size_t workspace_bytes(int64_t n) {
+size_t workspace_bytes(int64_t H, int64_t W) {
+    const int64_t n = H * W;
     return kControl + round256((size_t)scan_blocks(n) * sizeof(uint32_t)) + round256((size_t)n * sizeof(int32_t)) +
-           2 * round256((size_t)kXcds * n * sizeof(uint32_t));
+           2 * round256((size_t)kXcds * n * sizeof(uint32_t)) + round256((size_t)n * sizeof(StartRec)) +
+           round256((size_t)padded_cells(H, W) * sizeof(float));
 }
 
-Workspace carve(void* base, int64_t n) {
+Workspace carve(void* base, int64_t H, int64_t W) {
+    const int64_t n = H * W;
     char* p = static_cast<char*>(base);
     Workspace w{};
     w.n_cells = reinterpret_cast<int32_t*>(p);
@@ -34,6 +37,10 @@ Workspace carve(void* base, int64_t n) {
     w.priv_counts = reinterpret_cast<uint32_t*>(p);
     p += round256((size_t)kXcds * n * sizeof(uint32_t));
     w.priv_vmax2 = reinterpret_cast<uint32_t*>(p);
+    p += round256((size_t)kXcds * n * sizeof(uint32_t));
+    w.starts = reinterpret_cast<StartRec*>(p);
+    p += round256((size_t)n * sizeof(StartRec));
+    w.dem_pad = reinterpret_cast<float*>(p);
     return w;
 }
 
@@ -270,7 +277,7 @@ int32_t avl_last_variant(void) { return g_last_variant; }
 
 size_t avl_workspace_bytes(int32_t H, int32_t W) {
     if (H < 1 || W < 1) return 0;
-    return avl::workspace_bytes((int64_t)H * W);
+    return avl::workspace_bytes(H, W);
 }
 
 size_t avl_batched_workspace_bytes(int32_t H, int32_t W, int32_t n_masks, int32_t n_runs) {
@@ -312,8 +319,8 @@ int avl_release_cells(const uint8_t* mask, int32_t H, int32_t W, int32_t* cells,
     if (!mask || !cells || !n_cells || !workspace) return fail(AVL_EINVAL, "avl_release_cells: null pointer");
     if (!grid_ok(H, W, 1)) return fail(AVL_EINVAL, "avl_release_cells: need H, W >= 1 and H*W < 2^31");
     const int64_t n = (int64_t)H * W;
-    if (workspace_bytes < avl::workspace_bytes(n)) return fail(AVL_ENOMEM, "avl_release_cells: workspace too small");
-    avl::Workspace ws = avl::carve(workspace, n);
+    if (workspace_bytes < avl::workspace_bytes(H, W)) return fail(AVL_ENOMEM, "avl_release_cells: workspace too small");
+    avl::Workspace ws = avl::carve(workspace, H, W);
     hipError_t e = avl::launch_compact(mask, n, cells, n_cells, ws.blk, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? AVL_OK : hip_fail(e, "avl_release_cells");
 }
@@ -324,14 +331,15 @@ int avl_trajectories(const float* dem, const uint8_t* mask, int32_t H, int32_t W
                      size_t workspace_bytes, void* stream) {
     g_last_error.clear();
     if (!dem || !mask || !counts || !vmax || !workspace) return fail(AVL_EINVAL, "avl_trajectories: null pointer");
-    if (!grid_ok(H, W, 1)) return fail(AVL_EINVAL, "avl_trajectories: need H, W >= 1 and H*W < 2^31");
+    if (!grid_ok(H, W, 1) || avl::padded_cells(H, W) >= (int64_t(1) << 30))
+        return fail(AVL_EINVAL, "avl_trajectories: need H, W >= 1 and (H + 2)(W + 2) < 2^30");
     if (!finite(cell_size) || !(cell_size > 0.0f)) return fail(AVL_EINVAL, "avl_trajectories: cell_size must be > 0");
     if (particles_per_cell == 0) return fail(AVL_EINVAL, "avl_trajectories: particles_per_cell must be >= 1");
     if (const char* why = check_params(params)) return fail(AVL_EINVAL, "avl_trajectories: %s", why);
     const int64_t n = (int64_t)H * W;
-    if (workspace_bytes < avl::workspace_bytes(n)) return fail(AVL_ENOMEM, "avl_trajectories: workspace too small");
+    if (workspace_bytes < avl::workspace_bytes(H, W)) return fail(AVL_ENOMEM, "avl_trajectories: workspace too small");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    avl::Workspace ws = avl::carve(workspace, n);
+    avl::Workspace ws = avl::carve(workspace, H, W);
 
     avl::TrajArgs a{};
     a.dem = dem;
@@ -348,6 +356,10 @@ int avl_trajectories(const float* dem, const uint8_t* mask, int32_t H, int32_t W
     a.S = step_limit;
     a.g2 = 9.81f + 9.81f;
     a.xcd_stride = (uint32_t)n;
+    a.starts = ws.starts;
+    a.pdiv = avl::make_divu32(particles_per_cell);
+    a.dem_pad = ws.dem_pad;
+    a.pad_bytes = (uint32_t)(avl::padded_cells(H, W) * sizeof(float));
 
     // the private rasters (counts then v^2 bits) are one contiguous region
     const int64_t priv_words = (int64_t)(ws.priv_vmax2 - ws.priv_counts) + avl::kXcds * n;
@@ -360,6 +372,10 @@ int avl_trajectories(const float* dem, const uint8_t* mask, int32_t H, int32_t W
     hipError_t e;
     if ((e = avl::launch_compact(mask, n, ws.cells, ws.n_cells, ws.blk, s)) != hipSuccess)
         return hip_fail(e, "avl_trajectories: compaction");
+    if ((e = avl::launch_start_records(dem, H, W, ws.cells, ws.n_cells, n, ws.starts, s)) != hipSuccess)
+        return hip_fail(e, "avl_trajectories: start records");
+    if ((e = avl::launch_pad_dem(dem, H, W, ws.dem_pad, s)) != hipSuccess)
+        return hip_fail(e, "avl_trajectories: padded DEM");
     const avl::RunSpec spec{0u, 0u, 0u, run_id, (unsigned long long)seed};
     if ((e = avl::launch_setup_runs(nullptr, nullptr, 0, spec, *params, ws.n_cells, 1, 1, 1, H, W, cell_size,
                                     particles_per_cell, false, ws.runs, ws.run_off, nullptr, s)) != hipSuccess)
@@ -549,6 +565,8 @@ int avl_trajectories_batched(const float* dems, int32_t n_tiles, const uint8_t* 
     a.S = step_limit;
     a.g2 = 9.81f + 9.81f;
     a.xcd_stride = 0;
+    a.starts = nullptr;
+    a.pdiv = avl::make_divu32(particles_per_cell);
     const int64_t raster = (int64_t)n_runs * n;
 
     auto zero = [&]() -> hipError_t {

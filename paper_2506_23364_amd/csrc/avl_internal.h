@@ -17,7 +17,9 @@ constexpr int kWave = 64;
 //   [0, 512)     control block: n_cells (i32 @0), stats (4 x u64 @64), per-XCD slot queues (kXcds x u64
 //                @128), run offsets (2 x u64 @192), the run's constants (RunConst @256)
 //   then         per-block sums of the compaction scan (u32), the release-cell list (i32, H*W), and the
-//                per-XCD private rasters: kXcds count rasters, then kXcds v^2-bit rasters (u32, H*W each)
+//                per-XCD private rasters: kXcds count rasters, then kXcds v^2-bit rasters (u32, H*W each),
+//                then the start records of the release cells (StartRec, H*W), then the padded DEM (f32,
+//                (H + 2) x (W + 2))
 // Batch (avl_batched_workspace_bytes):
 //   [0, 512)     control block: per-XCD slot queues @128
 //   then         compaction scan sums; n_masks release-cell lists (i32, H*W each); n_masks cell counts;
@@ -33,6 +35,7 @@ inline size_t round256(size_t v) { return (v + 255) & ~size_t(255); }
 inline int64_t scan_blocks(int64_t n) { return (n + kScanChunk - 1) / kScanChunk; }
 
 struct RunConst;
+struct StartRec;
 
 struct Workspace {
     int32_t* n_cells;             // single: 1; batch: n_masks
@@ -44,10 +47,14 @@ struct Workspace {
     int32_t* cells;               // single: H*W; batch: n_masks x H*W
     uint32_t* priv_counts;        // single only: kXcds x H*W
     uint32_t* priv_vmax2;         // single only: kXcds x H*W
+    StartRec* starts;             // single only: H*W
+    float* dem_pad;               // single only: (H + 2) x (W + 2)
 };
 
-size_t workspace_bytes(int64_t n);
-Workspace carve(void* base, int64_t n);
+// cells of the DEM with a one-texel border
+inline int64_t padded_cells(int64_t H, int64_t W) { return (H + 2) * (W + 2); }
+size_t workspace_bytes(int64_t H, int64_t W);
+Workspace carve(void* base, int64_t H, int64_t W);
 size_t batched_workspace_bytes(int64_t n, int64_t n_masks, int64_t n_runs);
 Workspace carve_batched(void* base, int64_t n, int64_t n_masks, int64_t n_runs);
 
@@ -68,6 +75,29 @@ struct RunConst {
 };
 static_assert(sizeof(RunConst) == 80, "RunConst layout");
 
+// Start state of the particles released at one cell (the cell centre, its bilinear sample and the
+// downslope unit direction), computed once per release cell for a single run.
+struct StartRec {
+    float x, y, z, gx, gy, dx, dy;
+    uint32_t cell;
+};
+static_assert(sizeof(StartRec) == 32, "StartRec layout");
+
+// Unsigned 32-bit division by an invariant d >= 1 (Granlund and Montgomery, PLDI 1994, section 4):
+// q = (t + ((n - t) >> sh1)) >> sh2 with t = mulhi(mul, n), exact for every 32-bit n.
+struct DivU32 {
+    uint32_t mul, sh1, sh2;
+};
+inline DivU32 make_divu32(uint32_t d) {
+    uint32_t l = 0;
+    while (l < 32 && (uint64_t(1) << l) < d) ++l;  // l = ceil(log2 d)
+    DivU32 v;
+    v.mul = (uint32_t)(((uint64_t(1) << 32) * ((uint64_t(1) << l) - d)) / d + 1);
+    v.sh1 = l < 1 ? l : 1;
+    v.sh2 = l > 1 ? l - 1 : 0;
+    return v;
+}
+
 struct TrajArgs {
     const float* __restrict__ dem;               // all DEM tiles, H*W each
     const int32_t* __restrict__ cells;           // all release-cell lists, H*W each
@@ -83,6 +113,10 @@ struct TrajArgs {
     uint32_t S;                                  // step limit
     float g2;                                    // 2g
     uint32_t xcd_stride;  // single run: elements between the per-XCD private rasters; batched: 0
+    const StartRec* __restrict__ starts;         // single run: one per release cell; batched: NULL
+    DivU32 pdiv;                                 // division by the particles per cell (same for every run)
+    const float* __restrict__ dem_pad;           // single run: the DEM with a replicated border; batched: NULL
+    uint32_t pad_bytes;                          // (H + 2) (W + 2) x 4 < 2^32
 };
 
 struct LaunchShape {
@@ -99,6 +133,11 @@ hipError_t launch_compact(const uint8_t* mask, int64_t n, int32_t* cells, int32_
                           hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t n, hipStream_t s);
+// (H + 2) x (W + 2) copy of the DEM with the edge texels replicated into a one-texel border.
+hipError_t launch_pad_dem(const float* dem, int H, int W, float* out, hipStream_t s);
+// starts[i] for each of the *n_cells release cells (capacity n).
+hipError_t launch_start_records(const float* dem, int H, int W, const int32_t* cells, const int32_t* n_cells,
+                                int64_t n, StartRec* starts, hipStream_t s);
 hipError_t launch_merge_rasters(const uint32_t* priv_counts, const uint32_t* priv_vmax2, int64_t n, uint32_t* counts,
                                 float* vmax, hipStream_t s);
 // Setup of the run table: per run, constants from its parameter set and the slot count from its

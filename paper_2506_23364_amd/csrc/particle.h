@@ -58,6 +58,36 @@ __device__ __forceinline__ Sample bilinear(const float* __restrict__ dem, int H,
     return s;
 }
 
+// The same patch read from the DEM with a one-texel replicated border (row length Wp = W + 2 texels,
+// row_bytes = 4 Wp) through a buffer resource: for (x, y) inside the grid the corner (floor(x - 1/2),
+// floor(y - 1/2)) lies in [-1, W - 1] x [-1, H - 1], i.e. inside the padded grid, and the border holds
+// exactly the clamped texels, so the four values and the arithmetic are those of bilinear().
+__device__ __forceinline__ Sample bilinear_pad(__amdgpu_buffer_rsrc_t rs, uint32_t Wp, uint32_t row_bytes, float x,
+                                               float y) {
+    const float sx = x - 0.5f, sy = y - 0.5f;
+    const float fc = floorf(sx), fr = floorf(sy);
+    const float fx = sx - fc, fy = sy - fr;
+    const uint32_t off = (__umul24((uint32_t)((int)fr + 1), Wp) + (uint32_t)((int)fc + 1)) * 4u;
+    // two 8-byte loads (the raw words of a, b and of c, d), both issued before either is used
+    const auto ab = __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0);
+    const auto cd = __builtin_amdgcn_raw_buffer_load_b64(rs, off, row_bytes, 0);
+    __builtin_amdgcn_sched_barrier(0);  // keep both loads ahead of their uses (one memory latency, not two)
+    const float a = __uint_as_float(ab[0]), b = __uint_as_float(ab[1]);
+    const float c = __uint_as_float(cd[0]), d = __uint_as_float(cd[1]);
+    const float top = a + fx * (b - a);
+    const float bot = c + fx * (d - c);
+    Sample s;
+    s.z = top + fy * (bot - top);
+    s.gx = (b - a) + fy * ((d - c) - (b - a));
+    s.gy = bot - top;
+    return s;
+}
+
+// buffer resource over `bytes` bytes at p (gfx9 descriptor word 3: 32-bit data format)
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void* p, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+
 // Corners and fractions of the bilinear patch (or splat) at (x, y), indices clamped to the grid.
 struct Corners {
     int ca, cb, ra, rb;
@@ -75,6 +105,36 @@ __device__ __forceinline__ Corners corners(int H, int W, float x, float y) {
     k.ra = min(max(r0, 0), H - 1);
     k.rb = min(max(r0 + 1, 0), H - 1);
     return k;
+}
+
+// Start state at the centre of release cell `cell`: position, bilinear sample and the unit direction of
+// steepest descent (zero on flat ground).
+__device__ __forceinline__ StartRec start_state(const float* __restrict__ dem, int H, int W, uint32_t cell) {
+    StartRec st;
+    const int r = (int)(cell / (uint32_t)W);
+    const int c = (int)(cell - (uint32_t)r * (uint32_t)W);
+    st.x = (float)c + 0.5f;
+    st.y = (float)r + 0.5f;
+    const Sample s0 = bilinear(dem, H, W, st.x, st.y);
+    st.z = s0.z;
+    st.gx = s0.gx;
+    st.gy = s0.gy;
+    const float gg = s0.gx * s0.gx + s0.gy * s0.gy;
+    if (gg > 0.0f) {
+        const float t = 1.0f / sqrtf(gg);
+        st.dx = -(s0.gx * t);
+        st.dy = -(s0.gy * t);
+    } else {
+        st.dx = 0.0f;
+        st.dy = 0.0f;
+    }
+    st.cell = cell;
+    return st;
+}
+
+__device__ __forceinline__ uint32_t udiv(uint32_t n, const DivU32& d) {
+    const uint32_t t = __umulhi(d.mul, n);
+    return (t + ((n - t) >> d.sh1)) >> d.sh2;
 }
 
 __device__ __forceinline__ uint64_t wave_bcast64(uint64_t v) {

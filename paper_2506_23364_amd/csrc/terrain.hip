@@ -222,6 +222,20 @@ __global__ __launch_bounds__(256) void k_fill_u64(unsigned long long* __restrict
 }
 
 // Merge of the per-XCD private rasters of the trajectory pass into the caller's rasters:
+// DEM with a one-texel border replicating the edge texels: (H + 2) x (W + 2), row-major. Its texel
+// (r + 1, c + 1) holds dem[clamp(r)][clamp(c)] for r in [-1, H], c in [-1, W], which is what the clamped
+// bilinear patch reads, so the padded lookup needs no clamps.
+__global__ __launch_bounds__(256) void k_pad_dem(const float* __restrict__ dem, int H, int W,
+                                                 float* __restrict__ out) {
+    const int64_t Wp = (int64_t)W + 2, n = ((int64_t)H + 2) * Wp;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t rp = i / Wp, cp = i - rp * Wp;
+        const int64_t r = rp < 1 ? 0 : (rp > H ? H - 1 : rp - 1);
+        const int64_t c = cp < 1 ? 0 : (cp > W ? W - 1 : cp - 1);
+        out[i] = dem[r * W + c];
+    }
+}
+
 // counts = sum over XCDs, vmax = sqrt(max over XCDs of the v^2 bits). One cell per thread, each of the
 // 2 x kXcds reads coalesced across the wave.
 __global__ __launch_bounds__(256) void k_merge_rasters(const uint32_t* __restrict__ pc, const uint32_t* __restrict__ pv,
@@ -257,6 +271,13 @@ __global__ __launch_bounds__(256) void k_finalize_vmax(uint32_t* __restrict__ bi
 static unsigned blocks_for(int64_t items, int per_thread) {
     const int64_t threads = (items + per_thread - 1) / per_thread;
     return (unsigned)((threads + 255) / 256);
+}
+
+hipError_t launch_pad_dem(const float* dem, int H, int W, float* out, hipStream_t s) {
+    const int64_t n = ((int64_t)H + 2) * ((int64_t)W + 2);
+    const unsigned blocks = blocks_for(n, 4);
+    hipLaunchKernelGGL(k_pad_dem, dim3(blocks), dim3(256), 0, s, dem, H, W, out);
+    return hipGetLastError();
 }
 
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s) {

@@ -33,7 +33,6 @@ namespace avl {
 
 namespace {
 
-constexpr int kProbes = 4;  // linear probes per table lookup
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;
 using dev::kChunk;
 
@@ -53,7 +52,7 @@ __device__ __forceinline__ void global_max(uint32_t* __restrict__ p, uint32_t bi
 using namespace dev;
 
 // Workgroup-shared accumulation table: kTbl slots of (cell key, entry count, max v^2 bits) in LDS,
-// open addressing with kProbes linear probes. Cleared at every epoch boundary after its flush.
+// open addressing with a few linear probes. Cleared at every epoch boundary after its flush.
 template <int kTbl>
 struct Table {
     static_assert((kTbl & (kTbl - 1)) == 0, "table size must be a power of two");
@@ -70,10 +69,11 @@ struct Control {
     uint32_t part, tried, empty;  // the window's own walk over the XCD partitions
 };
 
-template <bool kBatch, int kBlock, int kFlush, int kTbl>
+template <bool kBatch, int kBlock, int kFlush, int kTbl, int kProbes, int kWindow>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((!kBatch || kBlock >= 1024) ? 8 : 1)))
 void k_trajectories(TrajArgs a) {
-    constexpr uint32_t kSuper = 2u * kBlock;  // slots per window refill
+    static_assert(kFlush % 2 == 0, "epochs keep the iteration parity");
+    constexpr uint32_t kSuper = (uint32_t)kWindow * kBlock;  // slots per window top-up
     __shared__ Table<kTbl> tb;
     __shared__ Control ctl;
     const int lane = threadIdx.x & (kWave - 1);
@@ -84,6 +84,9 @@ void k_trajectories(TrajArgs a) {
     const uint32_t xcd = xcd_id();
     uint32_t* const counts = a.counts + (size_t)xcd * a.xcd_stride;
     uint32_t* const vmax2 = a.vmax2 + (size_t)xcd * a.xcd_stride;
+    // single run: the padded DEM through a buffer resource (32-bit offsets, no clamps)
+    const __amdgpu_buffer_rsrc_t dem_rs = buffer_rsrc(a.dem_pad, a.pad_bytes);
+    const uint32_t Wp = (uint32_t)W + 2u, row_bytes = 4u * Wp;
 
     for (int k = threadIdx.x; k < kTbl; k += kBlock) {
         tb.tag[k] = kEmpty;
@@ -161,8 +164,8 @@ void k_trajectories(TrajArgs a) {
     if (threadIdx.x == 0) refill_window(true);
     __syncthreads();
 
-    // constants of the run a lane works on: uniform for a single run, per lane in a batch
-    RunConst rc = uniform_run(a.runs[0]);
+    // constants of a single run, in scalar registers (a batch reads them per lane, per iteration)
+    const RunConst rc = uniform_run(a.runs[0]);
     uint32_t b = 0;  // run index of the lane's particle (batched)
 
     // per-lane statistics of run b
@@ -235,9 +238,11 @@ void k_trajectories(TrajArgs a) {
                 break;
             }
 
-            // ---- hand slots to idle lanes in lane order: reservoir, then the window, then the queues
+            // ---- hand slots to idle lanes in lane order: reservoir, then the window, then the queues.
+            // Only on even iterations: every particle then starts on an even iteration, so its step
+            // parity is the iteration's and the Philox block (one per two steps) is a uniform branch.
             bool fresh = false;
-            if (nidle > 0 && !drained) {
+            if ((it & 1) == 0 && nidle > 0 && !drained) {
                 const uint64_t avail = res_end - res_next;
                 const int rank = __popcll(idle & below);
                 uint64_t slot = ~0ull;
@@ -284,58 +289,51 @@ void k_trajectories(TrajArgs a) {
                     res_end = cend;
                     res_run = new_run;
                 }
+                uint64_t i = 0;  // release-cell index of the new particle within its run
                 if (!alive && slot < total) {
                     const uint64_t local = kBatch ? slot - a.run_off[srun] : slot;
                     const uint64_t n_slots = kBatch ? a.runs[srun].n_slots : rc.n_slots;
                     const uint32_t P = kBatch ? a.runs[srun].P : rc.P;
-                    const uint32_t cells_off = kBatch ? a.runs[srun].cells_off : rc.cells_off;
                     if (local < n_slots) {  // past n_slots: padding up to the next multiple of 64
-                        const uint64_t i = local / P;
-                        rep = (uint32_t)(local - i * P);
-                        cell_id = (uint32_t)a.cells[cells_off + i];
+                        i = (local >> 32) == 0 ? (uint64_t)udiv((uint32_t)local, a.pdiv) : local / P;
+                        rep = (uint32_t)local - (uint32_t)i * P;
                         fresh = true;
                     }
                 }
                 if (kBatch) {
                     // a lane's statistics belong to the run of its previous particle
                     flush_stats(fresh && srun != b);
-                    if (fresh) {
-                        b = srun;
-                        rc = a.runs[b];
-                    }
+                    if (fresh) b = srun;
                 }
                 if (fresh) {
-                    const float* dem = a.dem + rc.dem_off;
-                    const int r = (int)(cell_id / (uint32_t)W);
-                    const int c = (int)(cell_id - (uint32_t)r * (uint32_t)W);
-                    x = (float)c + 0.5f;
-                    y = (float)r + 0.5f;
-                    const Sample s0 = bilinear(dem, H, W, x, y);
-                    z = s0.z;
-                    gx = s0.gx;
-                    gy = s0.gy;
+                    // a batch computes the start state per particle (its DEM tile varies by run); a single
+                    // run reads it from the per-cell records
+                    const StartRec st =
+                        kBatch ? start_state(a.dem + a.runs[b].dem_off, H, W, (uint32_t)a.cells[a.runs[b].cells_off + i])
+                               : a.starts[i];
+                    cell_id = st.cell;
+                    x = st.x;
+                    y = st.y;
+                    z = st.z;
+                    gx = st.gx;
+                    gy = st.gy;
+                    dx = st.dx;
+                    dy = st.dy;
                     x0 = x;
                     y0 = y;
                     zr = z;
-                    const float gg = gx * gx + gy * gy;
-                    if (gg > 0.0f) {
-                        const float t = 1.0f / sqrtf(gg);
-                        dx = -(gx * t);
-                        dy = -(gy * t);
-                    } else {
-                        dx = 0.0f;
-                        dy = 0.0f;
-                    }
                     v2 = 0.0f;
                     cmax2 = 0.0f;
                     n = 0;
-                    cur = rc.raster_off + cell_id;
+                    cur = (kBatch ? a.runs[b].raster_off : rc.raster_off) + cell_id;
                     alive = true;
                 }
             }
             count_entry(fresh);  // entry into the release cell
 
-            // ---- one step of every live particle
+            // ---- one step of every live particle. A batch reads its run's constants afresh each
+            // iteration (L1/L2 hits) rather than holding 16 more VGPRs per lane.
+            const RunConst R = kBatch ? a.runs[b] : rc;
             bool leave = false, entered = false;
             uint32_t leave_bits = 0;
             int leave_slot = -1;
@@ -348,8 +346,8 @@ void k_trajectories(TrajArgs a) {
                 } else {
                     ++st_steps;
                     uint32_t ux, uy;
-                    if ((n & 1u) == 0u) {
-                        const uint4 o = philox4x32_10(n >> 1, rep, cell_id, rc.run, rc.key0, rc.key1);
+                    if ((it & 1) == 0) {  // n is even
+                        const uint4 o = philox4x32_10(n >> 1, rep, cell_id, R.run, R.key0, R.key1);
                         ux = o.x;
                         uy = o.y;
                         spare_x = o.z;
@@ -360,33 +358,34 @@ void k_trajectories(TrajArgs a) {
                     }
                     const float rx = signed_unit(ux), ry = signed_unit(uy);
                     const float gg = gx * gx + gy * gy;
-                    const float t = gg > 0.0f ? rc.Q / sqrtf(gg) : 0.0f;
-                    const float wx = (rc.per * dx - t * gx) + rc.rnd * rx;
-                    const float wy = (rc.per * dy - t * gy) + rc.rnd * ry;
+                    const float t = gg > 0.0f ? R.Q / sqrtf(gg) : 0.0f;
+                    const float wx = (R.per * dx - t * gx) + R.rnd * rx;
+                    const float wy = (R.per * dy - t * gy) + R.rnd * ry;
                     const float ww = wx * wx + wy * wy;
                     if (ww > 0.0f) {
                         const float inv = 1.0f / sqrtf(ww);
                         dx = wx * inv;
                         dy = wy * inv;
                     }
-                    const float x1 = x + rc.L * dx;
-                    const float y1 = y + rc.L * dy;
+                    const float x1 = x + R.L * dx;
+                    const float y1 = y + R.L * dy;
                     const float fc1 = floorf(x1), fr1 = floorf(y1);
                     if (!(fc1 >= 0.0f && fc1 < fW && fr1 >= 0.0f && fr1 < fH)) {
                         ++st_exit;
                         ended = true;
                     } else {
-                        const Sample s1 = bilinear(a.dem + rc.dem_off, H, W, x1, y1);
+                        const Sample s1 = kBatch ? bilinear(a.dem + R.dem_off, H, W, x1, y1)
+                                                : bilinear_pad(dem_rs, Wp, row_bytes, x1, y1);
                         const float dz = z - s1.z;
-                        const float ds = sqrtf(rc.dl2 + dz * dz);
-                        const float num = v2 + a.g2 * (dz - rc.mdl);
+                        const float ds = sqrtf(R.dl2 + dz * dz);
+                        const float num = v2 + a.g2 * (dz - R.mdl);
                         bool stop = !(num > 0.0f);
                         float v2n = 0.0f;
                         if (!stop) {
-                            v2n = num / (1.0f + rc.cd * ds);
-                            if (rc.use_alpha) {
+                            v2n = num / (1.0f + R.cd * ds);
+                            if (R.use_alpha) {
                                 const float hx = x1 - x0, hy = y1 - y0;
-                                stop = (zr - s1.z) < rc.tca * sqrtf(hx * hx + hy * hy);
+                                stop = (zr - s1.z) < R.tca * sqrtf(hx * hx + hy * hy);
                             }
                         }
                         if (stop) {
@@ -401,7 +400,7 @@ void k_trajectories(TrajArgs a) {
                             v2 = v2n;
                             ++n;
                             const uint32_t nc =
-                                rc.raster_off + (uint32_t)(int)fr1 * (uint32_t)W + (uint32_t)(int)fc1;
+                                R.raster_off + (uint32_t)(int)fr1 * (uint32_t)W + (uint32_t)(int)fc1;
                             if (nc != cur) {
                                 leave = cmax2 > 0.0f;
                                 leave_bits = __float_as_uint(cmax2);
@@ -459,6 +458,25 @@ void k_trajectories(TrajArgs a) {
         if (ctl.busy[epoch & 1u] == 0u) break;
     }
     flush_stats(st_steps != 0 || st_exit != 0 || st_stop != 0 || st_limit != 0);
+}
+
+// ------------------------------------------------------------------------------------------ start records
+
+__global__ __launch_bounds__(256) void k_start_records(const float* __restrict__ dem, int H, int W,
+                                                       const int32_t* __restrict__ cells,
+                                                       const int32_t* __restrict__ n_cells,
+                                                       StartRec* __restrict__ starts) {
+    const int64_t n = *n_cells;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        starts[i] = start_state(dem, H, W, (uint32_t)cells[i]);
+}
+
+hipError_t launch_start_records(const float* dem, int H, int W, const int32_t* cells, const int32_t* n_cells,
+                                int64_t n, StartRec* starts, hipStream_t s) {
+    const int64_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(k_start_records, dim3((unsigned)(blocks < 4096 ? (blocks > 0 ? blocks : 1) : 4096)), dim3(256),
+                       0, s, dem, H, W, cells, n_cells, starts);
+    return hipGetLastError();
 }
 
 // ------------------------------------------------------------------------------------------ run table
@@ -570,22 +588,23 @@ struct Variant {
     void (*launch_batch)(dim3, dim3, hipStream_t, const TrajArgs&);
 };
 
-template <bool B, int Blk, int F, int T>
+template <bool B, int Blk, int F, int T, int Q, int M>
 void launch_t(dim3 g, dim3 t, hipStream_t s, const TrajArgs& a) {
-    hipLaunchKernelGGL((k_trajectories<B, Blk, F, T>), g, t, 0, s, a);
+    hipLaunchKernelGGL((k_trajectories<B, Blk, F, T, Q, M>), g, t, 0, s, a);
 }
 
-template <int Blk, int F, int T>
+template <int Blk, int F, int T, int Q, int M>
 constexpr Variant make_variant() {
-    return Variant{reinterpret_cast<const void*>(&k_trajectories<false, Blk, F, T>),
-                   reinterpret_cast<const void*>(&k_trajectories<true, Blk, F, T>), Blk, &launch_t<false, Blk, F, T>,
-                   &launch_t<true, Blk, F, T>};
+    return Variant{reinterpret_cast<const void*>(&k_trajectories<false, Blk, F, T, Q, M>),
+                   reinterpret_cast<const void*>(&k_trajectories<true, Blk, F, T, Q, M>), Blk,
+                   &launch_t<false, Blk, F, T, Q, M>, &launch_t<true, Blk, F, T, Q, M>};
 }
 
-// candidates of the autotuner: (threads per block, iterations per epoch, table slots per block)
+// candidates of the autotuner: (threads per block, iterations per epoch, table slots per block, probes,
+// window top-up in blocks of slots)
 const Variant kVariants[] = {
-    make_variant<1024, 16, 4096>(), make_variant<1024, 32, 4096>(), make_variant<512, 16, 2048>(),
-    make_variant<512, 32, 2048>(), make_variant<256, 8, 1024>(),
+    make_variant<1024, 32, 4096, 4, 4>(), make_variant<1024, 64, 4096, 8, 4>(), make_variant<1024, 32, 4096, 4, 2>(),
+    make_variant<1024, 16, 4096, 4, 4>(), make_variant<512, 32, 2048, 4, 4>(),
 };
 
 }  // namespace

@@ -187,6 +187,20 @@ def test_edge_cases(avl):
     assert not np.array_equal(g1[0], g2[0])
 
 
+@pytest.mark.parametrize("P", [2, 5, 63, 64, 65, 127, 4099])
+def test_particles_per_cell_sweep(avl, P):
+    """Slot decoding (release cell = slot / P, replica = slot mod P) for divisors around the 64-slot chunk
+    size and a large prime."""
+    dem = synth.alpine_dem(96, 700.0, seed=17)
+    nrm = oracle.normals(dem, 10.0)
+    mask = oracle.release_mask(nrm, dem, 28.0, 50.0, float(np.quantile(dem, 0.55)), INF)
+    if P > 1000:  # keep the oracle short: a handful of cells
+        sub = np.zeros(mask.size, np.uint8)
+        sub[np.flatnonzero(mask)[::40]] = 1
+        mask = sub.reshape(mask.shape)
+    both(avl, dem, mask, 10.0, dict(mu=0.2, xi=2000.0, randomness=0.3), P, 300, 77, 5, f"P={P}")
+
+
 def test_alpine_full_size_sampled(avl):
     """Full 2048^2 alpine tile at 256 particles per cell, in the launch shape the benchmark times: the
     oracle runs every 97th release cell; the GPU runs that sample, its complement and the whole mask."""
