@@ -51,20 +51,22 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def recorded_traffic():
-    """(bytes per launch, source hash) from the committed counter summary, or None."""
+def recorded_traffic(variant: int):
+    """Memory-side bytes per launch of kernel variant `variant` from the committed counter summary, or
+    None when the summary has no figure for it or was taken on other kernel sources."""
     try:
         text = open(TRAFFIC_FILE).read()
     except OSError:
         return None
     vals = {}
     for line in text.splitlines():
-        if line.startswith("traffic_bytes_per_launch:") or line.startswith("source_sha256:"):
+        if line.startswith("traffic_bytes_per_launch[") or line.startswith("source_sha256:"):
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
-    if "traffic_bytes_per_launch" not in vals or vals.get("source_sha256") != kernel_source_hash():
+    key = f"traffic_bytes_per_launch[{variant}]"
+    if key not in vals or vals.get("source_sha256") != kernel_source_hash():
         return None
-    return float(vals["traffic_bytes_per_launch"])
+    return float(vals[key])
 
 
 def parse():
@@ -73,6 +75,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="alpine", choices=["tiny", "alpine", "large"])
+    ap.add_argument("--variant", type=int, default=-1,
+                    help="trajectory kernel variant (default -1: the library's autotuner chooses)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-stride", type=int, default=0, help="oracle sample: every n-th release cell (0 = auto)")
     ap.add_argument("--no-batched", action="store_true", help="skip the ensemble (batched vs plain) leg")
@@ -214,6 +218,8 @@ def main() -> int:
         print(json.dumps({"error": "no GPU visible"}))
         return 1
     torch.cuda.set_device(0)
+    if args.variant >= 0:
+        avl.set_tuning(args.variant, True)
     if args.copy_probe:
         src = torch.ones(256 << 20, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)
@@ -250,7 +256,10 @@ def main() -> int:
     n_release = int(mask.sum().item())
     mask_np = mask.cpu().numpy()
 
-    t_terrain = t_traj = 0.0
+    # per-step timing: the terrain passes and the trajectory call with torch events on the stream, the
+    # trajectory kernel alone with the library's events around its launch on the same stream
+    t_terrain = t_traj = t_kernel = 0.0
+    avl.set_profiling(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -258,8 +267,11 @@ def main() -> int:
         ev[2].synchronize()
         t_terrain += ev[0].elapsed_time(ev[1])
         t_traj += ev[1].elapsed_time(ev[2])
+        t_kernel += avl.last_kernel_ms()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    avl.set_profiling(False)
+    variant = avl.last_variant()
     # a second loop without per-step syncs gives the throughput figure
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -270,8 +282,8 @@ def main() -> int:
     assert int(res.stats.cpu().numpy()[0]) == steps_per_pass, "particle-step count changed between passes"
 
     value = steps_per_pass * args.steps / elapsed
-    traj_s = t_traj / 1e3 / args.steps
-    achieved_tops = OPS_PER_STEP * steps_per_pass / traj_s / 1e12
+    kern_s = t_kernel / 1e3 / args.steps
+    achieved_tops = OPS_PER_STEP * steps_per_pass / kern_s / 1e12
     out = {
         "metric": "particle-steps/s forward + s per (mu,xi) gradient, batched vs plain, 1 MI355X",
         "value": value,
@@ -300,19 +312,21 @@ def main() -> int:
         "timing": {
             "ms_terrain_normals_mask": t_terrain / args.steps,
             "ms_trajectories_call": t_traj / args.steps,
+            "ms_trajectory_kernel": t_kernel / args.steps,
             "ms_per_step_synced": wall / args.steps * 1e3,
         },
         "roofline": {
             "bound": "alu",
             "kernel": "k_trajectories",
+            "variant": variant,
             "achieved": achieved_tops,
             "peak": ALU_PEAK_TOPS,
             "unit": "TFLOP/s",
             "frac": achieved_tops / ALU_PEAK_TOPS,
-            "traffic": recorded_traffic() if args.workload == "alpine" else None,
+            "traffic": recorded_traffic(variant) if args.workload == "alpine" else None,
             "ops_per_particle_step": OPS_PER_STEP,
             "hbm_view": {"bytes_per_particle_step": BYTES_PER_STEP,
-                         "achieved_GBs": BYTES_PER_STEP * steps_per_pass / traj_s / 1e9,
+                         "achieved_GBs": BYTES_PER_STEP * steps_per_pass / kern_s / 1e9,
                          "peak_GBs": HBM_PEAK_GBS},
         },
     }

@@ -185,6 +185,14 @@ AVL_API int32_t avl_tuning_variants(void);
 /* The variant the last trajectory call on this thread used. */
 AVL_API int32_t avl_last_variant(void);
 
+/* Kernel timing (diagnostics; not for concurrent callers). With enable = 1, every later uncaptured
+ * trajectory call (plain or batched) records a pair of HIP events on its stream around the trajectory
+ * kernel alone; avl_last_kernel_ms waits for the last such pair and writes the kernel's duration in
+ * milliseconds to *ms. Returns AVL_EINVAL if ms is NULL or no call was timed since profiling was
+ * enabled, AVL_EHIP on a HIP error. enable = 0 stops the timing (the events are kept). */
+AVL_API int avl_set_profiling(int32_t enable);
+AVL_API int avl_last_kernel_ms(float* ms);
+
 /* Name of an error code. Never NULL. */
 AVL_API const char* avl_strerror(int code);
 

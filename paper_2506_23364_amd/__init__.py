@@ -54,7 +54,8 @@ class Run(ctypes.Structure):
 
 def _load() -> ctypes.CDLL:
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2506_23364_amd.build`")
+        raise ImportError(f"{LIB_PATH} is not built; run `python paper_2506_23364_amd/build.py` or "
+                          "`python -c 'import __graft_entry__; __graft_entry__.build()'`")
     L = ctypes.CDLL(LIB_PATH)
     vp, i32, u32, u64, f32, sz = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32, ctypes.c_uint64,
                                   ctypes.c_float, ctypes.c_size_t)
@@ -65,6 +66,8 @@ def _load() -> ctypes.CDLL:
     L.avl_release_cells.argtypes = [vp, i32, i32, vp, vp, vp, sz, vp]
     L.avl_trajectories.argtypes = [vp, vp, i32, i32, f32, ctypes.POINTER(Params), u32, u32, u64, u32, vp, vp, vp,
                                    vp, sz, vp]
+    L.avl_set_profiling.argtypes = [i32]
+    L.avl_last_kernel_ms.argtypes = [ctypes.POINTER(ctypes.c_float)]
     L.avl_batched_workspace_bytes.argtypes = [i32, i32, i32, i32]
     L.avl_batched_workspace_bytes.restype = sz
     L.avl_trajectories_batched.argtypes = [vp, i32, vp, i32, i32, i32, f32, vp, i32, vp, i32, u32, u32, vp, vp, vp,
@@ -150,6 +153,18 @@ def tuning_variants() -> int:
 
 def last_variant() -> int:
     return int(lib.avl_last_variant())
+
+
+def set_profiling(enable: bool) -> None:
+    """Time the trajectory kernel of later calls with HIP events on their stream (diagnostics)."""
+    _check(lib.avl_set_profiling(1 if enable else 0), "avl_set_profiling")
+
+
+def last_kernel_ms() -> float:
+    """Duration of the trajectory kernel of the last timed call (waits for it)."""
+    ms = ctypes.c_float(0.0)
+    _check(lib.avl_last_kernel_ms(ctypes.byref(ms)), "avl_last_kernel_ms")
+    return float(ms.value)
 
 
 def normals(dem: torch.Tensor, cell_size: float) -> torch.Tensor:

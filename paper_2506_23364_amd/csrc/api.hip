@@ -16,7 +16,7 @@ namespace avl {
 size_t workspace_bytes(int64_t H, int64_t W) {
     const int64_t n = H * W;
     return kControl + round256((size_t)scan_blocks(n) * sizeof(uint32_t)) + round256((size_t)n * sizeof(int32_t)) +
-           2 * round256((size_t)kXcds * n * sizeof(uint32_t)) + round256((size_t)n * sizeof(StartRec)) +
+           round256((size_t)n * sizeof(StartRec)) +
            round256((size_t)padded_cells(H, W) * sizeof(float));
 }
 
@@ -34,10 +34,6 @@ Workspace carve(void* base, int64_t H, int64_t W) {
     p += round256((size_t)scan_blocks(n) * sizeof(uint32_t));
     w.cells = reinterpret_cast<int32_t*>(p);
     p += round256((size_t)n * sizeof(int32_t));
-    w.priv_counts = reinterpret_cast<uint32_t*>(p);
-    p += round256((size_t)kXcds * n * sizeof(uint32_t));
-    w.priv_vmax2 = reinterpret_cast<uint32_t*>(p);
-    p += round256((size_t)kXcds * n * sizeof(uint32_t));
     w.starts = reinterpret_cast<StartRec*>(p);
     p += round256((size_t)n * sizeof(StartRec));
     w.dem_pad = reinterpret_cast<float*>(p);
@@ -123,6 +119,26 @@ namespace {
 
 thread_local std::string g_last_error;
 thread_local int32_t g_last_variant = -1;
+
+// kernel timing (avl_set_profiling): events around the last uncaptured trajectory launch
+bool g_profile = false;
+bool g_profile_valid = false;
+hipEvent_t g_prof_ev[2] = {nullptr, nullptr};
+
+// Launches the trajectory kernel, bracketed by the timing events when profiling is on and the stream
+// is not being captured.
+hipError_t timed_launch(const avl::TrajArgs& a, bool batched, const avl::LaunchShape& sh, hipStream_t s) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    const bool timed = g_profile && hipStreamIsCapturing(s, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone;
+    hipError_t e;
+    if (timed && (e = hipEventRecord(g_prof_ev[0], s)) != hipSuccess) return e;
+    if ((e = avl::launch_trajectories(a, batched, sh, s)) != hipSuccess) return e;
+    if (timed) {
+        if ((e = hipEventRecord(g_prof_ev[1], s)) != hipSuccess) return e;
+        g_profile_valid = true;
+    }
+    return hipSuccess;
+}
 
 int fail(int code, const char* fmt, const char* detail = nullptr) {
     char buf[512];
@@ -213,22 +229,28 @@ hipError_t choose_variant(const avl::TrajArgs& a, bool batched, const std::vecto
         (void)hipEventDestroy(e0);
         return e;
     }
-    float best_ms = 1e30f;
-    int best = 0;
-    for (int v = 0; v < avl::trajectory_variants(); ++v) {
-        const avl::LaunchShape sh = avl::trajectory_shape(batched, v);
-        if ((e = zero()) != hipSuccess) break;
-        if ((e = hipEventRecord(e0, s)) != hipSuccess) break;
-        if ((e = avl::launch_trajectories(a, batched, sh, s)) != hipSuccess) break;
-        if ((e = hipEventRecord(e1, s)) != hipSuccess) break;
-        if ((e = hipEventSynchronize(e1)) != hipSuccess) break;
-        float ms = 0.0f;
-        if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
-        if (ms < best_ms) {
-            best_ms = ms;
-            best = v;
+    // Each variant's time is the minimum over kTuneRounds launches, the rounds interleaved: the first
+    // launch of a kernel also pays for loading its code, and the variants differ by a few percent.
+    constexpr int kTuneRounds = 3;
+    const int nv = avl::trajectory_variants();
+    std::vector<float> vmin(nv, 1e30f);
+    e = hipSuccess;
+    for (int round = 0; round < kTuneRounds && e == hipSuccess; ++round) {
+        for (int v = 0; v < nv; ++v) {
+            const avl::LaunchShape sh = avl::trajectory_shape(batched, v);
+            if ((e = zero()) != hipSuccess) break;
+            if ((e = hipEventRecord(e0, s)) != hipSuccess) break;
+            if ((e = avl::launch_trajectories(a, batched, sh, s)) != hipSuccess) break;
+            if ((e = hipEventRecord(e1, s)) != hipSuccess) break;
+            if ((e = hipEventSynchronize(e1)) != hipSuccess) break;
+            float ms = 0.0f;
+            if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
+            if (ms < vmin[v]) vmin[v] = ms;
         }
     }
+    int best = 0;
+    for (int v = 1; v < nv; ++v)
+        if (vmin[v] < vmin[best]) best = v;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (e != hipSuccess) return e;
@@ -274,6 +296,29 @@ int avl_set_tuning(int32_t variant, int32_t graphs) {
 int32_t avl_tuning_variants(void) { return avl::trajectory_variants(); }
 
 int32_t avl_last_variant(void) { return g_last_variant; }
+
+int avl_set_profiling(int32_t enable) {
+    g_last_error.clear();
+    if (enable && !g_prof_ev[0]) {
+        hipError_t e;
+        if ((e = hipEventCreate(&g_prof_ev[0])) != hipSuccess) return hip_fail(e, "avl_set_profiling");
+        if ((e = hipEventCreate(&g_prof_ev[1])) != hipSuccess) return hip_fail(e, "avl_set_profiling");
+    }
+    g_profile = enable != 0;
+    g_profile_valid = false;
+    return AVL_OK;
+}
+
+int avl_last_kernel_ms(float* ms) {
+    g_last_error.clear();
+    if (!ms) return fail(AVL_EINVAL, "avl_last_kernel_ms: null pointer");
+    if (!g_profile_valid) return fail(AVL_EINVAL, "avl_last_kernel_ms: no timed trajectory call");
+    hipError_t e;
+    if ((e = hipEventSynchronize(g_prof_ev[1])) != hipSuccess) return hip_fail(e, "avl_last_kernel_ms");
+    if ((e = hipEventElapsedTime(ms, g_prof_ev[0], g_prof_ev[1])) != hipSuccess)
+        return hip_fail(e, "avl_last_kernel_ms");
+    return AVL_OK;
+}
 
 size_t avl_workspace_bytes(int32_t H, int32_t W) {
     if (H < 1 || W < 1) return 0;
@@ -347,25 +392,23 @@ int avl_trajectories(const float* dem, const uint8_t* mask, int32_t H, int32_t W
     a.runs = ws.runs;
     a.run_off = ws.run_off;
     a.queues = ws.queues;
-    a.counts = ws.priv_counts;
-    a.vmax2 = ws.priv_vmax2;
+    a.counts = counts;
+    a.vmax2 = reinterpret_cast<uint32_t*>(vmax);  // v^2 bits during the kernel, speeds after the finalize
     a.stats = stats ? reinterpret_cast<unsigned long long*>(stats) : ws.stats;
     a.H = H;
     a.W = W;
     a.n_runs = 1;
     a.S = step_limit;
     a.g2 = 9.81f + 9.81f;
-    a.xcd_stride = (uint32_t)n;
     a.starts = ws.starts;
     a.pdiv = avl::make_divu32(particles_per_cell);
     a.dem_pad = ws.dem_pad;
     a.pad_bytes = (uint32_t)(avl::padded_cells(H, W) * sizeof(float));
 
-    // the private rasters (counts then v^2 bits) are one contiguous region
-    const int64_t priv_words = (int64_t)(ws.priv_vmax2 - ws.priv_counts) + avl::kXcds * n;
     auto zero = [&]() -> hipError_t {
         hipError_t e;
-        if ((e = avl::launch_fill_u32(ws.priv_counts, 0u, priv_words, s)) != hipSuccess) return e;
+        if ((e = avl::launch_fill_u32(counts, 0u, n, s)) != hipSuccess) return e;
+        if ((e = avl::launch_fill_u32(a.vmax2, 0u, n, s)) != hipSuccess) return e;
         if ((e = avl::launch_fill_u64(ws.queues, 0ull, avl::kXcds, s)) != hipSuccess) return e;
         return avl::launch_fill_u64(a.stats, 0ull, 4, s);
     };
@@ -386,10 +429,10 @@ int avl_trajectories(const float* dem, const uint8_t* mask, int32_t H, int32_t W
         return hip_fail(e, "avl_trajectories: autotune");
     g_last_variant = variant;
     if ((e = zero()) != hipSuccess) return hip_fail(e, "avl_trajectories: zero");
-    if ((e = avl::launch_trajectories(a, false, avl::trajectory_shape(false, variant), s)) != hipSuccess)
+    if ((e = timed_launch(a, false, avl::trajectory_shape(false, variant), s)) != hipSuccess)
         return hip_fail(e, "avl_trajectories: launch");
-    if ((e = avl::launch_merge_rasters(ws.priv_counts, ws.priv_vmax2, n, counts, vmax, s)) != hipSuccess)
-        return hip_fail(e, "avl_trajectories: merge");
+    if ((e = avl::launch_finalize_vmax(a.vmax2, n, s)) != hipSuccess)
+        return hip_fail(e, "avl_trajectories: finalize");
     return AVL_OK;
 }
 
@@ -564,7 +607,6 @@ int avl_trajectories_batched(const float* dems, int32_t n_tiles, const uint8_t* 
     a.n_runs = (uint32_t)n_runs;
     a.S = step_limit;
     a.g2 = 9.81f + 9.81f;
-    a.xcd_stride = 0;
     a.starts = nullptr;
     a.pdiv = avl::make_divu32(particles_per_cell);
     const int64_t raster = (int64_t)n_runs * n;
@@ -593,7 +635,7 @@ int avl_trajectories_batched(const float* dems, int32_t n_tiles, const uint8_t* 
         hipError_t e;
         if ((e = prologue()) != hipSuccess) return e;
         if ((e = zero()) != hipSuccess) return e;
-        if ((e = avl::launch_trajectories(a, true, shape, s)) != hipSuccess) return e;
+        if ((e = timed_launch(a, true, shape, s)) != hipSuccess) return e;
         return avl::launch_finalize_vmax(a.vmax2, raster, s);
     };
 

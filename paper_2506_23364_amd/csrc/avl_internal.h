@@ -16,10 +16,8 @@ constexpr int kWave = 64;
 // Single run (avl_workspace_bytes):
 //   [0, 512)     control block: n_cells (i32 @0), stats (4 x u64 @64), per-XCD slot queues (kXcds x u64
 //                @128), run offsets (2 x u64 @192), the run's constants (RunConst @256)
-//   then         per-block sums of the compaction scan (u32), the release-cell list (i32, H*W), and the
-//                per-XCD private rasters: kXcds count rasters, then kXcds v^2-bit rasters (u32, H*W each),
-//                then the start records of the release cells (StartRec, H*W), then the padded DEM (f32,
-//                (H + 2) x (W + 2))
+//   then         per-block sums of the compaction scan (u32), the release-cell list (i32, H*W), the start
+//                records of the release cells (StartRec, H*W) and the padded DEM (f32, (H + 2) x (W + 2))
 // Batch (avl_batched_workspace_bytes):
 //   [0, 512)     control block: per-XCD slot queues @128
 //   then         compaction scan sums; n_masks release-cell lists (i32, H*W each); n_masks cell counts;
@@ -45,8 +43,6 @@ struct Workspace {
     RunConst* runs;               // n_runs
     uint32_t* blk;
     int32_t* cells;               // single: H*W; batch: n_masks x H*W
-    uint32_t* priv_counts;        // single only: kXcds x H*W
-    uint32_t* priv_vmax2;         // single only: kXcds x H*W
     StartRec* starts;             // single only: H*W
     float* dem_pad;               // single only: (H + 2) x (W + 2)
 };
@@ -112,7 +108,6 @@ struct TrajArgs {
     uint32_t n_runs;
     uint32_t S;                                  // step limit
     float g2;                                    // 2g
-    uint32_t xcd_stride;  // single run: elements between the per-XCD private rasters; batched: 0
     const StartRec* __restrict__ starts;         // single run: one per release cell; batched: NULL
     DivU32 pdiv;                                 // division by the particles per cell (same for every run)
     const float* __restrict__ dem_pad;           // single run: the DEM with a replicated border; batched: NULL
@@ -138,8 +133,6 @@ hipError_t launch_pad_dem(const float* dem, int H, int W, float* out, hipStream_
 // starts[i] for each of the *n_cells release cells (capacity n).
 hipError_t launch_start_records(const float* dem, int H, int W, const int32_t* cells, const int32_t* n_cells,
                                 int64_t n, StartRec* starts, hipStream_t s);
-hipError_t launch_merge_rasters(const uint32_t* priv_counts, const uint32_t* priv_vmax2, int64_t n, uint32_t* counts,
-                                float* vmax, hipStream_t s);
 // Setup of the run table: per run, constants from its parameter set and the slot count from its
 // scenario's release-cell count (written by the compaction); then 64-aligned slot offsets.
 struct RunSpec {

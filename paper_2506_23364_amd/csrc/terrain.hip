@@ -1,6 +1,7 @@
 // Terrain passes of the avalanche overlay (section 5.2 of arXiv 2506.23364): surface normals and
 // steepness per DEM texel, the release-point map from a steepness range and an elevation window, and
-// the row-major list of release texels. Plus the raster fill / merge helpers of the trajectory pass.
+// the row-major list of release texels. Plus the fill, padded-DEM and finalize helpers of the trajectory
+// pass.
 //
 // All of these are streaming passes bound by HBM bandwidth; each is written for 64-wide wavefronts
 // with every wave touching whole 256-byte stretches of consecutive cells.
@@ -221,7 +222,6 @@ __global__ __launch_bounds__(256) void k_fill_u64(unsigned long long* __restrict
     if (i < n) p[i] = v;
 }
 
-// Merge of the per-XCD private rasters of the trajectory pass into the caller's rasters:
 // DEM with a one-texel border replicating the edge texels: (H + 2) x (W + 2), row-major. Its texel
 // (r + 1, c + 1) holds dem[clamp(r)][clamp(c)] for r in [-1, H], c in [-1, W], which is what the clamped
 // bilinear patch reads, so the padded lookup needs no clamps.
@@ -234,23 +234,6 @@ __global__ __launch_bounds__(256) void k_pad_dem(const float* __restrict__ dem, 
         const int64_t c = cp < 1 ? 0 : (cp > W ? W - 1 : cp - 1);
         out[i] = dem[r * W + c];
     }
-}
-
-// counts = sum over XCDs, vmax = sqrt(max over XCDs of the v^2 bits). One cell per thread, each of the
-// 2 x kXcds reads coalesced across the wave.
-__global__ __launch_bounds__(256) void k_merge_rasters(const uint32_t* __restrict__ pc, const uint32_t* __restrict__ pv,
-                                                       int64_t n, uint32_t* __restrict__ counts,
-                                                       float* __restrict__ vmax) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    uint32_t c = 0, v = 0;
-#pragma unroll
-    for (int x = 0; x < kXcds; ++x) {
-        c += pc[x * n + i];
-        v = max(v, pv[x * n + i]);
-    }
-    counts[i] = c;
-    vmax[i] = sqrtf(__uint_as_float(v));
 }
 
 // v^2 bits -> speed, in place: vmax = sqrt(max v^2)
@@ -295,14 +278,6 @@ hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t 
 hipError_t launch_finalize_vmax(uint32_t* vmax_bits, int64_t n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_finalize_vmax, dim3(blocks_for(n, 4)), dim3(256), 0, s, vmax_bits, n);
-    return hipGetLastError();
-}
-
-hipError_t launch_merge_rasters(const uint32_t* priv_counts, const uint32_t* priv_vmax2, int64_t n, uint32_t* counts,
-                                float* vmax, hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_merge_rasters, dim3(blocks_for(n, 1)), dim3(256), 0, s, priv_counts, priv_vmax2, n, counts,
-                       vmax);
     return hipGetLastError();
 }
 

@@ -22,8 +22,9 @@
 //  - The slot range is split into one partition per XCD; windows and chunks come from the XCD's own
 //    partition first and from the others only when it is empty. Each XCD's L2 then holds its own band
 //    of the DEM (or its own runs).
-//  - A single run accumulates into private per-XCD rasters (merged after the kernel); a batch writes
-//    each run's own rasters.
+//  - Every run writes the caller's rasters directly (v^2 bits, turned into speeds by a finalize pass).
+//    Per-XCD private copies bought nothing once the table had cut the atomics: the atomics are
+//    performed at the memory side either way, and zeroing and merging the copies cost 9 % at 8192^2.
 //  - Accumulation is integer only (u32 add; u32 max on the bits of v^2 >= 0, whose order is the value
 //    order), so every raster is independent of scheduling and of the kernel variant: bit-reproducible.
 //  - Philox4x32-10 gives four words per block; one block serves two consecutive steps.
@@ -74,6 +75,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((!kBatch
 void k_trajectories(TrajArgs a) {
     static_assert(kFlush % 2 == 0, "epochs keep the iteration parity");
     constexpr uint32_t kSuper = (uint32_t)kWindow * kBlock;  // slots per window top-up
+    static_assert(kTbl % kBlock == 0, "every thread flushes the same number of table slots");
+    constexpr int kPer = kTbl / kBlock;
     __shared__ Table<kTbl> tb;
     __shared__ Control ctl;
     const int lane = threadIdx.x & (kWave - 1);
@@ -82,8 +85,8 @@ void k_trajectories(TrajArgs a) {
     const int W = a.W, H = a.H;
     const float fW = (float)W, fH = (float)H;
     const uint32_t xcd = xcd_id();
-    uint32_t* const counts = a.counts + (size_t)xcd * a.xcd_stride;
-    uint32_t* const vmax2 = a.vmax2 + (size_t)xcd * a.xcd_stride;
+    uint32_t* const counts = a.counts;
+    uint32_t* const vmax2 = a.vmax2;
     // single run: the padded DEM through a buffer resource (32-bit offsets, no clamps)
     const __amdgpu_buffer_rsrc_t dem_rs = buffer_rsrc(a.dem_pad, a.pad_bytes);
     const uint32_t Wp = (uint32_t)W + 2u, row_bytes = 4u * Wp;
@@ -442,17 +445,32 @@ void k_trajectories(TrajArgs a) {
             ctl.busy[(epoch + 1) & 1u] = 0u;
             refill_window(false);
         }
-        for (int k = threadIdx.x; k < kTbl; k += kBlock) {
-            const uint32_t t = tb.tag[k];
-            if (t != kEmpty) {
-                const uint32_t c = tb.cnt[k], v = tb.vmx[k];
-                if (c) atomicAdd(counts + t, c);
-                if (v) global_max(vmax2 + t, v);
+        // flush this thread's kPer slots: all raster reads of the max check are issued before any is
+        // used, so the flush costs one memory round trip rather than one per slot
+        uint32_t ft[kPer], fc[kPer], fv[kPer], fg[kPer];
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            const int k = threadIdx.x + j * kBlock;
+            ft[j] = tb.tag[k];
+            fc[j] = tb.cnt[k];
+            fv[j] = tb.vmx[k];
+        }
+#pragma unroll
+        for (int j = 0; j < kPer; ++j)  // unconditional (an empty slot reads cell 0): no branch between the loads
+            fg[j] = __builtin_nontemporal_load(vmax2 + (ft[j] != kEmpty ? ft[j] : 0u));
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            const int k = threadIdx.x + j * kBlock;
+            if (ft[j] != kEmpty) {
+                if (fc[j]) atomicAdd(counts + ft[j], fc[j]);
+                tb.tag[k] = kEmpty;
                 tb.cnt[k] = 0u;
                 tb.vmx[k] = 0u;
-                tb.tag[k] = kEmpty;
             }
         }
+#pragma unroll
+        for (int j = 0; j < kPer; ++j)
+            if (ft[j] != kEmpty && fg[j] < fv[j]) atomicMax(vmax2 + ft[j], fv[j]);  // a stale read >= v suffices
         my_slot = -1;
         __syncthreads();
         if (ctl.busy[epoch & 1u] == 0u) break;

@@ -220,3 +220,28 @@ def test_alpine_full_size_sampled(avl):
     assert np.array_equal(got_f[0], got_s[0] + got_r[0])
     assert np.array_equal(got_f[1], np.maximum(got_s[1], got_r[1]))
     assert np.array_equal(got_f[2], got_s[2] + got_r[2])
+
+
+def test_large_region_full_size_sampled(avl):
+    """Full 8192^2 region at 5 m (256 MB DEM, ~1.4e6 release cells, 64 particles per cell, step limit
+    8000) in the benchmark's launch shape: the oracle runs every 1009th release cell; the GPU runs that
+    sample, its complement and the whole mask, whose rasters must be the sum (counts, statistics) and the
+    maximum (speeds) of the two parts."""
+    w = synth.make_workload("large")
+    nrm = oracle.normals(w.dem, w.cell_size)
+    mask = oracle.release_mask(nrm, w.dem, w.slope_min_deg, w.slope_max_deg, w.z_min, w.z_max)
+    del nrm
+    cells = np.flatnonzero(mask)
+    assert 5e5 < len(cells) < 3e6
+    sample = np.zeros(mask.size, np.uint8)
+    sample[cells[::1009]] = 1
+    sample = sample.reshape(mask.shape)
+    rest = (mask & (1 - sample)).astype(np.uint8)
+    got_s, ref = both(avl, w.dem, sample, w.cell_size, w.params, w.particles_per_cell, w.step_limit, w.seed, 0,
+                      "large sample")
+    del ref
+    got_r = gpu_run(avl, w.dem, rest, w.cell_size, w.params, w.particles_per_cell, w.step_limit, w.seed)
+    got_f = gpu_run(avl, w.dem, mask, w.cell_size, w.params, w.particles_per_cell, w.step_limit, w.seed)
+    assert np.array_equal(got_f[0], got_s[0] + got_r[0])
+    assert np.array_equal(got_f[1], np.maximum(got_s[1], got_r[1]))
+    assert np.array_equal(got_f[2], got_s[2] + got_r[2])
