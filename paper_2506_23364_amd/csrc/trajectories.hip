@@ -16,9 +16,11 @@
 //    workgroup (tag, count, max; linear probing), flushed to the rasters at epoch boundaries (a pair of
 //    barriers every kFlush iterations). A cell whose probes are all held by other cells goes straight to
 //    the raster.
-//  - The waves of a workgroup share a window of consecutive slots (two ranges of 2 x kBlock slots, topped
-//    up at epoch boundaries), so the table sees the paths of neighbouring release cells together. A wave
-//    that runs the window dry mid-epoch takes 64-slot chunks from the queues directly.
+//  - The waves of a workgroup share a window of consecutive slots (two ranges, topped up at epoch
+//    boundaries), so the table sees the paths of neighbouring release cells together. Top-ups are guided:
+//    up to kWindow x kBlock slots, but at most half the partition's remainder over the blocks of an XCD,
+//    so windows shrink as the queues drain and the blocks finish together. A wave that runs the window
+//    dry mid-epoch takes 64-slot chunks from the queues directly.
 //  - The slot range is split into one partition per XCD; windows and chunks come from the XCD's own
 //    partition first and from the others only when it is empty. Each XCD's L2 then holds its own band
 //    of the DEM (or its own runs).
@@ -68,6 +70,7 @@ struct Control {
     uint32_t take;                // window slots handed out this epoch (grows by 64 per take)
     uint32_t busy[2];             // waves with work left, per epoch parity
     uint32_t part, tried, empty;  // the window's own walk over the XCD partitions
+    unsigned long long left;      // slots left in the partition after the window's last top-up
 };
 
 template <bool kBatch, int kBlock, int kFlush, int kTbl, int kProbes, int kWindow>
@@ -99,15 +102,17 @@ void k_trajectories(TrajArgs a) {
 
     // Takes up to `len` consecutive slots from the XCD queues, starting with this XCD's partition and
     // moving on when it is empty; [base, end) is empty once every partition is. Single lane.
+    // `left` receives what remained of the partition after the take.
     auto take_global = [&](uint32_t& part, uint32_t& tried, uint32_t& empty, uint32_t len, uint64_t& base,
-                           uint64_t& end) {
-        base = end = 0;
+                           uint64_t& end, uint64_t& left) {
+        base = end = left = 0;
         while (!empty) {
             const uint64_t pb = part_begin(total, part), pe = part_begin(total, part + 1);
             const uint64_t got = atomicAdd(a.queues + part, (unsigned long long)len);
             if (pb + got < pe) {
                 base = pb + got;
                 end = (base + len < pe) ? base + len : pe;
+                left = pe - end;
                 return;
             }
             part = (part + 1) % kXcds;
@@ -135,6 +140,7 @@ void k_trajectories(TrajArgs a) {
 
     // Shifts the window past the slots handed out in the epoch that ended and tops it up with a new
     // range when the second range has been reached. Thread 0, between the barriers of a boundary.
+    const uint64_t guide_div = 2ull * max(1u, gridDim.x / (uint32_t)kXcds);  // 2 x blocks per XCD
     auto refill_window = [&](bool first) {
         if (first) {
             ctl.base[0] = ctl.base[1] = 0;
@@ -144,6 +150,7 @@ void k_trajectories(TrajArgs a) {
             ctl.part = xcd;
             ctl.tried = 0;
             ctl.empty = total == 0 ? 1u : 0u;
+            ctl.left = ~0ull;
         }
         const uint32_t l0 = ctl.len[0], l1 = ctl.len[1];
         const uint32_t t = min(ctl.take, l0 + l1);
@@ -158,10 +165,15 @@ void k_trajectories(TrajArgs a) {
         }
         ctl.take = 0;
         if (ctl.len[1] == 0u) {
-            uint64_t wb = 0, we = 0;
-            take_global(ctl.part, ctl.tried, ctl.empty, kSuper, wb, we);
+            // guided top-up: a share of what the partition had left, so windows shrink as the queues
+            // drain and every block runs out of work at about the same time
+            const uint64_t share = ctl.left / guide_div;
+            const uint32_t want = share >= kSuper ? kSuper : max(kChunk, (uint32_t)share & ~(kChunk - 1u));
+            uint64_t wb = 0, we = 0, left = 0;
+            take_global(ctl.part, ctl.tried, ctl.empty, want, wb, we, left);
             ctl.base[1] = wb;
             ctl.len[1] = (uint32_t)(we - wb);
+            ctl.left = left;
         }
     };
     if (threadIdx.x == 0) refill_window(true);
@@ -272,8 +284,8 @@ void k_trajectories(TrajArgs a) {
                         }
                     }
                     if (cend == base && !queue_empty) {
-                        uint64_t gb = 0, ge = 0;
-                        if (lane == leader) take_global(part, tried, queue_empty, kChunk, gb, ge);
+                        uint64_t gb = 0, ge = 0, gl = 0;
+                        if (lane == leader) take_global(part, tried, queue_empty, kChunk, gb, ge, gl);
                         base = wave_bcast64(__shfl(gb, leader, kWave));
                         cend = wave_bcast64(__shfl(ge, leader, kWave));
                         queue_empty = __builtin_amdgcn_readlane(queue_empty, leader);
