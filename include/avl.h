@@ -116,8 +116,8 @@ typedef struct avl_run {
     uint64_t seed;     /* Philox key */
 } avl_run;
 
-/* Workspace bytes that avl_trajectories_batched needs. */
-AVL_API size_t avl_batched_workspace_bytes(int32_t H, int32_t W, int32_t n_masks, int32_t n_runs);
+/* Workspace bytes that avl_trajectories_batched needs (0 if a count is < 1). */
+AVL_API size_t avl_batched_workspace_bytes(int32_t H, int32_t W, int32_t n_tiles, int32_t n_masks, int32_t n_runs);
 
 /* Batched ensembles (section 5.2 motivates interactive sweeps of the trajectory parameters; section 3
  * recomputes the overlay whenever the user changes them): n_runs independent trajectory passes, each
@@ -128,7 +128,8 @@ AVL_API size_t avl_batched_workspace_bytes(int32_t H, int32_t W, int32_t n_masks
  * counts, vmax: n_runs*H*W (run r at r*H*W), as in avl_trajectories. stats (nullable): n_runs*4 uint64.
  * run_status (nullable): n_runs int32, 0 = ran, 1 = an index out of range, 2 = invalid parameters (such a
  * run releases no particle and leaves zero rasters). particles_per_cell and step_limit are shared.
- * Need n_runs*H*W, n_tiles*H*W and n_masks*H*W all < 2^32 - 1. When `stream` is not the null stream, the
+ * Need n_runs*H*W, n_tiles*H*W, n_masks*H*W and n_tiles*(H+2)*(W+2) all < 2^32 - 1 and (H+2)*(W+2) < 2^30
+ * (the kernel reads padded copies of the tiles through 32-bit offsets). When `stream` is not the null stream, the
  * whole sequence (zero fills, compactions, run setup, trajectory kernel, finalize) is captured once into
  * a HIP graph per argument set and replayed on later calls. */
 AVL_API int avl_trajectories_batched(const float* dems, int32_t n_tiles, const uint8_t* masks, int32_t n_masks,

@@ -68,7 +68,7 @@ def _load() -> ctypes.CDLL:
                                    vp, sz, vp]
     L.avl_set_profiling.argtypes = [i32]
     L.avl_last_kernel_ms.argtypes = [ctypes.POINTER(ctypes.c_float)]
-    L.avl_batched_workspace_bytes.argtypes = [i32, i32, i32, i32]
+    L.avl_batched_workspace_bytes.argtypes = [i32, i32, i32, i32, i32]
     L.avl_batched_workspace_bytes.restype = sz
     L.avl_trajectories_batched.argtypes = [vp, i32, vp, i32, i32, i32, f32, vp, i32, vp, i32, u32, u32, vp, vp, vp,
                                            vp, vp, sz, vp]
@@ -138,8 +138,8 @@ def workspace_bytes(h: int, w: int) -> int:
     return int(lib.avl_workspace_bytes(h, w))
 
 
-def batched_workspace_bytes(h: int, w: int, n_masks: int, n_runs: int) -> int:
-    return int(lib.avl_batched_workspace_bytes(h, w, n_masks, n_runs))
+def batched_workspace_bytes(h: int, w: int, n_tiles: int, n_masks: int, n_runs: int) -> int:
+    return int(lib.avl_batched_workspace_bytes(h, w, n_tiles, n_masks, n_runs))
 
 
 def set_tuning(variant: int = -1, graphs: bool = True) -> None:
@@ -279,7 +279,7 @@ def trajectories_batched(dems: torch.Tensor, masks: torch.Tensor, cell_size: flo
                           torch.empty((n_runs, h, w), dtype=torch.float32, device=dev),
                           torch.empty((n_runs, 4), dtype=torch.uint64, device=dev),
                           torch.empty(n_runs, dtype=torch.int32, device=dev))
-    nb = batched_workspace_bytes(h, w, n_masks, n_runs)
+    nb = batched_workspace_bytes(h, w, n_tiles, n_masks, n_runs)
     with torch.cuda.device(dems.device):
         ws = _workspace(dems.device, nb)
         _check(lib.avl_trajectories_batched(dems.data_ptr(), n_tiles, masks.data_ptr(), n_masks, h, w, cell_size,

@@ -40,14 +40,17 @@ Workspace carve(void* base, int64_t H, int64_t W) {
     return w;
 }
 
-size_t batched_workspace_bytes(int64_t n, int64_t n_masks, int64_t n_runs) {
+size_t batched_workspace_bytes(int64_t H, int64_t W, int64_t n_tiles, int64_t n_masks, int64_t n_runs) {
+    const int64_t n = H * W;
     return kControl + round256((size_t)scan_blocks(n) * sizeof(uint32_t)) +
            round256((size_t)n_masks * n * sizeof(int32_t)) + round256((size_t)n_masks * sizeof(int32_t)) +
            round256((size_t)n_runs * sizeof(RunConst)) + round256((size_t)(n_runs + 1) * sizeof(unsigned long long)) +
-           round256((size_t)n_runs * 4 * sizeof(unsigned long long));
+           round256((size_t)n_runs * 4 * sizeof(unsigned long long)) +
+           round256((size_t)n_tiles * padded_cells(H, W) * sizeof(float));
 }
 
-Workspace carve_batched(void* base, int64_t n, int64_t n_masks, int64_t n_runs) {
+Workspace carve_batched(void* base, int64_t H, int64_t W, int64_t n_masks, int64_t n_runs) {
+    const int64_t n = H * W;
     char* p = static_cast<char*>(base);
     Workspace w{};
     w.queues = reinterpret_cast<unsigned long long*>(p + 128);
@@ -63,6 +66,8 @@ Workspace carve_batched(void* base, int64_t n, int64_t n_masks, int64_t n_runs) 
     w.run_off = reinterpret_cast<unsigned long long*>(p);
     p += round256((size_t)(n_runs + 1) * sizeof(unsigned long long));
     w.stats = reinterpret_cast<unsigned long long*>(p);
+    p += round256((size_t)n_runs * 4 * sizeof(unsigned long long));
+    w.dem_pad = reinterpret_cast<float*>(p);
     return w;
 }
 
@@ -325,9 +330,9 @@ size_t avl_workspace_bytes(int32_t H, int32_t W) {
     return avl::workspace_bytes(H, W);
 }
 
-size_t avl_batched_workspace_bytes(int32_t H, int32_t W, int32_t n_masks, int32_t n_runs) {
-    if (H < 1 || W < 1 || n_masks < 1 || n_runs < 1) return 0;
-    return avl::batched_workspace_bytes((int64_t)H * W, n_masks, n_runs);
+size_t avl_batched_workspace_bytes(int32_t H, int32_t W, int32_t n_tiles, int32_t n_masks, int32_t n_runs) {
+    if (H < 1 || W < 1 || n_tiles < 1 || n_masks < 1 || n_runs < 1) return 0;
+    return avl::batched_workspace_bytes(H, W, n_tiles, n_masks, n_runs);
 }
 
 int avl_normals(const float* dem, int32_t H, int32_t W, float cell_size, float* normals4, void* stream) {
@@ -588,10 +593,13 @@ int avl_trajectories_batched(const float* dems, int32_t n_tiles, const uint8_t* 
     if (!finite(cell_size) || !(cell_size > 0.0f))
         return fail(AVL_EINVAL, "avl_trajectories_batched: cell_size must be > 0");
     if (particles_per_cell == 0) return fail(AVL_EINVAL, "avl_trajectories_batched: particles_per_cell must be >= 1");
-    if (workspace_bytes < avl::batched_workspace_bytes(n, n_masks, n_runs))
+    const int64_t np = avl::padded_cells(H, W);
+    if (np >= (int64_t(1) << 30) || (int64_t)n_tiles * np >= lim)
+        return fail(AVL_EINVAL, "avl_trajectories_batched: need (H + 2)(W + 2) < 2^30 and n_tiles (H + 2)(W + 2) < 2^32 - 1");
+    if (workspace_bytes < avl::batched_workspace_bytes(H, W, n_tiles, n_masks, n_runs))
         return fail(AVL_ENOMEM, "avl_trajectories_batched: workspace too small");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    avl::Workspace ws = avl::carve_batched(workspace, n, n_masks, n_runs);
+    avl::Workspace ws = avl::carve_batched(workspace, H, W, n_masks, n_runs);
 
     avl::TrajArgs a{};
     a.dem = dems;
@@ -609,6 +617,8 @@ int avl_trajectories_batched(const float* dems, int32_t n_tiles, const uint8_t* 
     a.g2 = 9.81f + 9.81f;
     a.starts = nullptr;
     a.pdiv = avl::make_divu32(particles_per_cell);
+    a.dem_pad = ws.dem_pad;
+    a.pad_bytes = (uint32_t)(np * sizeof(float));
     const int64_t raster = (int64_t)n_runs * n;
 
     auto zero = [&]() -> hipError_t {
@@ -618,9 +628,12 @@ int avl_trajectories_batched(const float* dems, int32_t n_tiles, const uint8_t* 
         if ((e = avl::launch_fill_u64(ws.queues, 0ull, avl::kXcds, s)) != hipSuccess) return e;
         return avl::launch_fill_u64(a.stats, 0ull, 4 * (int64_t)n_runs, s);
     };
-    // release-cell lists of every scenario, then the run table
+    // padded copies of the tiles, release-cell lists of every scenario, then the run table
     auto prologue = [&]() -> hipError_t {
         hipError_t e;
+        for (int32_t t = 0; t < n_tiles; ++t)
+            if ((e = avl::launch_pad_dem(dems + (size_t)t * n, H, W, ws.dem_pad + (size_t)t * np, s)) != hipSuccess)
+                return e;
         for (int32_t m = 0; m < n_masks; ++m)
             if ((e = avl::launch_compact(masks + (size_t)m * n, n, ws.cells + (size_t)m * n, ws.n_cells + m, ws.blk,
                                          s)) != hipSuccess)

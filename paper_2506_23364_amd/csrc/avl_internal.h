@@ -21,7 +21,8 @@ constexpr int kWave = 64;
 // Batch (avl_batched_workspace_bytes):
 //   [0, 512)     control block: per-XCD slot queues @128
 //   then         compaction scan sums; n_masks release-cell lists (i32, H*W each); n_masks cell counts;
-//                n_runs RunConst; n_runs + 1 slot offsets; n_runs x 4 internal statistics
+//                n_runs RunConst; n_runs + 1 slot offsets; n_runs x 4 internal statistics; n_tiles padded
+//                DEM tiles (f32, (H + 2) x (W + 2) each)
 // Every region starts on a 256-byte boundary.
 constexpr int kXcds = 8;            // MI355X: 8 XCDs, each with its own L2
 constexpr int kScanThreads = 256;
@@ -44,15 +45,15 @@ struct Workspace {
     uint32_t* blk;
     int32_t* cells;               // single: H*W; batch: n_masks x H*W
     StartRec* starts;             // single only: H*W
-    float* dem_pad;               // single only: (H + 2) x (W + 2)
+    float* dem_pad;               // single: (H + 2) x (W + 2); batch: n_tiles of them
 };
 
 // cells of the DEM with a one-texel border
-inline int64_t padded_cells(int64_t H, int64_t W) { return (H + 2) * (W + 2); }
+__host__ __device__ inline int64_t padded_cells(int64_t H, int64_t W) { return (H + 2) * (W + 2); }
 size_t workspace_bytes(int64_t H, int64_t W);
 Workspace carve(void* base, int64_t H, int64_t W);
-size_t batched_workspace_bytes(int64_t n, int64_t n_masks, int64_t n_runs);
-Workspace carve_batched(void* base, int64_t n, int64_t n_masks, int64_t n_runs);
+size_t batched_workspace_bytes(int64_t H, int64_t W, int64_t n_tiles, int64_t n_masks, int64_t n_runs);
+Workspace carve_batched(void* base, int64_t H, int64_t W, int64_t n_masks, int64_t n_runs);
 
 // ------------------------------------------------------------------ trajectory kernel arguments
 // Derived constants of one run (one parameter set on one DEM tile and release scenario), binary32,
@@ -67,7 +68,8 @@ struct RunConst {
     uint32_t raster_off;       // element offset of the run's rasters
     uint32_t P;                // particles per release cell
     unsigned long long n_slots;  // release cells x P
-    unsigned long long pad;
+    uint32_t pad_off;          // element offset of the run's padded DEM tile
+    uint32_t pad2;
 };
 static_assert(sizeof(RunConst) == 80, "RunConst layout");
 
@@ -110,8 +112,8 @@ struct TrajArgs {
     float g2;                                    // 2g
     const StartRec* __restrict__ starts;         // single run: one per release cell; batched: NULL
     DivU32 pdiv;                                 // division by the particles per cell (same for every run)
-    const float* __restrict__ dem_pad;           // single run: the DEM with a replicated border; batched: NULL
-    uint32_t pad_bytes;                          // (H + 2) (W + 2) x 4 < 2^32
+    const float* __restrict__ dem_pad;           // the DEM tiles with a replicated border, (H + 2)(W + 2) each
+    uint32_t pad_bytes;                          // bytes of one padded tile, (H + 2) (W + 2) x 4 < 2^32
 };
 
 struct LaunchShape {

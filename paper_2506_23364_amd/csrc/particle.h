@@ -132,6 +132,31 @@ __device__ __forceinline__ StartRec start_state(const float* __restrict__ dem, i
     return st;
 }
 
+// start_state() with the patch read from the padded DEM (the same values, so the same result)
+__device__ __forceinline__ StartRec start_state_pad(__amdgpu_buffer_rsrc_t rs, uint32_t Wp, uint32_t row_bytes, int W,
+                                                    uint32_t cell) {
+    StartRec st;
+    const int r = (int)(cell / (uint32_t)W);
+    const int c = (int)(cell - (uint32_t)r * (uint32_t)W);
+    st.x = (float)c + 0.5f;
+    st.y = (float)r + 0.5f;
+    const Sample s0 = bilinear_pad(rs, Wp, row_bytes, st.x, st.y);
+    st.z = s0.z;
+    st.gx = s0.gx;
+    st.gy = s0.gy;
+    const float gg = s0.gx * s0.gx + s0.gy * s0.gy;
+    if (gg > 0.0f) {
+        const float t = 1.0f / sqrtf(gg);
+        st.dx = -(s0.gx * t);
+        st.dy = -(s0.gy * t);
+    } else {
+        st.dx = 0.0f;
+        st.dy = 0.0f;
+    }
+    st.cell = cell;
+    return st;
+}
+
 __device__ __forceinline__ uint32_t udiv(uint32_t n, const DivU32& d) {
     const uint32_t t = __umulhi(d.mul, n);
     return (t + ((n - t) >> d.sh1)) >> d.sh2;

@@ -74,7 +74,7 @@ struct Control {
 };
 
 template <bool kBatch, int kBlock, int kFlush, int kTbl, int kProbes, int kWindow>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu((!kBatch || kBlock >= 1024) ? 8 : 1)))
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8)))
 void k_trajectories(TrajArgs a) {
     static_assert(kFlush % 2 == 0, "epochs keep the iteration parity");
     constexpr uint32_t kSuper = (uint32_t)kWindow * kBlock;  // slots per window top-up
@@ -90,9 +90,7 @@ void k_trajectories(TrajArgs a) {
     const uint32_t xcd = xcd_id();
     uint32_t* const counts = a.counts;
     uint32_t* const vmax2 = a.vmax2;
-    // single run: the padded DEM through a buffer resource (32-bit offsets, no clamps)
-    const __amdgpu_buffer_rsrc_t dem_rs = buffer_rsrc(a.dem_pad, a.pad_bytes);
-    const uint32_t Wp = (uint32_t)W + 2u, row_bytes = 4u * Wp;
+    const uint32_t Wp = (uint32_t)W + 2u, row_bytes = 4u * Wp;  // rows of the padded DEM tiles
 
     for (int k = threadIdx.x; k < kTbl; k += kBlock) {
         tb.tag[k] = kEmpty;
@@ -179,41 +177,28 @@ void k_trajectories(TrajArgs a) {
     if (threadIdx.x == 0) refill_window(true);
     __syncthreads();
 
-    // constants of a single run, in scalar registers (a batch reads them per lane, per iteration)
-    const RunConst rc = uniform_run(a.runs[0]);
-    uint32_t b = 0;  // run index of the lane's particle (batched)
+    // The wave's run: its constants in scalar registers and its padded DEM tile through a buffer
+    // resource (32-bit offsets, no clamps). A single run keeps run 0; in a batch a wave works on one run
+    // at a time, and slots of the next run wait in its reservoir until the wave has no particle left.
+    uint32_t wrun = 0;
+    RunConst rc = uniform_run(a.runs[0]);
+    __amdgpu_buffer_rsrc_t dem_rs = buffer_rsrc(a.dem_pad + rc.pad_off, a.pad_bytes);
 
-    // per-lane statistics of run b
+    // per-lane statistics of run wrun, added to the run's counters when the wave changes run or ends
     uint64_t st_steps = 0;
     uint32_t st_exit = 0, st_stop = 0, st_limit = 0;
-    auto flush_stats = [&](bool has) {
-        // all lanes that have counters to flush belong to one run: reduce across the wave
-        const uint64_t m = __ballot(has);
-        if (!m) return;
-        const int leader = __ffsll((long long)m) - 1;
-        const uint32_t lb = __builtin_amdgcn_readlane(b, leader);
-        if (__ballot(has && b != lb) == 0) {
-            const uint64_t s0 = wave_sum64(has ? st_steps : 0);
-            const uint64_t s1 = wave_sum64(has ? st_exit : 0), s2 = wave_sum64(has ? st_stop : 0);
-            const uint64_t s3 = wave_sum64(has ? st_limit : 0);
-            if (lane == leader) {
-                unsigned long long* st = a.stats + 4 * (size_t)lb;
-                if (s0) atomicAdd(st + 0, (unsigned long long)s0);
-                if (s1) atomicAdd(st + 1, (unsigned long long)s1);
-                if (s2) atomicAdd(st + 2, (unsigned long long)s2);
-                if (s3) atomicAdd(st + 3, (unsigned long long)s3);
-            }
-        } else if (has) {
-            unsigned long long* st = a.stats + 4 * (size_t)b;
-            if (st_steps) atomicAdd(st + 0, (unsigned long long)st_steps);
-            if (st_exit) atomicAdd(st + 1, (unsigned long long)st_exit);
-            if (st_stop) atomicAdd(st + 2, (unsigned long long)st_stop);
-            if (st_limit) atomicAdd(st + 3, (unsigned long long)st_limit);
+    auto flush_stats = [&]() {
+        const uint64_t s0 = wave_sum64(st_steps), s1 = wave_sum64(st_exit), s2 = wave_sum64(st_stop);
+        const uint64_t s3 = wave_sum64(st_limit);
+        if (lane == 0) {
+            unsigned long long* st = a.stats + 4 * (size_t)wrun;
+            if (s0) atomicAdd(st + 0, (unsigned long long)s0);
+            if (s1) atomicAdd(st + 1, (unsigned long long)s1);
+            if (s2) atomicAdd(st + 2, (unsigned long long)s2);
+            if (s3) atomicAdd(st + 3, (unsigned long long)s3);
         }
-        if (has) {
-            st_steps = 0;
-            st_exit = st_stop = st_limit = 0;
-        }
+        st_steps = 0;
+        st_exit = st_stop = st_limit = 0;
     };
 
     // wave-uniform slot state: this wave's own walk over the XCD partitions (once the window is spent),
@@ -253,79 +238,79 @@ void k_trajectories(TrajArgs a) {
                 break;
             }
 
-            // ---- hand slots to idle lanes in lane order: reservoir, then the window, then the queues.
-            // Only on even iterations: every particle then starts on an even iteration, so its step
-            // parity is the iteration's and the Philox block (one per two steps) is a uniform branch.
+            // ---- hand slots to idle lanes in lane order: the reservoir, refilled with the next 64-slot
+            // chunk of the window (else of the queues) when it runs dry. Only on even iterations: every
+            // particle then starts on an even iteration, so its step parity is the iteration's and the
+            // Philox block (one per two steps) is a uniform branch.
             bool fresh = false;
             if ((it & 1) == 0 && nidle > 0 && !drained) {
-                const uint64_t avail = res_end - res_next;
-                const int rank = __popcll(idle & below);
+                uint64_t want = idle;  // idle lanes not yet served
                 uint64_t slot = ~0ull;
-                uint32_t srun = res_run;
-                if (avail >= (uint64_t)nidle) {
-                    slot = res_next + rank;
-                    res_next += nidle;
-                } else {
-                    uint64_t base = 0, cend = 0;
-                    const int leader = __ffsll((long long)idle) - 1;
-                    if (!win_out) {
-                        uint32_t v = 0;
-                        if (lane == leader) v = atomicAdd(&ctl.take, kChunk);
-                        v = __builtin_amdgcn_readlane(v, leader);
-                        // the ranges are multiples of 64 long, so a chunk never straddles them
-                        if (v < wl0) {
-                            base = wb0 + v;
-                            cend = base + min(wl0 - v, kChunk);
-                        } else if (v - wl0 < wl1) {
-                            base = wb1 + (v - wl0);
-                            cend = base + min(wl1 - (v - wl0), kChunk);
-                        } else {
-                            win_out = true;
+#pragma unroll 1
+                for (int round = 0; round < 2 && want != 0ull; ++round) {
+                    if (res_next >= res_end) {
+                        uint64_t base = 0, cend = 0;
+                        if (!win_out) {
+                            uint32_t v = 0;
+                            if (lane == 0) v = atomicAdd(&ctl.take, kChunk);
+                            v = __builtin_amdgcn_readfirstlane(v);
+                            // the ranges are multiples of 64 long, so a chunk never straddles them
+                            if (v < wl0) {
+                                base = wb0 + v;
+                                cend = base + min(wl0 - v, kChunk);
+                            } else if (v - wl0 < wl1) {
+                                base = wb1 + (v - wl0);
+                                cend = base + min(wl1 - (v - wl0), kChunk);
+                            } else {
+                                win_out = true;
+                            }
                         }
+                        if (cend == base && !queue_empty) {
+                            uint64_t gb = 0, ge = 0, gl = 0;
+                            if (lane == 0) take_global(part, tried, queue_empty, kChunk, gb, ge, gl);
+                            base = wave_bcast64(gb);
+                            cend = wave_bcast64(ge);
+                            queue_empty = __builtin_amdgcn_readfirstlane(queue_empty);
+                            part = __builtin_amdgcn_readfirstlane(part);
+                            tried = __builtin_amdgcn_readfirstlane(tried);
+                        }
+                        if (cend == base) break;  // nothing left for this wave
+                        res_next = base;
+                        res_end = cend;
+                        res_run = kBatch ? find_run(a.run_off, a.n_runs, base) : 0u;
                     }
-                    if (cend == base && !queue_empty) {
-                        uint64_t gb = 0, ge = 0, gl = 0;
-                        if (lane == leader) take_global(part, tried, queue_empty, kChunk, gb, ge, gl);
-                        base = wave_bcast64(__shfl(gb, leader, kWave));
-                        cend = wave_bcast64(__shfl(ge, leader, kWave));
-                        queue_empty = __builtin_amdgcn_readlane(queue_empty, leader);
-                        part = __builtin_amdgcn_readlane(part, leader);
-                        tried = __builtin_amdgcn_readlane(tried, leader);
+                    if (kBatch && res_run != wrun) {
+                        // the wave changes run only once it has no particle of the old one
+                        if (want != idle || __ballot(alive) != 0ull) break;
+                        flush_stats();
+                        wrun = res_run;
+                        rc = uniform_run(a.runs[wrun]);
+                        dem_rs = buffer_rsrc(a.dem_pad + rc.pad_off, a.pad_bytes);
                     }
-                    const uint32_t new_run = (kBatch && cend > base) ? find_run(a.run_off, a.n_runs, base) : 0u;
-                    if ((uint64_t)rank < avail) {
-                        slot = res_next + rank;
-                    } else if (base + (rank - avail) < cend) {
-                        slot = base + (rank - avail);
-                        srun = new_run;
-                    }
-                    const uint64_t next = base + ((uint64_t)nidle - avail);
-                    res_next = next < cend ? next : cend;
-                    res_end = cend;
-                    res_run = new_run;
+                    const uint64_t avail = res_end - res_next;
+                    const bool mine = ((want >> lane) & 1ull) != 0ull;
+                    const int rank = __popcll(want & below);
+                    const bool served = mine && (uint64_t)rank < avail;
+                    if (served) slot = res_next + (uint64_t)rank;
+                    const uint64_t n_want = (uint64_t)__popcll(want);
+                    res_next += avail < n_want ? avail : n_want;
+                    want &= ~__ballot(served);
                 }
                 uint64_t i = 0;  // release-cell index of the new particle within its run
-                if (!alive && slot < total) {
-                    const uint64_t local = kBatch ? slot - a.run_off[srun] : slot;
-                    const uint64_t n_slots = kBatch ? a.runs[srun].n_slots : rc.n_slots;
-                    const uint32_t P = kBatch ? a.runs[srun].P : rc.P;
-                    if (local < n_slots) {  // past n_slots: padding up to the next multiple of 64
-                        i = (local >> 32) == 0 ? (uint64_t)udiv((uint32_t)local, a.pdiv) : local / P;
-                        rep = (uint32_t)local - (uint32_t)i * P;
+                if (slot != ~0ull) {
+                    const uint64_t local = slot - (kBatch ? a.run_off[wrun] : 0ull);
+                    if (local < rc.n_slots) {  // past n_slots: padding up to the next multiple of 64
+                        i = (local >> 32) == 0 ? (uint64_t)udiv((uint32_t)local, a.pdiv) : local / rc.P;
+                        rep = (uint32_t)local - (uint32_t)i * rc.P;
                         fresh = true;
                     }
                 }
-                if (kBatch) {
-                    // a lane's statistics belong to the run of its previous particle
-                    flush_stats(fresh && srun != b);
-                    if (fresh) b = srun;
-                }
                 if (fresh) {
-                    // a batch computes the start state per particle (its DEM tile varies by run); a single
-                    // run reads it from the per-cell records
-                    const StartRec st =
-                        kBatch ? start_state(a.dem + a.runs[b].dem_off, H, W, (uint32_t)a.cells[a.runs[b].cells_off + i])
-                               : a.starts[i];
+                    // a single run reads the start state from its per-cell records; a batch computes it
+                    // (the DEM tile differs between runs), from the same padded tile the steps read
+                    const StartRec st = kBatch ? start_state_pad(dem_rs, Wp, row_bytes, W,
+                                                                 (uint32_t)a.cells[rc.cells_off + i])
+                                               : a.starts[i];
                     cell_id = st.cell;
                     x = st.x;
                     y = st.y;
@@ -340,15 +325,14 @@ void k_trajectories(TrajArgs a) {
                     v2 = 0.0f;
                     cmax2 = 0.0f;
                     n = 0;
-                    cur = (kBatch ? a.runs[b].raster_off : rc.raster_off) + cell_id;
+                    cur = rc.raster_off + cell_id;
                     alive = true;
                 }
             }
             count_entry(fresh);  // entry into the release cell
 
-            // ---- one step of every live particle. A batch reads its run's constants afresh each
-            // iteration (L1/L2 hits) rather than holding 16 more VGPRs per lane.
-            const RunConst R = kBatch ? a.runs[b] : rc;
+            // ---- one step of every live particle
+            const RunConst& R = rc;
             bool leave = false, entered = false;
             uint32_t leave_bits = 0;
             int leave_slot = -1;
@@ -389,8 +373,7 @@ void k_trajectories(TrajArgs a) {
                         ++st_exit;
                         ended = true;
                     } else {
-                        const Sample s1 = kBatch ? bilinear(a.dem + R.dem_off, H, W, x1, y1)
-                                                : bilinear_pad(dem_rs, Wp, row_bytes, x1, y1);
+                        const Sample s1 = bilinear_pad(dem_rs, Wp, row_bytes, x1, y1);
                         const float dz = z - s1.z;
                         const float ds = sqrtf(R.dl2 + dz * dz);
                         const float num = v2 + a.g2 * (dz - R.mdl);
@@ -487,7 +470,7 @@ void k_trajectories(TrajArgs a) {
         __syncthreads();
         if (ctl.busy[epoch & 1u] == 0u) break;
     }
-    flush_stats(st_steps != 0 || st_exit != 0 || st_stop != 0 || st_limit != 0);
+    flush_stats();
 }
 
 // ------------------------------------------------------------------------------------------ start records
@@ -562,6 +545,7 @@ __global__ __launch_bounds__(1024) void k_setup_runs(const RunSpec* __restrict__
         c.key1 = (uint32_t)(sp.seed >> 32);
         c.run = sp.run_id;
         c.dem_off = (uint32_t)(sp.tile * HW);
+        c.pad_off = (uint32_t)(sp.tile * (uint64_t)padded_cells(H, W));
         c.cells_off = (uint32_t)(sp.scenario * HW);
         c.raster_off = batched ? (uint32_t)(r * HW) : 0u;
         c.P = P;
