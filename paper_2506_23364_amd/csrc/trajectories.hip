@@ -244,60 +244,86 @@ void k_trajectories(TrajArgs a) {
             // Philox block (one per two steps) is a uniform branch.
             bool fresh = false;
             if ((it & 1) == 0 && nidle > 0 && !drained) {
-                uint64_t want = idle;  // idle lanes not yet served
+                // next 64-slot chunk of the window, else of the queues; empty when neither has any left
+                auto next_chunk = [&](uint64_t& base, uint64_t& cend) {
+                    base = cend = 0;
+                    if (!win_out) {
+                        uint32_t v = 0;
+                        if (lane == 0) v = atomicAdd(&ctl.take, kChunk);
+                        v = __builtin_amdgcn_readfirstlane(v);
+                        // the ranges are multiples of 64 long, so a chunk never straddles them
+                        if (v < wl0) {
+                            base = wb0 + v;
+                            cend = base + min(wl0 - v, kChunk);
+                        } else if (v - wl0 < wl1) {
+                            base = wb1 + (v - wl0);
+                            cend = base + min(wl1 - (v - wl0), kChunk);
+                        } else {
+                            win_out = true;
+                        }
+                    }
+                    if (cend == base && !queue_empty) {
+                        uint64_t gb = 0, ge = 0, gl = 0;
+                        if (lane == 0) take_global(part, tried, queue_empty, kChunk, gb, ge, gl);
+                        base = wave_bcast64(gb);
+                        cend = wave_bcast64(ge);
+                        queue_empty = __builtin_amdgcn_readfirstlane(queue_empty);
+                        part = __builtin_amdgcn_readfirstlane(part);
+                        tried = __builtin_amdgcn_readfirstlane(tried);
+                    }
+                };
+                const int rank = __popcll(idle & below);
                 uint64_t slot = ~0ull;
-#pragma unroll 1
-                for (int round = 0; round < 2 && want != 0ull; ++round) {
-                    if (res_next >= res_end) {
-                        uint64_t base = 0, cend = 0;
-                        if (!win_out) {
-                            uint32_t v = 0;
-                            if (lane == 0) v = atomicAdd(&ctl.take, kChunk);
-                            v = __builtin_amdgcn_readfirstlane(v);
-                            // the ranges are multiples of 64 long, so a chunk never straddles them
-                            if (v < wl0) {
-                                base = wb0 + v;
-                                cend = base + min(wl0 - v, kChunk);
-                            } else if (v - wl0 < wl1) {
-                                base = wb1 + (v - wl0);
-                                cend = base + min(wl1 - (v - wl0), kChunk);
-                            } else {
-                                win_out = true;
-                            }
-                        }
-                        if (cend == base && !queue_empty) {
-                            uint64_t gb = 0, ge = 0, gl = 0;
-                            if (lane == 0) take_global(part, tried, queue_empty, kChunk, gb, ge, gl);
-                            base = wave_bcast64(gb);
-                            cend = wave_bcast64(ge);
-                            queue_empty = __builtin_amdgcn_readfirstlane(queue_empty);
-                            part = __builtin_amdgcn_readfirstlane(part);
-                            tried = __builtin_amdgcn_readfirstlane(tried);
-                        }
-                        if (cend == base) break;  // nothing left for this wave
-                        res_next = base;
-                        res_end = cend;
-                        res_run = kBatch ? find_run(a.run_off, a.n_runs, base) : 0u;
-                    }
-                    if (kBatch && res_run != wrun) {
-                        // the wave changes run only once it has no particle of the old one
-                        if (want != idle || __ballot(alive) != 0ull) break;
-                        flush_stats();
-                        wrun = res_run;
-                        rc = uniform_run(a.runs[wrun]);
-                        dem_rs = buffer_rsrc(a.dem_pad + rc.pad_off, a.pad_bytes);
-                    }
+                if constexpr (!kBatch) {
+                    // one run: the reservoir's remainder, then a new chunk, in one pass
                     const uint64_t avail = res_end - res_next;
-                    const bool mine = ((want >> lane) & 1ull) != 0ull;
-                    const int rank = __popcll(want & below);
-                    const bool served = mine && (uint64_t)rank < avail;
-                    if (served) slot = res_next + (uint64_t)rank;
-                    const uint64_t n_want = (uint64_t)__popcll(want);
-                    res_next += avail < n_want ? avail : n_want;
-                    want &= ~__ballot(served);
+                    if (avail >= (uint64_t)nidle) {
+                        slot = res_next + rank;
+                        res_next += nidle;
+                    } else {
+                        uint64_t base, cend;
+                        next_chunk(base, cend);
+                        if ((uint64_t)rank < avail)
+                            slot = res_next + rank;
+                        else if (base + (rank - avail) < cend)
+                            slot = base + (rank - avail);
+                        const uint64_t next = base + ((uint64_t)nidle - avail);
+                        res_next = next < cend ? next : cend;
+                        res_end = cend;
+                    }
+                } else {
+                    // a batch: the same two sources, but a chunk of another run waits in the reservoir
+                    // until the wave has no particle of its current run left
+                    uint64_t want = idle;  // idle lanes not yet served
+#pragma unroll 1
+                    for (int round = 0; round < 2 && want != 0ull; ++round) {
+                        if (res_next >= res_end) {
+                            uint64_t base, cend;
+                            next_chunk(base, cend);
+                            if (cend == base) break;  // nothing left for this wave
+                            res_next = base;
+                            res_end = cend;
+                            res_run = find_run(a.run_off, a.n_runs, base);
+                        }
+                        if (res_run != wrun) {
+                            if (want != idle || __ballot(alive) != 0ull) break;
+                            flush_stats();
+                            wrun = res_run;
+                            rc = uniform_run(a.runs[wrun]);
+                            dem_rs = buffer_rsrc(a.dem_pad + rc.pad_off, a.pad_bytes);
+                        }
+                        const uint64_t avail = res_end - res_next;
+                        const bool mine = ((want >> lane) & 1ull) != 0ull;
+                        const int r = __popcll(want & below);
+                        const bool served = mine && (uint64_t)r < avail;
+                        if (served) slot = res_next + (uint64_t)r;
+                        const uint64_t n_want = (uint64_t)__popcll(want);
+                        res_next += avail < n_want ? avail : n_want;
+                        want &= ~__ballot(served);
+                    }
                 }
                 uint64_t i = 0;  // release-cell index of the new particle within its run
-                if (slot != ~0ull) {
+                if (!alive && slot < total) {
                     const uint64_t local = slot - (kBatch ? a.run_off[wrun] : 0ull);
                     if (local < rc.n_slots) {  // past n_slots: padding up to the next multiple of 64
                         i = (local >> 32) == 0 ? (uint64_t)udiv((uint32_t)local, a.pdiv) : local / rc.P;
