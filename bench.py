@@ -78,6 +78,8 @@ def parse():
     ap.add_argument("--variant", type=int, default=-1,
                     help="trajectory kernel variant (default -1: the library's autotuner chooses)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-procs", type=int, default=min(16, os.cpu_count() or 1),
+                    help="processes of the full-pass oracle run (0 to skip it)")
     ap.add_argument("--cpu-stride", type=int, default=0, help="oracle sample: every n-th release cell (0 = auto)")
     ap.add_argument("--no-batched", action="store_true", help="skip the ensemble (batched vs plain) leg")
     ap.add_argument("--no-gradient", action="store_true", help="skip the calibration-gradient leg")
@@ -87,10 +89,11 @@ def parse():
 
 
 def cpu_baseline(w, mask: np.ndarray, stride: int) -> dict:
+    """The FP32 oracle, single-threaded, on every `stride`-th release cell of the workload."""
     import oracle
     cells = np.flatnonzero(mask)
     if stride <= 0:
-        stride = max(1, len(cells) // 1500)
+        stride = 2
     sample = np.zeros(mask.size, np.uint8)
     sample[cells[::stride]] = 1
     sample = sample.reshape(mask.shape)
@@ -98,9 +101,49 @@ def cpu_baseline(w, mask: np.ndarray, stride: int) -> dict:
     t0 = time.perf_counter()
     res = oracle.trajectories(w.dem, sample, w.cell_size, p, w.particles_per_cell, w.step_limit, w.seed)
     dt = time.perf_counter() - t0
-    return {"value": res.steps / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"every {stride}th release cell ({int(sample.sum())} cells x {w.particles_per_cell} "
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
+    return {"value": res.steps / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle", "cpu": model,
+            "sample": f"1 in {stride} release cells ({int(sample.sum())} cells x {w.particles_per_cell} "
                       f"particles, {res.steps} particle-steps, {dt:.1f} s, single-threaded FP32 C oracle)"}
+
+
+def _oracle_part(args):
+    """One worker of the parallel oracle pass: the particles of a contiguous range of release cells."""
+    dem, mask_part, cell_size, params, P, S, seed = args
+    import oracle
+    r = oracle.trajectories(dem, mask_part, cell_size, oracle.make_params(**params), P, S, seed)
+    return r.counts, r.vmax, (r.steps, r.n_exit, r.n_stop, r.n_limit)
+
+
+def cpu_parallel(w, mask: np.ndarray, procs: int, gpu_counts: np.ndarray, gpu_vmax: np.ndarray) -> dict:
+    """The whole pass on the oracle, run as `procs` processes over disjoint ranges of release cells and
+    merged exactly (counts add, speeds take the maximum): a full-size CPU time and a full-size check of the
+    GPU rasters."""
+    import multiprocessing as mp
+    cells = np.flatnonzero(mask)
+    parts = []
+    for chunk in np.array_split(cells, procs):
+        m = np.zeros(mask.size, np.uint8)
+        m[chunk] = 1
+        parts.append((w.dem, m.reshape(mask.shape), w.cell_size, w.params, w.particles_per_cell, w.step_limit,
+                      w.seed))
+    ctx = mp.get_context("spawn")  # fresh interpreters: the children never touch the GPU
+    with ctx.Pool(procs) as pool:
+        pool.map(_oracle_part, parts[:1])  # start-up and library load, untimed
+        t0 = time.perf_counter()
+        out = pool.map(_oracle_part, parts)
+        dt = time.perf_counter() - t0
+    counts = np.sum([o[0] for o in out], axis=0, dtype=np.uint64).astype(np.uint32)
+    vmax = np.max([o[1] for o in out], axis=0)
+    steps = sum(o[2][0] for o in out)
+    same = bool(np.array_equal(counts, gpu_counts) and np.array_equal(vmax, gpu_vmax))
+    return {"value": steps / dt, "unit": "particle-steps/s", "processes": procs, "seconds": dt,
+            "particle_steps": int(steps), "gpu_rasters_equal_oracle": same}
 
 
 def batched_leg(avl, torch, reps: int) -> dict:
@@ -336,6 +379,9 @@ def main() -> int:
         out["gradient"] = gradient_leg(avl, torch, 5)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, mask_np, args.cpu_stride)
+        if args.cpu_procs > 0:
+            out["cpu_baseline"]["parallel_full_pass"] = cpu_parallel(
+                w, mask_np, args.cpu_procs, res.counts.cpu().numpy(), res.vmax.cpu().numpy())
     print(json.dumps(out), flush=True)
     return 0
 
