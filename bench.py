@@ -302,6 +302,7 @@ def main() -> int:
     # per-step timing: the terrain passes and the trajectory call with torch events on the stream, the
     # trajectory kernel alone with the library's events around its launch on the same stream
     t_terrain = t_traj = t_kernel = 0.0
+    kernel_ms = []
     avl.set_profiling(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -310,7 +311,8 @@ def main() -> int:
         ev[2].synchronize()
         t_terrain += ev[0].elapsed_time(ev[1])
         t_traj += ev[1].elapsed_time(ev[2])
-        t_kernel += avl.last_kernel_ms()
+        kernel_ms.append(avl.last_kernel_ms())
+        t_kernel += kernel_ms[-1]
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     avl.set_profiling(False)
@@ -356,6 +358,7 @@ def main() -> int:
             "ms_terrain_normals_mask": t_terrain / args.steps,
             "ms_trajectories_call": t_traj / args.steps,
             "ms_trajectory_kernel": t_kernel / args.steps,
+            "ms_trajectory_kernel_median": float(np.median(kernel_ms)),
             "ms_per_step_synced": wall / args.steps * 1e3,
         },
         "roofline": {
