@@ -150,6 +150,7 @@ __device__ __forceinline__ float mass_per_particle(const float* __restrict__ mas
 
 
 __global__ __launch_bounds__(kSmoothBlock) void k_smooth_forward(SmoothArgs a) {
+    if ((uint64_t)blockIdx.x >= active_blocks(a.run_off[1], kSmoothBlock)) return;  // small problems: fewer blocks
     const int lane = threadIdx.x & (kWave - 1);
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
     const RunConst rc = uniform_run(a.runs[0]);
@@ -232,6 +233,7 @@ __global__ __launch_bounds__(kSmoothBlock) void k_smooth_forward(SmoothArgs a) {
 }
 
 __global__ __launch_bounds__(kSmoothBlock) void k_smooth_backward(SmoothArgs a) {
+    if ((uint64_t)blockIdx.x >= active_blocks(a.run_off[1], kSmoothBlock)) return;  // small problems: fewer blocks
     const int lane = threadIdx.x & (kWave - 1);
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
     const RunConst rc = uniform_run(a.runs[0]);

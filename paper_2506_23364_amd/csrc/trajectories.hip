@@ -85,6 +85,10 @@ void k_trajectories(TrajArgs a) {
     const int lane = threadIdx.x & (kWave - 1);
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
     const uint64_t total = wave_bcast64(a.run_off[a.n_runs]);
+    // A small problem runs on fewer blocks: with ~1 particle per lane every wave would issue the whole
+    // iteration for a few live lanes, and the waves of a SIMD would share its issue slots until the
+    // longest path ends. Blocks past what gives each lane about kSlotsPerLane slots leave at once.
+    if ((uint64_t)blockIdx.x >= active_blocks(total, kBlock)) return;
     const int W = a.W, H = a.H;
     const float fW = (float)W, fH = (float)H;
     const uint32_t xcd = xcd_id();
