@@ -100,3 +100,20 @@ def test_terrain_calls_reject_bad_arguments(L):
     assert lib.avl_release_mask(None, FAKE, 4, 4, 30.0, 45.0, 0.0, 1.0, FAKE, None) == L.AVL_EINVAL
     assert lib.avl_release_cells(FAKE, 4, 4, FAKE, FAKE, FAKE, 10, None) == L.AVL_ENOMEM
     assert lib.avl_release_cells(None, 4, 4, FAKE, FAKE, FAKE, 1 << 20, None) == L.AVL_EINVAL
+
+
+def test_batched_workspace_size_and_padded_limits(L):
+    assert L.batched_workspace_bytes(64, 64, 0, 1, 1) == 0
+    assert L.batched_workspace_bytes(64, 64, 1, 0, 1) == 0
+    one = L.batched_workspace_bytes(64, 64, 1, 1, 1)
+    two = L.batched_workspace_bytes(64, 64, 2, 1, 1)
+    assert two - one >= 66 * 66 * 4 - 255  # one more padded tile (H + 2) x (W + 2) f32, regions 256-aligned
+    # the single-run call rejects grids whose padded DEM needs byte offsets of 2^32 or more
+    assert _traj(L, H=32768, W=32766) == -1
+
+
+def test_kernel_timing_needs_a_timed_call(L):
+    ms = ctypes.c_float(0.0)
+    assert L.lib.avl_last_kernel_ms(None) == -1
+    assert L.lib.avl_last_kernel_ms(ctypes.byref(ms)) == -1
+    assert "no timed" in L.lib.avl_last_error().decode()
