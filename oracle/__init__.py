@@ -100,6 +100,41 @@ def compact(mask: np.ndarray) -> np.ndarray:
     return out[:n].copy()
 
 
+def mipmap_levels(h: int, w: int) -> int:
+    """Levels of the overlay mipmap including the full-resolution one: halving (rounding up) until 1 x 1."""
+    n, m = 1, max(h, w)
+    while m > 1:
+        m = (m + 1) // 2
+        n += 1
+    return n
+
+
+def mipmap(counts: np.ndarray, vmax: np.ndarray):
+    """Levels 1 .. L-1 of the overlay mipmap (section 3): [(counts u64, vmax f32), ...], each level
+    halving the previous one (rounding up); counts of the up-to-4 covered cells add, speeds take the max."""
+    counts = np.ascontiguousarray(counts, dtype=np.uint32)
+    vmax = np.ascontiguousarray(vmax, dtype=np.float32)
+    h, w = counts.shape
+    L = mipmap_levels(h, w)
+    dims = []
+    hh, ww = h, w
+    for _ in range(1, L):
+        hh, ww = (hh + 1) // 2, (ww + 1) // 2
+        dims.append((hh, ww))
+    total = sum(a * b for a, b in dims)
+    cp = np.zeros(max(total, 1), dtype=np.uint64)
+    vp = np.zeros(max(total, 1), dtype=np.float32)
+    fn = _lib("f32").oracle_mipmap_f32
+    fn.restype = ctypes.c_int64
+    n = fn(_ptr(counts), _ptr(vmax), ctypes.c_int(h), ctypes.c_int(w), ctypes.c_int(L), _ptr(cp), _ptr(vp))
+    assert n == total
+    out, at = [], 0
+    for a, b in dims:
+        out.append((cp[at:at + a * b].reshape(a, b).copy(), vp[at:at + a * b].reshape(a, b).copy()))
+        at += a * b
+    return out
+
+
 @dataclass
 class RunResult:
     counts: np.ndarray

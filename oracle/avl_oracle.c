@@ -656,3 +656,41 @@ int NAME(oracle_smooth_particles)(const float* dem, const uint8_t* mask, const f
     free(trace);
     return 0;
 }
+
+/* ----------------------------------------------------------------------------------------------
+ * Multi-resolution overlay (section 3: a mipmap is computed from the full-resolution overlay).
+ * Level l + 1 halves level l, rounding up: cell (r, c) of level l + 1 covers cells 2r..2r+1 x
+ * 2c..2c+1 of level l, those that exist. Entry counts add (64-bit); speeds take the maximum.
+ * Levels 1 .. n_levels - 1 are written one after the other, each row-major.
+ * ---------------------------------------------------------------------------------------------- */
+int64_t NAME(oracle_mipmap)(const uint32_t* counts, const float* vmax, int H, int W, int n_levels, uint64_t* cpyr,
+                            float* vpyr)
+{
+    int h = H, w = W;
+    int64_t at = 0, prev = -1; /* start of the previous level in the output (-1: the input) */
+    for (int l = 1; l < n_levels; ++l) {
+        const int h2 = (h + 1) / 2, w2 = (w + 1) / 2;
+        for (int r = 0; r < h2; ++r)
+            for (int c = 0; c < w2; ++c) {
+                uint64_t sum = 0;
+                float mx = 0.0f;
+                for (int dr = 0; dr < 2; ++dr)
+                    for (int dc = 0; dc < 2; ++dc) {
+                        const int rr = 2 * r + dr, cc = 2 * c + dc;
+                        if (rr >= h || cc >= w) continue;
+                        const size_t i = (size_t)rr * w + cc;
+                        const uint64_t cnt = prev < 0 ? (uint64_t)counts[i] : cpyr[prev + i];
+                        const float v = prev < 0 ? vmax[i] : vpyr[prev + i];
+                        sum += cnt;
+                        if (v > mx) mx = v;
+                    }
+                cpyr[at + (size_t)r * w2 + c] = sum;
+                vpyr[at + (size_t)r * w2 + c] = mx;
+            }
+        prev = at;
+        at += (int64_t)h2 * w2;
+        h = h2;
+        w = w2;
+    }
+    return at;
+}
