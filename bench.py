@@ -146,6 +146,44 @@ def cpu_parallel(w, mask: np.ndarray, procs: int, gpu_counts: np.ndarray, gpu_vm
             "particle_steps": int(steps), "gpu_rasters_equal_oracle": same}
 
 
+def mipmap_leg(avl, torch, res, reps: int) -> dict:
+    """The multi-resolution overlay of the pass's rasters: every coarser level of counts and speeds.
+    Timed as replays of a captured HIP graph of the call (two kernel launches), so host overhead is out."""
+    h, w = res.counts.shape
+    n = h * w
+    levels = int(avl.lib.avl_mipmap_levels(h, w))
+    cells = int(avl.lib.avl_mipmap_cells(h, w))
+    cp = torch.empty(cells, dtype=torch.uint64, device="cuda")
+    vp = torch.empty(cells, dtype=torch.float32, device="cuda")
+    stream = torch.cuda.Stream()
+
+    def call():
+        rc = avl.lib.avl_overlay_mipmap(res.counts.data_ptr(), res.vmax.data_ptr(), h, w, cp.data_ptr(), vp.data_ptr(),
+                                        stream.cuda_stream)
+        assert rc == 0, rc
+
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        call()
+        stream.synchronize()
+        eager = vp.clone()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=stream):
+            call()
+        g.replay()
+        stream.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            g.replay()
+        e1.record(stream)
+        e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    nbytes = 8 * n + 12 * cells  # read level 0 (u32 + f32), write every coarser level (u64 + f32)
+    return {"levels": levels, "ms": ms, "algorithmic_bytes": nbytes, "achieved_GBs": nbytes / ms / 1e6,
+            "peak_GBs": HBM_PEAK_GBS, "replay_equals_eager": bool(torch.equal(eager, vp))}
+
+
 def batched_leg(avl, torch, reps: int) -> dict:
     """Ensemble sweep: 16 ridged-fBm tiles of 1024^2 at 10 m, one release scenario each (103-26,397
     cells), crossed with 64 (mu, xi, h) sets: 1024 runs of 32 particles per cell and 2000 steps. Timed
@@ -376,6 +414,7 @@ def main() -> int:
                          "peak_GBs": HBM_PEAK_GBS},
         },
     }
+    out["mipmap"] = mipmap_leg(avl, torch, res, 20)
     if not args.no_batched:
         out["batched"] = batched_leg(avl, torch, 3)
     if not args.no_gradient:

@@ -177,6 +177,19 @@ AVL_API int avl_trajectories_backward(const float* dem, const uint8_t* mask, con
                                       const float* grad_deposit, double* dparams, float* dmass, float* per_particle,
                                       void* workspace, size_t workspace_bytes, void* stream);
 
+/* Overlay mipmap (section 3: a mipmap of the full-resolution overlay texture is the multi-resolution
+ * overlay the renderer samples). Level l + 1 halves level l, rounding up: its cell (r, c) covers cells
+ * 2r..2r+1 x 2c..2c+1 of level l that exist. Entry counts add (uint64, so a coarse level cannot
+ * overflow); speeds take the maximum. Levels 1 .. L-1 (L = avl_mipmap_levels(H, W), level 0 being the
+ * input) are written one after the other, each row-major: counts_pyr and vmax_pyr hold
+ * avl_mipmap_cells(H, W) entries (a grid of one cell has no coarser level and writes nothing).
+ * counts (H*W uint32) and vmax (H*W float) as written by avl_trajectories; device pointers; H, W >= 1,
+ * H*W < 2^31. Asynchronous on `stream`. */
+AVL_API int32_t avl_mipmap_levels(int32_t H, int32_t W);
+AVL_API int64_t avl_mipmap_cells(int32_t H, int32_t W);
+AVL_API int avl_overlay_mipmap(const uint32_t* counts, const float* vmax, int32_t H, int32_t W, uint64_t* counts_pyr,
+                               float* vmax_pyr, void* stream);
+
 /* Tuning controls. variant: -1 = autotune (default: the first call per device and problem-size bucket
  * times every kernel variant and keeps the fastest; all variants give identical results), or a fixed
  * variant index in [0, avl_tuning_variants()). graphs: 1 = capture batched calls into HIP graphs

@@ -18,7 +18,7 @@ import torch
 
 __all__ = ["AvlError", "Params", "Run", "normals", "release_mask", "release_cells", "trajectories",
            "trajectories_batched", "trajectories_smooth", "trajectories_backward", "smooth_deposit", "SmoothDeposit",
-           "overlay", "workspace_bytes", "batched_workspace_bytes", "smooth_workspace_bytes", "set_tuning",
+           "overlay", "overlay_mipmap", "workspace_bytes", "batched_workspace_bytes", "smooth_workspace_bytes", "set_tuning",
            "tuning_variants", "last_variant", "LIB_PATH", "lib"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libavl.so")
@@ -66,6 +66,11 @@ def _load() -> ctypes.CDLL:
     L.avl_release_cells.argtypes = [vp, i32, i32, vp, vp, vp, sz, vp]
     L.avl_trajectories.argtypes = [vp, vp, i32, i32, f32, ctypes.POINTER(Params), u32, u32, u64, u32, vp, vp, vp,
                                    vp, sz, vp]
+    L.avl_mipmap_levels.argtypes = [i32, i32]
+    L.avl_mipmap_levels.restype = i32
+    L.avl_mipmap_cells.argtypes = [i32, i32]
+    L.avl_mipmap_cells.restype = ctypes.c_int64
+    L.avl_overlay_mipmap.argtypes = [vp, vp, i32, i32, vp, vp, vp]
     L.avl_set_profiling.argtypes = [i32]
     L.avl_last_kernel_ms.argtypes = [ctypes.POINTER(ctypes.c_float)]
     L.avl_batched_workspace_bytes.argtypes = [i32, i32, i32, i32, i32]
@@ -153,6 +158,29 @@ def tuning_variants() -> int:
 
 def last_variant() -> int:
     return int(lib.avl_last_variant())
+
+
+def overlay_mipmap(counts: torch.Tensor, vmax: torch.Tensor):
+    """Levels 1 .. L-1 of the overlay mipmap of (H, W) uint32 counts and float32 speeds: a list of
+    (counts uint64, vmax float32) pairs, each level halving the previous one (rounding up)."""
+    _need(counts, "counts", torch.uint32, 2)
+    _need(vmax, "vmax", torch.float32, 2)
+    h, w = counts.shape
+    if tuple(vmax.shape) != (h, w):
+        raise ValueError("counts and vmax must have the same shape")
+    n = int(lib.avl_mipmap_cells(h, w))
+    dev = counts.device
+    cp = torch.empty(max(n, 1), dtype=torch.uint64, device=dev)
+    vp = torch.empty(max(n, 1), dtype=torch.float32, device=dev)
+    with torch.cuda.device(dev):
+        _check(lib.avl_overlay_mipmap(counts.data_ptr(), vmax.data_ptr(), h, w, cp.data_ptr(), vp.data_ptr(),
+                                      _stream(dev)), "avl_overlay_mipmap")
+    out, at = [], 0
+    while h > 1 or w > 1:
+        h, w = (h + 1) // 2, (w + 1) // 2
+        out.append((cp[at:at + h * w].view(h, w), vp[at:at + h * w].view(h, w)))
+        at += h * w
+    return out
 
 
 def set_profiling(enable: bool) -> None:

@@ -300,6 +300,63 @@ int avl_set_tuning(int32_t variant, int32_t graphs) {
 
 int32_t avl_tuning_variants(void) { return avl::trajectory_variants(); }
 
+int32_t avl_mipmap_levels(int32_t H, int32_t W) {
+    if (H < 1 || W < 1) return 0;
+    int32_t n = 1;
+    for (int32_t m = H > W ? H : W; m > 1; m = (m + 1) / 2) ++n;
+    return n;
+}
+
+int64_t avl_mipmap_cells(int32_t H, int32_t W) {
+    if (H < 1 || W < 1) return 0;
+    int64_t total = 0, h = H, w = W;
+    while (h > 1 || w > 1) {
+        h = (h + 1) / 2;
+        w = (w + 1) / 2;
+        total += h * w;
+    }
+    return total;
+}
+
+int avl_overlay_mipmap(const uint32_t* counts, const float* vmax, int32_t H, int32_t W, uint64_t* counts_pyr,
+                       float* vmax_pyr, void* stream) {
+    g_last_error.clear();
+    if (!counts || !vmax || !counts_pyr || !vmax_pyr) return fail(AVL_EINVAL, "avl_overlay_mipmap: null pointer");
+    if (!grid_ok(H, W, 1)) return fail(AVL_EINVAL, "avl_overlay_mipmap: need H, W >= 1 and H*W < 2^31");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int32_t L = avl_mipmap_levels(H, W);
+    const void* cin = counts;
+    bool cin64 = false;
+    const float* vin = vmax;
+    int h0 = H, w0 = W, done = 1;
+    int64_t at = 0;
+    auto* cp = reinterpret_cast<unsigned long long*>(counts_pyr);
+    while (done < L) {
+        avl::MipLevels o{};
+        const int nlev = (L - done) < avl::kMipPass ? (L - done) : avl::kMipPass;
+        int h = h0, w = w0;
+        for (int l = 0; l < nlev; ++l) {
+            h = (h + 1) / 2;
+            w = (w + 1) / 2;
+            o.c[l] = cp + at;
+            o.v[l] = vmax_pyr + at;
+            o.h[l] = h;
+            o.w[l] = w;
+            at += (int64_t)h * w;
+        }
+        hipError_t e;
+        if ((e = avl::launch_mip_pass(cin, cin64, vin, h0, w0, nlev, o, s)) != hipSuccess)
+            return hip_fail(e, "avl_overlay_mipmap");
+        cin = o.c[nlev - 1];
+        cin64 = true;
+        vin = o.v[nlev - 1];
+        h0 = o.h[nlev - 1];
+        w0 = o.w[nlev - 1];
+        done += nlev;
+    }
+    return AVL_OK;
+}
+
 int32_t avl_last_variant(void) { return g_last_variant; }
 
 int avl_set_profiling(int32_t enable) {

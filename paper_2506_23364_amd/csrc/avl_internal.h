@@ -128,6 +128,15 @@ hipError_t launch_release_mask(const float* normals4, const float* dem, int64_t 
                                float zmin, float zmax, uint8_t* mask, hipStream_t s);
 hipError_t launch_compact(const uint8_t* mask, int64_t n, int32_t* cells, int32_t* n_cells, uint32_t* blk,
                           hipStream_t s);
+// Overlay mipmap: up to kMipPass output levels per pass (a 32 x 32 tile of the first halves to 1 x 1).
+constexpr int kMipPass = 6;
+struct MipLevels {
+    unsigned long long* c[kMipPass];
+    float* v[kMipPass];
+    int h[kMipPass], w[kMipPass];
+};
+hipError_t launch_mip_pass(const void* cin, bool cin64, const float* vin, int h0, int w0, int nlev,
+                           const MipLevels& o, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t n, hipStream_t s);
 // (H + 2) x (W + 2) copy of the DEM with the edge texels replicated into a one-texel border.

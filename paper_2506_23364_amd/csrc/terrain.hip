@@ -275,6 +275,84 @@ hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t 
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------------------------------------ mipmap
+
+// Up to kMipPass levels of the overlay mipmap in one pass. A block owns a 32 x 32 tile of the pass's
+// first output level (a 64 x 64 tile of its input) and every coarser cell of that tile down to 1 x 1:
+// each level halves the previous one rounding up, so the children of a cell never leave the tile.
+// Counts add in 64 bits; speeds (>= 0) take the maximum; cells past a level's edge count as empty.
+template <typename Tin>
+__global__ __launch_bounds__(256) void k_mip(const Tin* __restrict__ cin, const float* __restrict__ vin, int h0, int w0,
+                                             int nlev, MipLevels o) {
+    __shared__ unsigned long long sc[32 * 32];
+    __shared__ float sv[32 * 32];
+    const int tr = blockIdx.y * 32, tc = blockIdx.x * 32;
+    for (int k = threadIdx.x; k < 32 * 32; k += 256) {
+        const int r = tr + k / 32, c = tc + k % 32;
+        unsigned long long sum = 0;
+        float mx = 0.0f;
+        if (r < o.h[0] && c < o.w[0]) {
+#pragma unroll
+            for (int dr = 0; dr < 2; ++dr)
+#pragma unroll
+                for (int dc = 0; dc < 2; ++dc) {
+                    const int rr = 2 * r + dr, cc = 2 * c + dc;
+                    if (rr < h0 && cc < w0) {
+                        const size_t i = (size_t)rr * w0 + cc;
+                        sum += (unsigned long long)cin[i];
+                        mx = fmaxf(mx, vin[i]);
+                    }
+                }
+            o.c[0][(size_t)r * o.w[0] + c] = sum;
+            o.v[0][(size_t)r * o.w[0] + c] = mx;
+        }
+        sc[k] = sum;
+        sv[k] = mx;
+    }
+    __syncthreads();
+    int side = 32;
+    for (int l = 1; l < nlev; ++l) {
+        const int s2 = side / 2;
+        const int t = threadIdx.x;
+        unsigned long long sum = 0;
+        float mx = 0.0f;
+        const int i = t / s2, j = t - (t / s2) * s2;
+        if (t < s2 * s2) {
+#pragma unroll
+            for (int dr = 0; dr < 2; ++dr)
+#pragma unroll
+                for (int dc = 0; dc < 2; ++dc) {
+                    sum += sc[(2 * i + dr) * side + 2 * j + dc];
+                    mx = fmaxf(mx, sv[(2 * i + dr) * side + 2 * j + dc]);
+                }
+        }
+        __syncthreads();
+        if (t < s2 * s2) {
+            sc[i * s2 + j] = sum;
+            sv[i * s2 + j] = mx;
+            const int r = blockIdx.y * s2 + i, c = blockIdx.x * s2 + j;
+            if (r < o.h[l] && c < o.w[l]) {
+                o.c[l][(size_t)r * o.w[l] + c] = sum;
+                o.v[l][(size_t)r * o.w[l] + c] = mx;
+            }
+        }
+        __syncthreads();
+        side = s2;
+    }
+}
+
+hipError_t launch_mip_pass(const void* cin, bool cin64, const float* vin, int h0, int w0, int nlev,
+                           const MipLevels& o, hipStream_t s) {
+    const dim3 grid((unsigned)((o.w[0] + 31) / 32), (unsigned)((o.h[0] + 31) / 32));
+    if (cin64)
+        hipLaunchKernelGGL(k_mip<unsigned long long>, grid, dim3(256), 0, s,
+                           static_cast<const unsigned long long*>(cin), vin, h0, w0, nlev, o);
+    else
+        hipLaunchKernelGGL(k_mip<uint32_t>, grid, dim3(256), 0, s, static_cast<const uint32_t*>(cin), vin, h0, w0,
+                           nlev, o);
+    return hipGetLastError();
+}
+
 hipError_t launch_finalize_vmax(uint32_t* vmax_bits, int64_t n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_finalize_vmax, dim3(blocks_for(n, 4)), dim3(256), 0, s, vmax_bits, n);

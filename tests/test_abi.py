@@ -117,3 +117,21 @@ def test_kernel_timing_needs_a_timed_call(L):
     assert L.lib.avl_last_kernel_ms(None) == -1
     assert L.lib.avl_last_kernel_ms(ctypes.byref(ms)) == -1
     assert "no timed" in L.lib.avl_last_error().decode()
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (1, 2), (3, 5), (37, 53), (2048, 2048), (1, 100000), (8193, 3)])
+def test_mipmap_level_count_and_size(L, shape):
+    import oracle
+    h, w = shape
+    assert L.lib.avl_mipmap_levels(h, w) == oracle.mipmap_levels(h, w)
+    cells, hh, ww = 0, h, w
+    while hh > 1 or ww > 1:
+        hh, ww = (hh + 1) // 2, (ww + 1) // 2
+        cells += hh * ww
+    assert L.lib.avl_mipmap_cells(h, w) == cells
+
+
+def test_mipmap_rejects_bad_arguments(L):
+    assert L.lib.avl_overlay_mipmap(None, FAKE, 4, 4, FAKE, FAKE, None) == -1
+    assert L.lib.avl_overlay_mipmap(FAKE, FAKE, 0, 4, FAKE, FAKE, None) == -1
+    assert L.lib.avl_mipmap_levels(0, 3) == 0 and L.lib.avl_mipmap_cells(3, 0) == 0
