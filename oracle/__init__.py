@@ -90,6 +90,19 @@ def release_mask(nrm: np.ndarray, dem: np.ndarray, smin: float, smax: float, zmi
     return out
 
 
+def release_mask_fine(nrm: np.ndarray, dem: np.ndarray, mult: int, smin: float, smax: float, zmin: float,
+                      zmax: float, prec: str = "f32") -> np.ndarray:
+    """Release map at mult x mult texels per DEM cell: uint8 (mult*H, mult*W)."""
+    nrm = np.ascontiguousarray(nrm, dtype=_real(prec))
+    dem = np.ascontiguousarray(dem, dtype=np.float32)
+    h, w = dem.shape
+    out = np.zeros((h * mult, w * mult), dtype=np.uint8)
+    getattr(_lib(prec), f"oracle_release_mask_fine_{prec}")(
+        _ptr(nrm), _ptr(dem), ctypes.c_int(h), ctypes.c_int(w), ctypes.c_int(mult), ctypes.c_float(smin),
+        ctypes.c_float(smax), ctypes.c_float(zmin), ctypes.c_float(zmax), _ptr(out))
+    return out
+
+
 def compact(mask: np.ndarray) -> np.ndarray:
     mask = np.ascontiguousarray(mask, dtype=np.uint8)
     h, w = mask.shape
@@ -162,6 +175,25 @@ def trajectories(dem: np.ndarray, mask: np.ndarray, cell_size: float, params: Or
     return RunResult(counts, vmax, int(stats[0]), int(stats[1]), int(stats[2]), int(stats[3]))
 
 
+def trajectories_fine(dem: np.ndarray, mask: np.ndarray, mult: int, cell_size: float, params: OracleParams,
+                      particles_per_cell: int, step_limit: int, seed: int, run: int = 0,
+                      prec: str = "f32") -> RunResult:
+    """Run from a release texture with mult x mult texels per DEM cell (mask (mult*H, mult*W)); the
+    rasters are (H, W)."""
+    dem = np.ascontiguousarray(dem, dtype=np.float32)
+    mask = np.ascontiguousarray(mask, dtype=np.uint8)
+    h, w = dem.shape
+    assert mask.shape == (h * mult, w * mult)
+    counts = np.zeros((h, w), dtype=np.uint32)
+    vmax = np.zeros((h, w), dtype=_real(prec))
+    stats = np.zeros(4, dtype=np.uint64)
+    getattr(_lib(prec), f"oracle_trajectories_fine_{prec}")(
+        _ptr(dem), _ptr(mask), ctypes.c_int(h), ctypes.c_int(w), ctypes.c_int(mult), ctypes.c_float(cell_size),
+        ctypes.byref(params), ctypes.c_uint32(particles_per_cell), ctypes.c_uint32(step_limit),
+        ctypes.c_uint64(seed), ctypes.c_uint32(run), _ptr(counts), _ptr(vmax), _ptr(stats))
+    return RunResult(counts, vmax, int(stats[0]), int(stats[1]), int(stats[2]), int(stats[3]))
+
+
 @dataclass
 class Trace:
     rows: np.ndarray  # (n, 8): x, y, z, gx, gy, dx, dy, v2
@@ -182,17 +214,20 @@ class Trace:
 
 
 def trace(dem: np.ndarray, cell_size: float, params: OracleParams, r: int, c: int, replica: int,
-          step_limit: int, seed: int, run: int = 0, prec: str = "f32") -> Trace:
+          step_limit: int, seed: int, run: int = 0, prec: str = "f32", mult: int = 1) -> Trace:
+    """Path of one particle: replica `replica` of release texel (r, c) of a release texture with mult x mult
+    texels per DEM cell (mult = 1: DEM cell (r, c))."""
     dem = np.ascontiguousarray(dem, dtype=np.float32)
     h, w = dem.shape
     buf = np.zeros((step_limit + 1, 8), dtype=_real(prec))
     reason = ctypes.c_int32(0)
     steps = ctypes.c_uint64(0)
-    fn = getattr(_lib(prec), f"oracle_trace_{prec}")
+    fn = getattr(_lib(prec), f"oracle_trace_fine_{prec}")
     fn.restype = ctypes.c_int64
     n = fn(_ptr(dem), ctypes.c_int(h), ctypes.c_int(w), ctypes.c_float(cell_size), ctypes.byref(params),
-           ctypes.c_int(r), ctypes.c_int(c), ctypes.c_uint32(replica), ctypes.c_uint32(step_limit),
-           ctypes.c_uint64(seed), ctypes.c_uint32(run), _ptr(buf), ctypes.byref(reason), ctypes.byref(steps))
+           ctypes.c_int(r), ctypes.c_int(c), ctypes.c_int(mult), ctypes.c_uint32(replica),
+           ctypes.c_uint32(step_limit), ctypes.c_uint64(seed), ctypes.c_uint32(run), _ptr(buf), ctypes.byref(reason),
+           ctypes.byref(steps))
     return Trace(buf[:n].copy(), int(reason.value), int(steps.value))
 
 

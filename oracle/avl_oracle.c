@@ -71,7 +71,8 @@ static real unit24(uint32_t u) { return (real)(u >> 8) * R(0x1p-24); }
 
 /* The two uniforms of step n of particle (cell, replica) in run `run`: one Philox block serves two
  * consecutive steps; even steps take words 0 and 1, odd steps words 2 and 3. Counter = (n/2, replica,
- * release cell index r*W+c, run), key = the 64-bit seed as (low, high) words. */
+ * index of the release texel in the release texture (r*W+c at the DEM's resolution), run), key = the
+ * 64-bit seed as (low, high) words. */
 static void draw(uint32_t n, uint32_t replica, uint32_t cell, uint32_t run, uint64_t seed, real* rx, real* ry)
 {
     uint32_t ctr[4] = {n >> 1, replica, cell, run};
@@ -134,6 +135,42 @@ void NAME(oracle_release_mask)(const real* normals4, const float* dem, int H, in
         real z = (real)dem[i];
         mask[i] = (cmin <= nz && nz <= cmax && (real)z_min <= z && z <= (real)z_max) ? 1 : 0;
     }
+}
+
+/* Release map at a finer texture resolution (section 5.2: the user picks the texture resolution at which
+ * release points are evaluated). The release texture has mult x mult texels per DEM cell; texel (R, C) of
+ * the (mult*H) x (mult*W) grid is centred at ((C + 1/2) / mult, (R + 1/2) / mult) in DEM cell units. There
+ * nz and the elevation are read with bilinear filtering between texel centres and clamped indices (what a
+ * texture sampler with linear filtering and clamp-to-edge addressing returns), and the test of
+ * oracle_release_mask is applied to the filtered values. nz is filtered as a scalar, not renormalised. With
+ * mult = 1 every centre falls on a texel centre, the weights are zero and the map is oracle_release_mask's. */
+void NAME(oracle_release_mask_fine)(const real* normals4, const float* dem, int H, int W, int mult,
+                                    float smin_deg, float smax_deg, float z_min, float z_max, uint8_t* mask)
+{
+    const double d2r = 3.14159265358979323846 / 180.0;
+    const real cmin = (real)cos((double)smax_deg * d2r);
+    const real cmax = (real)cos((double)smin_deg * d2r);
+    const int Hf = H * mult, Wf = W * mult;
+    for (int rr = 0; rr < Hf; ++rr)
+        for (int cc = 0; cc < Wf; ++cc) {
+            real x = ((real)cc + R(0.5)) / (real)mult, y = ((real)rr + R(0.5)) / (real)mult;
+            real sx = x - R(0.5), sy = y - R(0.5);
+            real fc = FLOOR(sx), fr = FLOOR(sy);
+            real fx = sx - fc, fy = sy - fr;
+            int c0 = (int)fc, r0 = (int)fr;
+            size_t ca = (size_t)clampi(c0, 0, W - 1), cb = (size_t)clampi(c0 + 1, 0, W - 1);
+            size_t ra = (size_t)clampi(r0, 0, H - 1), rb = (size_t)clampi(r0 + 1, 0, H - 1);
+            real n00 = normals4[4 * (ra * W + ca) + 2], n01 = normals4[4 * (ra * W + cb) + 2];
+            real n10 = normals4[4 * (rb * W + ca) + 2], n11 = normals4[4 * (rb * W + cb) + 2];
+            real ntop = n00 + fx * (n01 - n00), nbot = n10 + fx * (n11 - n10);
+            real nz = ntop + fy * (nbot - ntop);
+            real z00 = (real)dem[ra * W + ca], z01 = (real)dem[ra * W + cb];
+            real z10 = (real)dem[rb * W + ca], z11 = (real)dem[rb * W + cb];
+            real ztop = z00 + fx * (z01 - z00), zbot = z10 + fx * (z11 - z10);
+            real z = ztop + fy * (zbot - ztop);
+            mask[(size_t)rr * Wf + cc] =
+                (cmin <= nz && nz <= cmax && (real)z_min <= z && z <= (real)z_max) ? 1 : 0;
+        }
 }
 
 /* Release-cell list: linear indices r*W+c of the set cells of the mask in row-major order. */
@@ -221,16 +258,20 @@ static void splat(const model* m, int64_t* q, real* f, real x, real y, real val)
 
 #define TRACE_COLS 8 /* x, y, z, gx, gy, dx, dy, v2 */
 
-/* One particle: released at the centre of cell (r, c), replica `replica`. Adds its cell entries to
- * counts and its per-cell maximum of v^2 to vmax2 (either may be NULL). With a trace buffer of
- * (S+1) rows, row 0 is the released state and row n+1 the state after step n. Returns the end reason;
- * *steps gets the number of steps entered (the terminating one included); *rows the trace rows. */
-static int particle(const model* m, int r, int c, uint32_t replica, uint32_t* counts, real* vmax2,
-                    uint64_t* steps, real* trace, int64_t* rows, end_info* ei, int64_t* vel_q, real* vel, real mp)
+/* One particle, replica `replica` of release texel (tr, tc) of a release texture with mult x mult texels
+ * per DEM cell: it starts at the texel's centre ((tc + 1/2) / mult, (tr + 1/2) / mult) in DEM cell units,
+ * inside DEM cell (tr / mult, tc / mult), and its random stream is keyed by the texel's index
+ * tr * (mult * W) + tc in the release texture (mult = 1: the centre and index of DEM cell (tr, tc)). Adds
+ * its cell entries to counts and its per-cell maximum of v^2 to vmax2 (either may be NULL). With a trace
+ * buffer of (S+1) rows, row 0 is the released state and row n+1 the state after step n. Returns the end
+ * reason; *steps gets the number of steps entered (the terminating one included); *rows the trace rows. */
+static int particle_at(const model* m, int tr, int tc, int mult, uint32_t replica, uint32_t* counts, real* vmax2,
+                       uint64_t* steps, real* trace, int64_t* rows, end_info* ei, int64_t* vel_q, real* vel,
+                       real mp)
 {
     const int W = m->W, H = m->H;
-    const uint32_t cell_id = (uint32_t)r * (uint32_t)W + (uint32_t)c;
-    real x = (real)c + R(0.5), y = (real)r + R(0.5);
+    const uint32_t cell_id = (uint32_t)tr * (uint32_t)(W * mult) + (uint32_t)tc;
+    real x = ((real)tc + R(0.5)) / (real)mult, y = ((real)tr + R(0.5)) / (real)mult;
     real z, gx, gy;
     sample(m, x, y, &z, &gx, &gy);
     const real x0 = x, y0 = y, zr = z;
@@ -245,7 +286,7 @@ static int particle(const model* m, int r, int c, uint32_t replica, uint32_t* co
         }
     }
     real v2 = 0;
-    int cr = r, cc = c;
+    int cr = tr / mult, cc = tc / mult;
     if (counts) counts[(size_t)cr * W + cc] += 1; /* entry into the release cell, with v = 0 */
     int64_t nrow = 0;
     if (trace) {
@@ -310,24 +351,34 @@ static int particle(const model* m, int r, int c, uint32_t replica, uint32_t* co
     return reason;
 }
 
-/* Whole run: particles_per_cell replicas from every set cell of the mask, cells in row-major order.
- * counts (u32) and vmax (real) are H*W and fully overwritten; vmax is sqrt of the per-cell max of v^2
- * (0 where no particle came). stats (may be NULL) gets {steps, ended by grid exit, by stop, by limit}. */
-int NAME(oracle_trajectories)(const float* dem, const uint8_t* mask, int H, int W, float cell_size,
-                              const oracle_params* p, uint32_t particles_per_cell, uint32_t step_limit,
-                              uint64_t seed, uint32_t run, uint32_t* counts, real* vmax, uint64_t* stats)
+/* a particle released at the centre of DEM cell (r, c) */
+static int particle(const model* m, int r, int c, uint32_t replica, uint32_t* counts, real* vmax2,
+                    uint64_t* steps, real* trace, int64_t* rows, end_info* ei, int64_t* vel_q, real* vel, real mp)
+{
+    return particle_at(m, r, c, 1, replica, counts, vmax2, steps, trace, rows, ei, vel_q, vel, mp);
+}
+
+/* Whole run from a release texture with mult x mult texels per DEM cell (mask: (mult*H) x (mult*W)):
+ * particles_per_cell replicas from every set texel, texels in row-major order. counts (u32) and vmax
+ * (real) are H*W DEM rasters, fully overwritten; vmax is sqrt of the per-cell max of v^2 (0 where no
+ * particle came). stats (may be NULL) gets {steps, ended by grid exit, by stop, by limit}. */
+int NAME(oracle_trajectories_fine)(const float* dem, const uint8_t* mask, int H, int W, int mult,
+                                   float cell_size, const oracle_params* p, uint32_t particles_per_cell,
+                                   uint32_t step_limit, uint64_t seed, uint32_t run, uint32_t* counts, real* vmax,
+                                   uint64_t* stats)
 {
     model m;
     model_init(&m, dem, H, W, cell_size, p, step_limit, seed, run);
     const size_t N = (size_t)H * W;
+    const int Hf = H * mult, Wf = W * mult;
     memset(counts, 0, N * sizeof(uint32_t));
     for (size_t i = 0; i < N; ++i) vmax[i] = 0; /* holds v^2 until the end */
     uint64_t st[4] = {0, 0, 0, 0};
-    for (int r = 0; r < H; ++r)
-        for (int c = 0; c < W; ++c) {
-            if (!mask[(size_t)r * W + c]) continue;
+    for (int r = 0; r < Hf; ++r)
+        for (int c = 0; c < Wf; ++c) {
+            if (!mask[(size_t)r * Wf + c]) continue;
             for (uint32_t j = 0; j < particles_per_cell; ++j) {
-                int why = particle(&m, r, c, j, counts, vmax, &st[0], NULL, NULL, NULL, NULL, NULL, 0);
+                int why = particle_at(&m, r, c, mult, j, counts, vmax, &st[0], NULL, NULL, NULL, NULL, NULL, 0);
                 st[why == END_EXIT ? 1 : (why == END_LIMIT ? 3 : 2)] += 1;
             }
         }
@@ -336,20 +387,40 @@ int NAME(oracle_trajectories)(const float* dem, const uint8_t* mask, int H, int 
     return 0;
 }
 
-/* Trace of one particle: trace must hold (step_limit+1)*8 reals. Returns the number of rows written;
+/* Whole run from a release map at the DEM's resolution: particles_per_cell replicas from the centre of
+ * every set cell of the mask (H*W), cells in row-major order. */
+int NAME(oracle_trajectories)(const float* dem, const uint8_t* mask, int H, int W, float cell_size,
+                              const oracle_params* p, uint32_t particles_per_cell, uint32_t step_limit,
+                              uint64_t seed, uint32_t run, uint32_t* counts, real* vmax, uint64_t* stats)
+{
+    return NAME(oracle_trajectories_fine)(dem, mask, H, W, 1, cell_size, p, particles_per_cell, step_limit, seed,
+                                          run, counts, vmax, stats);
+}
+
+/* Trace of one particle (replica `replica` of release texel (tr, tc) at mult texels per DEM cell, as in
+ * particle_at): trace must hold (step_limit+1)*8 reals. Returns the number of rows written;
  * *reason gets 0 (step limit), 1 (left the grid) or 2 (stopped); *steps the steps entered. */
-int64_t NAME(oracle_trace)(const float* dem, int H, int W, float cell_size, const oracle_params* p,
-                           int r, int c, uint32_t replica, uint32_t step_limit, uint64_t seed, uint32_t run,
-                           real* trace, int32_t* reason, uint64_t* steps)
+int64_t NAME(oracle_trace_fine)(const float* dem, int H, int W, float cell_size, const oracle_params* p,
+                                int tr, int tc, int mult, uint32_t replica, uint32_t step_limit, uint64_t seed,
+                                uint32_t run, real* trace, int32_t* reason, uint64_t* steps)
 {
     model m;
     model_init(&m, dem, H, W, cell_size, p, step_limit, seed, run);
     int64_t rows = 0;
     uint64_t st = 0;
-    *reason = particle(&m, r, c, replica, NULL, NULL, &st, trace, &rows, NULL, NULL, NULL, 0);
+    *reason = particle_at(&m, tr, tc, mult, replica, NULL, NULL, &st, trace, &rows, NULL, NULL, NULL, 0);
     if (*reason == END_ANGLE) *reason = END_STOP;
     *steps = st;
     return rows;
+}
+
+/* the same for a particle released at the centre of DEM cell (r, c) */
+int64_t NAME(oracle_trace)(const float* dem, int H, int W, float cell_size, const oracle_params* p,
+                           int r, int c, uint32_t replica, uint32_t step_limit, uint64_t seed, uint32_t run,
+                           real* trace, int32_t* reason, uint64_t* steps)
+{
+    return NAME(oracle_trace_fine)(dem, H, W, cell_size, p, r, c, 1, replica, step_limit, seed, run, trace, reason,
+                                   steps);
 }
 
 /* ----------------------------------------------------------------------------------------------
