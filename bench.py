@@ -184,6 +184,40 @@ def mipmap_leg(avl, torch, res, reps: int) -> dict:
             "peak_GBs": HBM_PEAK_GBS, "replay_equals_eager": bool(torch.equal(eager, vp))}
 
 
+def fine_leg(avl, torch, w, dem, reps: int, mult: int = 2, per_texel: int = 64) -> dict:
+    """The same tile and release rule evaluated on a release texture with mult x mult texels per DEM cell,
+    with per_texel particles per release texel (mult^2 * per_texel = the plain pass's particles per cell):
+    the fine release map and the trajectory pass from it."""
+    params = avl.Params.make(**w.params)
+    nrm = avl.normals(dem, w.cell_size)
+    stream = torch.cuda.current_stream()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    mask = avl.release_mask_fine(nrm, dem, mult, w.slope_min_deg, w.slope_max_deg, w.z_min, w.z_max)
+    res = avl.trajectories_fine(dem, mask, mult, w.cell_size, params, per_texel, w.step_limit, w.seed)
+    torch.cuda.synchronize()
+    map_ms, kern_ms = [], []
+    avl.set_profiling(True)
+    for _ in range(reps):
+        e[0].record(stream)
+        mask = avl.release_mask_fine(nrm, dem, mult, w.slope_min_deg, w.slope_max_deg, w.z_min, w.z_max)
+        e[1].record(stream)
+        res = avl.trajectories_fine(dem, mask, mult, w.cell_size, params, per_texel, w.step_limit, w.seed, 0, res)
+        torch.cuda.synchronize()
+        map_ms.append(e[0].elapsed_time(e[1]))
+        kern_ms.append(avl.last_kernel_ms())
+    avl.set_profiling(False)
+    texels = int(mask.count_nonzero().item())
+    steps = int(res.stats[0].item())
+    h, wd = dem.shape
+    fine_cells = h * wd * mult * mult
+    map_bytes = 20 * h * wd + fine_cells  # normals and heights once, one byte per release texel
+    kms = float(np.mean(kern_ms))
+    return {"mult": mult, "particles_per_texel": per_texel, "release_texels": texels,
+            "particles": texels * per_texel, "particle_steps_per_pass": steps,
+            "ms_release_map": float(np.mean(map_ms)), "release_map_GBs": map_bytes / float(np.mean(map_ms)) / 1e6,
+            "ms_trajectory_kernel": kms, "particle_steps_per_s": steps / (kms * 1e-3)}
+
+
 def batched_leg(avl, torch, reps: int) -> dict:
     """Ensemble sweep: 16 ridged-fBm tiles of 1024^2 at 10 m, one release scenario each (103-26,397
     cells), crossed with 64 (mu, xi, h) sets: 1024 runs of 32 particles per cell and 2000 steps. Timed
@@ -415,6 +449,8 @@ def main() -> int:
         },
     }
     out["mipmap"] = mipmap_leg(avl, torch, res, 20)
+    if args.workload == "alpine":
+        out["fine_release"] = fine_leg(avl, torch, w, dem, 5)
     if not args.no_batched:
         out["batched"] = batched_leg(avl, torch, 3)
     if not args.no_gradient:

@@ -98,13 +98,45 @@ AVL_API int avl_release_cells(const uint8_t* mask, int32_t H, int32_t W, int32_t
  *   per particle). vmax: H*W float, the maximum speed (m/s) reached in each texel (0 if none).
  * stats (nullable): 4 uint64 on the device: {steps, particles that left the grid, that stopped, that
  *   reached step_limit}; "steps" counts every step entered, the terminating one included.
- * particles_per_cell >= 1; dem, mask, counts, vmax as above; H, W >= 1; (H + 2) (W + 2) < 2^30 (the
- * kernel reads a copy of the DEM with a one-texel border through 32-bit byte offsets);
+ * particles_per_cell >= 1; dem, mask, counts, vmax as above; H, W >= 1, both < 2^23; (H + 2) (W + 2) < 2^30
+ * (the kernel reads a copy of the DEM with a one-texel border through 32-bit byte offsets);
  * workspace: avl_workspace_bytes(H, W) bytes of device memory, owned by the caller, not retained. */
 AVL_API int avl_trajectories(const float* dem, const uint8_t* mask, int32_t H, int32_t W, float cell_size,
                      const avl_params* params, uint32_t particles_per_cell, uint32_t step_limit, uint64_t seed,
                      uint32_t run_id, uint32_t* counts, float* vmax, uint64_t* stats, void* workspace,
                      size_t workspace_bytes, void* stream);
+
+/* Release texture at a finer resolution than the DEM (section 5.2: the user picks the texture resolution
+ * at which release points are evaluated; a known release area, as for the historic event of figure 1, can
+ * be handed in as a texture of its own). The texture has mult x mult texels per DEM cell, row-major,
+ * (mult*H) x (mult*W); texel (R, C) is centred at ((C + 1/2) / mult, (R + 1/2) / mult) in DEM cell units. */
+#define AVL_MAX_RELEASE_MULT 16
+
+/* Release map at mult texels per DEM cell edge: at each fine texel centre, nz (channel 2 of normals4) and
+ * the height are filtered bilinearly between the DEM texel centres with clamped indices (the sample a
+ * linear texture filter with clamp-to-edge addressing takes; nz is not renormalised), in binary32 as
+ * top = a + fx(b - a), bottom = c + fx(d - c), value = top + fy(bottom - top), and tested as in
+ * avl_release_mask. mult = 1 gives avl_release_mask's map. 1 <= mult <= AVL_MAX_RELEASE_MULT,
+ * (mult H)(mult W) < 2^31; mask: (mult*H)*(mult*W) bytes; other arguments as avl_release_mask. */
+AVL_API int avl_release_mask_fine(const float* normals4, const float* dem, int32_t H, int32_t W, int32_t mult,
+                                  float slope_min_deg, float slope_max_deg, float z_min, float z_max, uint8_t* mask,
+                                  void* stream);
+
+/* Workspace bytes that avl_trajectories_fine needs (0 if an argument is out of range); mult = 1 gives
+ * avl_workspace_bytes(H, W). */
+AVL_API size_t avl_fine_workspace_bytes(int32_t H, int32_t W, int32_t mult);
+
+/* avl_trajectories from a release texture with mult x mult texels per DEM cell (mask: (mult*H)*(mult*W)
+ * bytes): particles_per_cell particles start at the centre of every nonzero texel, inside the DEM cell
+ * (R / mult, C / mult), which counts their entry; their random stream has counter word 2 = the texel's
+ * index R*(mult*W) + C in the texture. Rasters, stats and the model are those of avl_trajectories (DEM
+ * resolution, H*W); mult = 1 is exactly avl_trajectories. 1 <= mult <= AVL_MAX_RELEASE_MULT,
+ * (mult H)(mult W) < 2^31, mult H and mult W < 2^23 (release points are formed in binary32);
+ * workspace: avl_fine_workspace_bytes(H, W, mult) bytes. */
+AVL_API int avl_trajectories_fine(const float* dem, const uint8_t* mask, int32_t H, int32_t W, int32_t mult,
+                                  float cell_size, const avl_params* params, uint32_t particles_per_cell,
+                                  uint32_t step_limit, uint64_t seed, uint32_t run_id, uint32_t* counts, float* vmax,
+                                  uint64_t* stats, void* workspace, size_t workspace_bytes, void* stream);
 
 /* One run of a batch: which DEM tile, which release scenario (mask) and which parameter set, and the
  * run's random stream (Philox key = seed, counter word 3 = run_id). 24 bytes. */

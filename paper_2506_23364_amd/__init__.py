@@ -66,6 +66,11 @@ def _load() -> ctypes.CDLL:
     L.avl_release_cells.argtypes = [vp, i32, i32, vp, vp, vp, sz, vp]
     L.avl_trajectories.argtypes = [vp, vp, i32, i32, f32, ctypes.POINTER(Params), u32, u32, u64, u32, vp, vp, vp,
                                    vp, sz, vp]
+    L.avl_release_mask_fine.argtypes = [vp, vp, i32, i32, i32, f32, f32, f32, f32, vp, vp]
+    L.avl_fine_workspace_bytes.argtypes = [i32, i32, i32]
+    L.avl_fine_workspace_bytes.restype = sz
+    L.avl_trajectories_fine.argtypes = [vp, vp, i32, i32, i32, f32, ctypes.POINTER(Params), u32, u32, u64, u32, vp,
+                                        vp, vp, vp, sz, vp]
     L.avl_mipmap_levels.argtypes = [i32, i32]
     L.avl_mipmap_levels.restype = i32
     L.avl_mipmap_cells.argtypes = [i32, i32]
@@ -96,7 +101,8 @@ def _load() -> ctypes.CDLL:
     L.avl_strerror.restype = ctypes.c_char_p
     L.avl_last_error.argtypes = []
     L.avl_last_error.restype = ctypes.c_char_p
-    for name in ("avl_normals", "avl_release_mask", "avl_release_cells", "avl_trajectories"):
+    for name in ("avl_normals", "avl_release_mask", "avl_release_cells", "avl_trajectories", "avl_release_mask_fine",
+                 "avl_trajectories_fine"):
         getattr(L, name).restype = ctypes.c_int
     return L
 
@@ -261,6 +267,51 @@ def trajectories(dem: torch.Tensor, mask: torch.Tensor, cell_size: float, params
                                     particles_per_cell, step_limit, seed & (2**64 - 1), run_id,
                                     out.counts.data_ptr(), out.vmax.data_ptr(), out.stats.data_ptr(), ws.data_ptr(),
                                     ws.numel(), _stream(dem.device)), "avl_trajectories")
+    return out
+
+
+def fine_workspace_bytes(h: int, w: int, mult: int) -> int:
+    return int(lib.avl_fine_workspace_bytes(h, w, mult))
+
+
+def release_mask_fine(nrm: torch.Tensor, dem: torch.Tensor, mult: int, slope_min_deg: float, slope_max_deg: float,
+                      z_min: float = float("-inf"), z_max: float = float("inf")) -> torch.Tensor:
+    """Release map at mult x mult texels per DEM cell: uint8 (mult*H, mult*W)."""
+    _need(nrm, "normals", torch.float32, 3)
+    _need(dem, "dem", torch.float32, 2)
+    h, w = dem.shape
+    if nrm.shape != (h, w, 4):
+        raise ValueError("normals must be (H, W, 4)")
+    out = torch.empty((h * mult, w * mult), dtype=torch.uint8, device=dem.device)
+    with torch.cuda.device(dem.device):
+        _check(lib.avl_release_mask_fine(nrm.data_ptr(), dem.data_ptr(), h, w, mult, slope_min_deg, slope_max_deg,
+                                         z_min, z_max, out.data_ptr(), _stream(dem.device)), "avl_release_mask_fine")
+    return out
+
+
+def trajectories_fine(dem: torch.Tensor, mask: torch.Tensor, mult: int, cell_size: float, params: Params,
+                      particles_per_cell: int, step_limit: int, seed: int, run_id: int = 0,
+                      out: RunResult | None = None) -> RunResult:
+    """One pass from a release texture with mult x mult texels per DEM cell (mask (mult*H, mult*W)); the
+    rasters have the DEM's shape."""
+    _need(dem, "dem", torch.float32, 2)
+    _need(mask, "mask", torch.uint8, 2)
+    h, w = dem.shape
+    if mask.shape != (h * mult, w * mult):
+        raise ValueError("mask must be (mult*H, mult*W)")
+    if out is None:
+        out = RunResult(torch.empty((h, w), dtype=torch.uint32, device=dem.device),
+                        torch.empty((h, w), dtype=torch.float32, device=dem.device),
+                        torch.empty(4, dtype=torch.uint64, device=dem.device))
+    nb = fine_workspace_bytes(h, w, mult)
+    if nb == 0:
+        raise ValueError("mult out of range")
+    with torch.cuda.device(dem.device):
+        ws = _workspace(dem.device, nb)
+        _check(lib.avl_trajectories_fine(dem.data_ptr(), mask.data_ptr(), h, w, mult, cell_size, ctypes.byref(params),
+                                         particles_per_cell, step_limit, seed & (2**64 - 1), run_id,
+                                         out.counts.data_ptr(), out.vmax.data_ptr(), out.stats.data_ptr(),
+                                         ws.data_ptr(), ws.numel(), _stream(dem.device)), "avl_trajectories_fine")
     return out
 
 

@@ -2,6 +2,7 @@
 // enqueueing, the autotuner of the trajectory kernel and the graph cache of batched calls.
 // See include/avl.h for the contract of each call.
 #include <cmath>
+#include <cstdarg>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -13,15 +14,15 @@
 
 namespace avl {
 
-size_t workspace_bytes(int64_t H, int64_t W) {
-    const int64_t n = H * W;
+size_t workspace_bytes(int64_t H, int64_t W, int64_t mult) {
+    const int64_t n = H * W * mult * mult;  // texels of the release texture
     return kControl + round256((size_t)scan_blocks(n) * sizeof(uint32_t)) + round256((size_t)n * sizeof(int32_t)) +
            round256((size_t)n * sizeof(StartRec)) +
            round256((size_t)padded_cells(H, W) * sizeof(float));
 }
 
-Workspace carve(void* base, int64_t H, int64_t W) {
-    const int64_t n = H * W;
+Workspace carve(void* base, int64_t H, int64_t W, int64_t mult) {
+    const int64_t n = H * W * mult * mult;
     char* p = static_cast<char*>(base);
     Workspace w{};
     w.n_cells = reinterpret_cast<int32_t*>(p);
@@ -145,9 +146,12 @@ hipError_t timed_launch(const avl::TrajArgs& a, bool batched, const avl::LaunchS
     return hipSuccess;
 }
 
-int fail(int code, const char* fmt, const char* detail = nullptr) {
+__attribute__((format(printf, 2, 3))) int fail(int code, const char* fmt, ...) {
     char buf[512];
-    std::snprintf(buf, sizeof buf, fmt, detail ? detail : "");
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
     g_last_error = buf;
     return code;
 }
@@ -432,21 +436,33 @@ int avl_release_cells(const uint8_t* mask, int32_t H, int32_t W, int32_t* cells,
     return e == hipSuccess ? AVL_OK : hip_fail(e, "avl_release_cells");
 }
 
-int avl_trajectories(const float* dem, const uint8_t* mask, int32_t H, int32_t W, float cell_size,
-                     const avl_params* params, uint32_t particles_per_cell, uint32_t step_limit, uint64_t seed,
-                     uint32_t run_id, uint32_t* counts, float* vmax, uint64_t* stats, void* workspace,
-                     size_t workspace_bytes, void* stream) {
-    g_last_error.clear();
-    if (!dem || !mask || !counts || !vmax || !workspace) return fail(AVL_EINVAL, "avl_trajectories: null pointer");
+namespace {
+
+// One trajectory pass from a release texture with mult x mult texels per DEM cell (mask: mult*H x mult*W).
+int single_pass(const char* where, const float* dem, const uint8_t* mask, int32_t H, int32_t W, int32_t mult,
+                float cell_size, const avl_params* params, uint32_t particles_per_cell, uint32_t step_limit,
+                uint64_t seed, uint32_t run_id, uint32_t* counts, float* vmax, uint64_t* stats, void* workspace,
+                size_t workspace_bytes, void* stream) {
+    if (!dem || !mask || !counts || !vmax || !workspace) return fail(AVL_EINVAL, "%s: null pointer", where);
     if (!grid_ok(H, W, 1) || avl::padded_cells(H, W) >= (int64_t(1) << 30))
-        return fail(AVL_EINVAL, "avl_trajectories: need H, W >= 1 and (H + 2)(W + 2) < 2^30");
-    if (!finite(cell_size) || !(cell_size > 0.0f)) return fail(AVL_EINVAL, "avl_trajectories: cell_size must be > 0");
-    if (particles_per_cell == 0) return fail(AVL_EINVAL, "avl_trajectories: particles_per_cell must be >= 1");
-    if (const char* why = check_params(params)) return fail(AVL_EINVAL, "avl_trajectories: %s", why);
+        return fail(AVL_EINVAL, "%s: need H, W >= 1 and (H + 2)(W + 2) < 2^30", where);
+    if (mult < 1 || mult > AVL_MAX_RELEASE_MULT)
+        return fail(AVL_EINVAL, "%s: release texels per DEM cell edge must be in [1, %d]", where, AVL_MAX_RELEASE_MULT);
+    if ((int64_t)H * W * mult * mult >= (int64_t(1) << 31))
+        return fail(AVL_EINVAL, "%s: need (mult H)(mult W) < 2^31", where);
+    // release points (k + 1/2) / mult are formed in binary32: below 2^23 texels per row and column the
+    // numerator is exact and the quotient's rounding error stays under the 1/(2 mult) margin to the next
+    // cell edge, so the DEM cell under each release point is the exact one
+    if ((int64_t)mult * W >= (int64_t(1) << 23) || (int64_t)mult * H >= (int64_t(1) << 23))
+        return fail(AVL_EINVAL, "%s: need mult W and mult H < 2^23", where);
+    if (!finite(cell_size) || !(cell_size > 0.0f)) return fail(AVL_EINVAL, "%s: cell_size must be > 0", where);
+    if (particles_per_cell == 0) return fail(AVL_EINVAL, "%s: particles_per_cell must be >= 1", where);
+    if (const char* why = check_params(params)) return fail(AVL_EINVAL, "%s: %s", where, why);
     const int64_t n = (int64_t)H * W;
-    if (workspace_bytes < avl::workspace_bytes(H, W)) return fail(AVL_ENOMEM, "avl_trajectories: workspace too small");
+    const int64_t nf = n * mult * mult;
+    if (workspace_bytes < avl::workspace_bytes(H, W, mult)) return fail(AVL_ENOMEM, "%s: workspace too small", where);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    avl::Workspace ws = avl::carve(workspace, H, W);
+    avl::Workspace ws = avl::carve(workspace, H, W, mult);
 
     avl::TrajArgs a{};
     a.dem = dem;
@@ -475,27 +491,75 @@ int avl_trajectories(const float* dem, const uint8_t* mask, int32_t H, int32_t W
         return avl::launch_fill_u64(a.stats, 0ull, 4, s);
     };
     hipError_t e;
-    if ((e = avl::launch_compact(mask, n, ws.cells, ws.n_cells, ws.blk, s)) != hipSuccess)
-        return hip_fail(e, "avl_trajectories: compaction");
-    if ((e = avl::launch_start_records(dem, H, W, ws.cells, ws.n_cells, n, ws.starts, s)) != hipSuccess)
-        return hip_fail(e, "avl_trajectories: start records");
+    if ((e = avl::launch_compact(mask, nf, ws.cells, ws.n_cells, ws.blk, s)) != hipSuccess)
+        return hip_fail(e, (std::string(where) + ": compaction").c_str());
+    if ((e = avl::launch_start_records(dem, H, W, mult, ws.cells, ws.n_cells, nf, ws.starts, s)) != hipSuccess)
+        return hip_fail(e, (std::string(where) + ": start records").c_str());
     if ((e = avl::launch_pad_dem(dem, H, W, ws.dem_pad, s)) != hipSuccess)
-        return hip_fail(e, "avl_trajectories: padded DEM");
+        return hip_fail(e, (std::string(where) + ": padded DEM").c_str());
     const avl::RunSpec spec{0u, 0u, 0u, run_id, (unsigned long long)seed};
     if ((e = avl::launch_setup_runs(nullptr, nullptr, 0, spec, *params, ws.n_cells, 1, 1, 1, H, W, cell_size,
                                     particles_per_cell, false, ws.runs, ws.run_off, nullptr, s)) != hipSuccess)
-        return hip_fail(e, "avl_trajectories: run setup");
+        return hip_fail(e, (std::string(where) + ": run setup").c_str());
     int variant = 0;
-    if ((e = choose_variant(a, false, tune_key(false, n, 1, particles_per_cell, step_limit), s, zero, &variant)) !=
+    if ((e = choose_variant(a, false, tune_key(false, nf, 1, particles_per_cell, step_limit), s, zero, &variant)) !=
         hipSuccess)
-        return hip_fail(e, "avl_trajectories: autotune");
+        return hip_fail(e, (std::string(where) + ": autotune").c_str());
     g_last_variant = variant;
-    if ((e = zero()) != hipSuccess) return hip_fail(e, "avl_trajectories: zero");
+    if ((e = zero()) != hipSuccess) return hip_fail(e, (std::string(where) + ": zero").c_str());
     if ((e = timed_launch(a, false, avl::trajectory_shape(false, variant), s)) != hipSuccess)
-        return hip_fail(e, "avl_trajectories: launch");
+        return hip_fail(e, (std::string(where) + ": launch").c_str());
     if ((e = avl::launch_finalize_vmax(a.vmax2, n, s)) != hipSuccess)
-        return hip_fail(e, "avl_trajectories: finalize");
+        return hip_fail(e, (std::string(where) + ": finalize").c_str());
     return AVL_OK;
+}
+
+}  // namespace
+
+int avl_trajectories(const float* dem, const uint8_t* mask, int32_t H, int32_t W, float cell_size,
+                     const avl_params* params, uint32_t particles_per_cell, uint32_t step_limit, uint64_t seed,
+                     uint32_t run_id, uint32_t* counts, float* vmax, uint64_t* stats, void* workspace,
+                     size_t workspace_bytes, void* stream) {
+    g_last_error.clear();
+    return single_pass("avl_trajectories", dem, mask, H, W, 1, cell_size, params, particles_per_cell, step_limit,
+                       seed, run_id, counts, vmax, stats, workspace, workspace_bytes, stream);
+}
+
+size_t avl_fine_workspace_bytes(int32_t H, int32_t W, int32_t mult) {
+    if (H < 1 || W < 1 || mult < 1 || mult > AVL_MAX_RELEASE_MULT) return 0;
+    return avl::workspace_bytes(H, W, mult);
+}
+
+int avl_release_mask_fine(const float* normals4, const float* dem, int32_t H, int32_t W, int32_t mult,
+                          float slope_min_deg, float slope_max_deg, float z_min, float z_max, uint8_t* mask,
+                          void* stream) {
+    g_last_error.clear();
+    if (!normals4 || !dem || !mask) return fail(AVL_EINVAL, "avl_release_mask_fine: null pointer");
+    if (!grid_ok(H, W, 1)) return fail(AVL_EINVAL, "avl_release_mask_fine: need H, W >= 1 and H*W < 2^31");
+    if (mult < 1 || mult > AVL_MAX_RELEASE_MULT)
+        return fail(AVL_EINVAL, "avl_release_mask_fine: mult must be in [1, %d]", AVL_MAX_RELEASE_MULT);
+    if ((int64_t)H * W * mult * mult >= (int64_t(1) << 31))
+        return fail(AVL_EINVAL, "avl_release_mask_fine: need (mult H)(mult W) < 2^31");
+    if (reinterpret_cast<uintptr_t>(normals4) & 15)
+        return fail(AVL_EINVAL, "avl_release_mask_fine: normals4 not 16-byte aligned");
+    if (!(slope_min_deg >= 0.0f && slope_min_deg <= slope_max_deg && slope_max_deg <= 90.0f))
+        return fail(AVL_EINVAL, "avl_release_mask_fine: need 0 <= slope_min_deg <= slope_max_deg <= 90");
+    if (std::isnan(z_min) || std::isnan(z_max)) return fail(AVL_EINVAL, "avl_release_mask_fine: NaN elevation bound");
+    const double d2r = 3.14159265358979323846 / 180.0;
+    const float cmin = (float)std::cos((double)slope_max_deg * d2r);
+    const float cmax = (float)std::cos((double)slope_min_deg * d2r);
+    hipError_t e = avl::launch_release_mask_fine(normals4, dem, H, W, mult, cmin, cmax, z_min, z_max, mask,
+                                                 static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? AVL_OK : hip_fail(e, "avl_release_mask_fine");
+}
+
+int avl_trajectories_fine(const float* dem, const uint8_t* mask, int32_t H, int32_t W, int32_t mult, float cell_size,
+                          const avl_params* params, uint32_t particles_per_cell, uint32_t step_limit, uint64_t seed,
+                          uint32_t run_id, uint32_t* counts, float* vmax, uint64_t* stats, void* workspace,
+                          size_t workspace_bytes, void* stream) {
+    g_last_error.clear();
+    return single_pass("avl_trajectories_fine", dem, mask, H, W, mult, cell_size, params, particles_per_cell,
+                       step_limit, seed, run_id, counts, vmax, stats, workspace, workspace_bytes, stream);
 }
 
 size_t avl_smooth_workspace_bytes(int32_t H, int32_t W, int32_t max_release_cells, uint32_t particles_per_cell,

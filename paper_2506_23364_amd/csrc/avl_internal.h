@@ -16,8 +16,9 @@ constexpr int kWave = 64;
 // Single run (avl_workspace_bytes):
 //   [0, 512)     control block: n_cells (i32 @0), stats (4 x u64 @64), per-XCD slot queues (kXcds x u64
 //                @128), run offsets (2 x u64 @192), the run's constants (RunConst @256)
-//   then         per-block sums of the compaction scan (u32), the release-cell list (i32, H*W), the start
-//                records of the release cells (StartRec, H*W) and the padded DEM (f32, (H + 2) x (W + 2))
+//   then         per-block sums of the compaction scan (u32), the release-texel list (i32, one per texel of
+//                the release texture: mult^2 H W), the start records of the release texels (StartRec, as
+//                many) and the padded DEM (f32, (H + 2) x (W + 2))
 // Batch (avl_batched_workspace_bytes):
 //   [0, 512)     control block: per-XCD slot queues @128
 //   then         compaction scan sums; n_masks release-cell lists (i32, H*W each); n_masks cell counts;
@@ -43,15 +44,15 @@ struct Workspace {
     unsigned long long* run_off;  // n_runs + 1
     RunConst* runs;               // n_runs
     uint32_t* blk;
-    int32_t* cells;               // single: H*W; batch: n_masks x H*W
-    StartRec* starts;             // single only: H*W
+    int32_t* cells;               // single: mult^2 H W; batch: n_masks x H*W
+    StartRec* starts;             // single only: mult^2 H W
     float* dem_pad;               // single: (H + 2) x (W + 2); batch: n_tiles of them
 };
 
 // cells of the DEM with a one-texel border
 __host__ __device__ inline int64_t padded_cells(int64_t H, int64_t W) { return (H + 2) * (W + 2); }
-size_t workspace_bytes(int64_t H, int64_t W);
-Workspace carve(void* base, int64_t H, int64_t W);
+size_t workspace_bytes(int64_t H, int64_t W, int64_t mult = 1);   // mult: release texels per DEM cell edge
+Workspace carve(void* base, int64_t H, int64_t W, int64_t mult = 1);
 size_t batched_workspace_bytes(int64_t H, int64_t W, int64_t n_tiles, int64_t n_masks, int64_t n_runs);
 Workspace carve_batched(void* base, int64_t H, int64_t W, int64_t n_masks, int64_t n_runs);
 
@@ -126,6 +127,8 @@ struct LaunchShape {
 hipError_t launch_normals(const float* dem, int H, int W, float cs, float* out4, hipStream_t s);
 hipError_t launch_release_mask(const float* normals4, const float* dem, int64_t n, float cmin, float cmax,
                                float zmin, float zmax, uint8_t* mask, hipStream_t s);
+hipError_t launch_release_mask_fine(const float* normals4, const float* dem, int H, int W, int mult, float cmin,
+                                    float cmax, float zmin, float zmax, uint8_t* mask, hipStream_t s);
 hipError_t launch_compact(const uint8_t* mask, int64_t n, int32_t* cells, int32_t* n_cells, uint32_t* blk,
                           hipStream_t s);
 // Overlay mipmap: up to kMipPass output levels per pass (a 32 x 32 tile of the first halves to 1 x 1).
@@ -142,8 +145,8 @@ hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t 
 // (H + 2) x (W + 2) copy of the DEM with the edge texels replicated into a one-texel border.
 hipError_t launch_pad_dem(const float* dem, int H, int W, float* out, hipStream_t s);
 // starts[i] for each of the *n_cells release cells (capacity n).
-hipError_t launch_start_records(const float* dem, int H, int W, const int32_t* cells, const int32_t* n_cells,
-                                int64_t n, StartRec* starts, hipStream_t s);
+hipError_t launch_start_records(const float* dem, int H, int W, int mult, const int32_t* cells,
+                                const int32_t* n_cells, int64_t n, StartRec* starts, hipStream_t s);
 // Setup of the run table: per run, constants from its parameter set and the slot count from its
 // scenario's release-cell count (written by the compaction); then 64-aligned slot offsets.
 struct RunSpec {

@@ -107,14 +107,19 @@ __device__ __forceinline__ Corners corners(int H, int W, float x, float y) {
     return k;
 }
 
-// Start state at the centre of release cell `cell`: position, bilinear sample and the unit direction of
-// steepest descent (zero on flat ground).
-__device__ __forceinline__ StartRec start_state(const float* __restrict__ dem, int H, int W, uint32_t cell) {
+// Start state of release texel `texel` of a release texture with mult x mult texels per DEM cell (row-major,
+// W * mult wide): its centre ((c + 1/2) / mult, (r + 1/2) / mult) in DEM cell units (mult = 1: the centre of
+// DEM cell `texel`), the bilinear sample there and the unit direction of steepest descent (zero on flat
+// ground). `cell` keeps the texel index, which keys the particle's random stream.
+__device__ __forceinline__ StartRec start_state(const float* __restrict__ dem, int H, int W, uint32_t mult,
+                                                uint32_t texel) {
     StartRec st;
-    const int r = (int)(cell / (uint32_t)W);
-    const int c = (int)(cell - (uint32_t)r * (uint32_t)W);
-    st.x = (float)c + 0.5f;
-    st.y = (float)r + 0.5f;
+    const uint32_t Wf = (uint32_t)W * mult;
+    const uint32_t r = texel / Wf;
+    const uint32_t c = texel - r * Wf;
+    const float fm = (float)mult;
+    st.x = ((float)c + 0.5f) / fm;
+    st.y = ((float)r + 0.5f) / fm;
     const Sample s0 = bilinear(dem, H, W, st.x, st.y);
     st.z = s0.z;
     st.gx = s0.gx;
@@ -128,11 +133,11 @@ __device__ __forceinline__ StartRec start_state(const float* __restrict__ dem, i
         st.dx = 0.0f;
         st.dy = 0.0f;
     }
-    st.cell = cell;
+    st.cell = texel;
     return st;
 }
 
-// start_state() with the patch read from the padded DEM (the same values, so the same result)
+// start state at the centre of DEM cell `cell`, with the patch read from the padded DEM (the same values, so the same result)
 __device__ __forceinline__ StartRec start_state_pad(__amdgpu_buffer_rsrc_t rs, uint32_t Wp, uint32_t row_bytes, int W,
                                                     uint32_t cell) {
     StartRec st;

@@ -103,6 +103,68 @@ hipError_t launch_release_mask(const float* normals4, const float* dem, int64_t 
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------------------------------------ fine release map
+// Release texture with mult x mult texels per DEM cell: texel (R, C) is centred at ((C + 1/2) / mult,
+// (R + 1/2) / mult) in DEM cell units, where nz and the height are filtered bilinearly between texel centres
+// with clamped indices and tested against the same bounds as the plain map. Four consecutive texels of a
+// row per thread (one 4-byte store); the row's vertical weights and rows are shared by the four, and the
+// DEM cells a thread reads are re-read by its neighbours from L1/L2.
+__global__ __launch_bounds__(256) void k_release_mask_fine(const float4* __restrict__ nrm,
+                                                           const float* __restrict__ dem, int H, int W, int mult,
+                                                           int64_t quads_per_row, int64_t n_quads, float cmin,
+                                                           float cmax, float zmin, float zmax,
+                                                           uint8_t* __restrict__ mask) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n_quads) return;
+    const int64_t Wf = (int64_t)W * mult;
+    const int64_t rr = q / quads_per_row;
+    const int64_t c0 = (q - rr * quads_per_row) * 4;
+    const float fm = (float)mult;
+    const float y = ((float)rr + 0.5f) / fm;
+    const float sy = y - 0.5f;
+    const float fr = floorf(sy);
+    const float fy = sy - fr;
+    const int r0 = (int)fr;
+    const int64_t ra = (int64_t)min(max(r0, 0), H - 1) * W;
+    const int64_t rb = (int64_t)min(max(r0 + 1, 0), H - 1) * W;
+    uint32_t packed = 0;
+    const int nk = (int)min((int64_t)4, Wf - c0);
+    for (int k = 0; k < nk; ++k) {
+        const float x = ((float)(c0 + k) + 0.5f) / fm;
+        const float sx = x - 0.5f;
+        const float fc = floorf(sx);
+        const float fx = sx - fc;
+        const int cc = (int)fc;
+        const int ca = min(max(cc, 0), W - 1), cb = min(max(cc + 1, 0), W - 1);
+        const float n00 = nrm[ra + ca].z, n01 = nrm[ra + cb].z, n10 = nrm[rb + ca].z, n11 = nrm[rb + cb].z;
+        const float ntop = n00 + fx * (n01 - n00), nbot = n10 + fx * (n11 - n10);
+        const float nz = ntop + fy * (nbot - ntop);
+        const float z00 = dem[ra + ca], z01 = dem[ra + cb], z10 = dem[rb + ca], z11 = dem[rb + cb];
+        const float ztop = z00 + fx * (z01 - z00), zbot = z10 + fx * (z11 - z10);
+        const float z = ztop + fy * (zbot - ztop);
+        const uint32_t m = (cmin <= nz && nz <= cmax && zmin <= z && z <= zmax) ? 1u : 0u;
+        packed |= m << (8 * k);
+    }
+    uint8_t* out = mask + rr * Wf + c0;
+    if (nk == 4 && (reinterpret_cast<uintptr_t>(out) & 3) == 0) {
+        *reinterpret_cast<uint32_t*>(out) = packed;
+    } else {
+        for (int k = 0; k < nk; ++k) out[k] = (uint8_t)(packed >> (8 * k));
+    }
+}
+
+hipError_t launch_release_mask_fine(const float* normals4, const float* dem, int H, int W, int mult, float cmin,
+                                    float cmax, float zmin, float zmax, uint8_t* mask, hipStream_t s) {
+    const int64_t Wf = (int64_t)W * mult, Hf = (int64_t)H * mult;
+    const int64_t qpr = (Wf + 3) / 4;
+    const int64_t nq = qpr * Hf;
+    const int64_t blocks = (nq + 255) / 256;
+    hipLaunchKernelGGL(k_release_mask_fine, dim3((unsigned)blocks), dim3(256), 0, s,
+                       reinterpret_cast<const float4*>(normals4), dem, H, W, mult, qpr, nq, cmin, cmax, zmin, zmax,
+                       mask);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------------------------------ compaction
 // Order-preserving stream compaction of the mask into linear indices, in three passes over
 // kScanChunk-cell blocks: per-block counts, one-block exclusive scan of the counts, per-block write.

@@ -355,7 +355,11 @@ void k_trajectories(TrajArgs a) {
                     v2 = 0.0f;
                     cmax2 = 0.0f;
                     n = 0;
-                    cur = rc.raster_off + cell_id;
+                    // the raster cell of the release point: the release texel's index keys the random
+                    // stream, the DEM cell under its centre takes the counts (the same cell at one texel per
+                    // DEM cell)
+                    cur = rc.raster_off +
+                          (kBatch ? cell_id : (uint32_t)(int)floorf(y) * (uint32_t)W + (uint32_t)(int)floorf(x));
                     alive = true;
                 }
             }
@@ -505,20 +509,20 @@ void k_trajectories(TrajArgs a) {
 
 // ------------------------------------------------------------------------------------------ start records
 
-__global__ __launch_bounds__(256) void k_start_records(const float* __restrict__ dem, int H, int W,
+__global__ __launch_bounds__(256) void k_start_records(const float* __restrict__ dem, int H, int W, uint32_t mult,
                                                        const int32_t* __restrict__ cells,
                                                        const int32_t* __restrict__ n_cells,
                                                        StartRec* __restrict__ starts) {
     const int64_t n = *n_cells;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        starts[i] = start_state(dem, H, W, (uint32_t)cells[i]);
+        starts[i] = start_state(dem, H, W, mult, (uint32_t)cells[i]);
 }
 
-hipError_t launch_start_records(const float* dem, int H, int W, const int32_t* cells, const int32_t* n_cells,
-                                int64_t n, StartRec* starts, hipStream_t s) {
+hipError_t launch_start_records(const float* dem, int H, int W, int mult, const int32_t* cells,
+                                const int32_t* n_cells, int64_t n, StartRec* starts, hipStream_t s) {
     const int64_t blocks = (n + 255) / 256;
     hipLaunchKernelGGL(k_start_records, dim3((unsigned)(blocks < 4096 ? (blocks > 0 ? blocks : 1) : 4096)), dim3(256),
-                       0, s, dem, H, W, cells, n_cells, starts);
+                       0, s, dem, H, W, (uint32_t)mult, cells, n_cells, starts);
     return hipGetLastError();
 }
 

@@ -135,3 +135,50 @@ def test_mipmap_rejects_bad_arguments(L):
     assert L.lib.avl_overlay_mipmap(None, FAKE, 4, 4, FAKE, FAKE, None) == -1
     assert L.lib.avl_overlay_mipmap(FAKE, FAKE, 0, 4, FAKE, FAKE, None) == -1
     assert L.lib.avl_mipmap_levels(0, 3) == 0 and L.lib.avl_mipmap_cells(3, 0) == 0
+
+
+def test_fine_workspace_size(L):
+    assert L.fine_workspace_bytes(16, 16, 1) == L.workspace_bytes(16, 16)
+    assert L.fine_workspace_bytes(16, 16, 0) == 0 and L.fine_workspace_bytes(16, 16, 17) == 0
+    assert L.fine_workspace_bytes(0, 16, 2) == 0
+    # the texel list and start records grow with the number of release texels (mult^2 H W)
+    assert L.fine_workspace_bytes(64, 64, 4) - L.workspace_bytes(64, 64) >= 15 * 64 * 64 * (4 + 32) - 3 * 256
+
+
+def _traj_fine(L, **kw):
+    a = dict(dem=FAKE, mask=FAKE, H=16, W=16, mult=2, cs=10.0, params=L.Params.make(), P=4, S=10, seed=1, run=0,
+             counts=FAKE, vmax=FAKE, stats=None, ws=FAKE, wsb=L.fine_workspace_bytes(16, 16, 2), stream=None)
+    a.update(kw)
+    p = a["params"]
+    return L.lib.avl_trajectories_fine(a["dem"], a["mask"], a["H"], a["W"], a["mult"], a["cs"],
+                                       ctypes.byref(p) if p else None, a["P"], a["S"], a["seed"], a["run"],
+                                       a["counts"], a["vmax"], a["stats"], a["ws"], a["wsb"], a["stream"])
+
+
+@pytest.mark.parametrize("kw", [
+    dict(dem=None), dict(mask=None), dict(counts=None), dict(vmax=None), dict(ws=None), dict(params=None),
+    dict(mult=0), dict(mult=17), dict(H=0), dict(H=20000, W=20000, mult=3), dict(cs=0.0), dict(P=0),
+    dict(H=2, W=(1 << 22) + 1, mult=2), dict(H=(1 << 23), W=1, mult=1),
+])
+def test_trajectories_fine_rejects_bad_arguments(L, kw):
+    assert _traj_fine(L, **kw) == L.AVL_EINVAL
+    assert L.lib.avl_last_error()
+
+
+def test_trajectories_fine_small_workspace(L):
+    assert _traj_fine(L, wsb=L.fine_workspace_bytes(16, 16, 2) - 1) == L.AVL_ENOMEM
+    assert _traj_fine(L, wsb=L.workspace_bytes(16, 16)) == L.AVL_ENOMEM
+
+
+@pytest.mark.parametrize("args", [
+    dict(nrm=None), dict(dem=None), dict(mask=None), dict(mult=0), dict(mult=17), dict(H=0),
+    dict(H=30000, W=30000, mult=2), dict(nrm=FAKE + 4), dict(smin=50.0, smax=40.0), dict(smax=91.0),
+    dict(zmin=float("nan")),
+])
+def test_release_mask_fine_rejects_bad_arguments(L, args):
+    a = dict(nrm=FAKE, dem=FAKE, H=16, W=16, mult=2, smin=30.0, smax=45.0, zmin=0.0, zmax=1.0, mask=FAKE)
+    a.update(args)
+    rc = L.lib.avl_release_mask_fine(a["nrm"], a["dem"], a["H"], a["W"], a["mult"], a["smin"], a["smax"], a["zmin"],
+                                     a["zmax"], a["mask"], None)
+    assert rc == L.AVL_EINVAL
+    assert L.lib.avl_last_error()
