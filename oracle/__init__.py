@@ -103,6 +103,19 @@ def release_mask_fine(nrm: np.ndarray, dem: np.ndarray, mult: int, smin: float, 
     return out
 
 
+def snow_cover(nrm: np.ndarray, dem: np.ndarray, snow_line: float, alt_blend: float, max_slope: float,
+               slope_blend: float, prec: str = "f32") -> np.ndarray:
+    """Snow-cover alpha (H, W) in [0, 1]."""
+    nrm = np.ascontiguousarray(nrm, dtype=_real(prec))
+    dem = np.ascontiguousarray(dem, dtype=np.float32)
+    h, w = dem.shape
+    out = np.zeros((h, w), dtype=_real(prec))
+    getattr(_lib(prec), f"oracle_snow_cover_{prec}")(
+        _ptr(nrm), _ptr(dem), ctypes.c_int(h), ctypes.c_int(w), ctypes.c_float(snow_line), ctypes.c_float(alt_blend),
+        ctypes.c_float(max_slope), ctypes.c_float(slope_blend), _ptr(out))
+    return out
+
+
 def compact(mask: np.ndarray) -> np.ndarray:
     mask = np.ascontiguousarray(mask, dtype=np.uint8)
     h, w = mask.shape

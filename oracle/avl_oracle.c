@@ -173,6 +173,39 @@ void NAME(oracle_release_mask_fine)(const real* normals4, const float* dem, int 
         }
 }
 
+/* ----------------------------------------------------------------------------------------------
+ * Snow cover (section 5.1): a per-texel decision from the terrain alone, with user parameters for the
+ * snow line, the maximal steepness and the blending of the transition zones; the overlay is white with
+ * the blend factor as its alpha. Reading: two linear ramps multiplied,
+ *   elevation: a_z = 0 at z <= snow_line, rising to 1 at z >= snow_line + alt_blend (a step at the
+ *              snow line when alt_blend = 0);
+ *   steepness: a_s = 1 where the slope is at most max_slope - slope_blend, falling to 0 at max_slope,
+ *              linear in nz = cos(slope) between the two host-rounded cosines (a step at max_slope when
+ *              slope_blend = 0);
+ *   alpha = a_z * a_s, in binary32, ramps as t = (v - lo) / (hi - lo) clamped to [0, 1] (NaN -> 0).
+ * ---------------------------------------------------------------------------------------------- */
+static real ramp(real v, real lo, real hi)
+{
+    if (!(hi > lo)) return v >= lo ? R(1) : R(0);
+    real t = (v - lo) / (hi - lo);
+    return t > 0 ? (t < 1 ? t : R(1)) : R(0);
+}
+
+void NAME(oracle_snow_cover)(const real* normals4, const float* dem, int H, int W, float snow_line,
+                             float alt_blend, float max_slope_deg, float slope_blend_deg, real* alpha)
+{
+    const double d2r = 3.14159265358979323846 / 180.0;
+    const real c_lo = (real)cos((double)max_slope_deg * d2r);                       /* nz at max_slope */
+    const real c_hi = (real)cos(((double)max_slope_deg - (double)slope_blend_deg) * d2r); /* full cover */
+    const real z_lo = (real)snow_line;
+    const real z_hi = (real)snow_line + (real)alt_blend;
+    for (size_t i = 0; i < (size_t)H * W; ++i) {
+        real a_z = ramp((real)dem[i], z_lo, z_hi);
+        real a_s = ramp(normals4[4 * i + 2], c_lo, c_hi);
+        alpha[i] = a_z * a_s;
+    }
+}
+
 /* Release-cell list: linear indices r*W+c of the set cells of the mask in row-major order. */
 int64_t NAME(oracle_compact)(const uint8_t* mask, int H, int W, int32_t* cells)
 {
