@@ -218,6 +218,26 @@ def fine_leg(avl, torch, w, dem, reps: int, mult: int = 2, per_texel: int = 64) 
             "ms_trajectory_kernel": kms, "particle_steps_per_s": steps / (kms * 1e-3)}
 
 
+def snow_leg(avl, torch, w, dem, reps: int) -> dict:
+    """Snow-cover alpha of the tile (section 5.1) from its normals: an HBM stream of 24 bytes per texel."""
+    nrm = avl.normals(dem, w.cell_size)
+    line = float(torch.quantile(dem.flatten()[::16], 0.6).item())
+    stream = torch.cuda.current_stream()
+    out = avl.snow_cover(nrm, dem, line, 200.0, 40.0, 8.0)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        out = avl.snow_cover(nrm, dem, line, 200.0, 40.0, 8.0)
+    e1.record(stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    nbytes = 24 * dem.numel()
+    return {"ms": ms, "algorithmic_bytes": nbytes, "achieved_GBs": nbytes / ms / 1e6, "peak_GBs": HBM_PEAK_GBS,
+            "covered_fraction": float((out > 0).float().mean().item()),
+            "note": "per call, launch included (one kernel)"}
+
+
 def batched_leg(avl, torch, reps: int) -> dict:
     """Ensemble sweep: 16 ridged-fBm tiles of 1024^2 at 10 m, one release scenario each (103-26,397
     cells), crossed with 64 (mu, xi, h) sets: 1024 runs of 32 particles per cell and 2000 steps. Timed
@@ -449,6 +469,7 @@ def main() -> int:
         },
     }
     out["mipmap"] = mipmap_leg(avl, torch, res, 20)
+    out["snow_cover"] = snow_leg(avl, torch, w, dem, 20)
     if args.workload == "alpine":
         out["fine_release"] = fine_leg(avl, torch, w, dem, 5)
     if not args.no_batched:

@@ -72,6 +72,19 @@ AVL_API int avl_normals(const float* dem, int32_t H, int32_t W, float cell_size,
 AVL_API int avl_release_mask(const float* normals4, const float* dem, int32_t H, int32_t W, float slope_min_deg,
                      float slope_max_deg, float z_min, float z_max, uint8_t* mask, void* stream);
 
+/* Snow cover (section 5.1: from the terrain alone, with the snow line, the maximal steepness and blend
+ * factors for the transition zones as parameters; the overlay is white with the blend factor as alpha).
+ * alpha[i] = a_z * a_s in binary32, where a ramp over [lo, hi] is (v - lo) / (hi - lo) clamped to [0, 1]
+ * (NaN gives 0), or the step v >= lo when hi <= lo:
+ *   a_z: v = dem[i] over [snow_line, snow_line + alt_blend] (the upper end rounded once to binary32);
+ *   a_s: v = nz (channel 2 of normals4) over [cos(max_slope), cos(max_slope - slope_blend)], the cosines
+ *        taken on the host in binary64 and rounded once (full cover up to max_slope - slope_blend, none
+ *        beyond max_slope, linear in nz between).
+ * normals4 as written by avl_normals (16-byte aligned); finite snow_line; finite alt_blend >= 0;
+ * 0 <= slope_blend_deg <= max_slope_deg <= 90. H, W >= 1. alpha: H*W floats. */
+AVL_API int avl_snow_cover(const float* normals4, const float* dem, int32_t H, int32_t W, float snow_line,
+                           float alt_blend, float max_slope_deg, float slope_blend_deg, float* alpha, void* stream);
+
 /* Workspace bytes that avl_release_cells and avl_trajectories need for an H x W grid. */
 AVL_API size_t avl_workspace_bytes(int32_t H, int32_t W);
 

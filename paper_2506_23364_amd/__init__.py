@@ -66,6 +66,7 @@ def _load() -> ctypes.CDLL:
     L.avl_release_cells.argtypes = [vp, i32, i32, vp, vp, vp, sz, vp]
     L.avl_trajectories.argtypes = [vp, vp, i32, i32, f32, ctypes.POINTER(Params), u32, u32, u64, u32, vp, vp, vp,
                                    vp, sz, vp]
+    L.avl_snow_cover.argtypes = [vp, vp, i32, i32, f32, f32, f32, f32, vp, vp]
     L.avl_release_mask_fine.argtypes = [vp, vp, i32, i32, i32, f32, f32, f32, f32, vp, vp]
     L.avl_fine_workspace_bytes.argtypes = [i32, i32, i32]
     L.avl_fine_workspace_bytes.restype = sz
@@ -102,7 +103,7 @@ def _load() -> ctypes.CDLL:
     L.avl_last_error.argtypes = []
     L.avl_last_error.restype = ctypes.c_char_p
     for name in ("avl_normals", "avl_release_mask", "avl_release_cells", "avl_trajectories", "avl_release_mask_fine",
-                 "avl_trajectories_fine"):
+                 "avl_trajectories_fine", "avl_snow_cover"):
         getattr(L, name).restype = ctypes.c_int
     return L
 
@@ -267,6 +268,21 @@ def trajectories(dem: torch.Tensor, mask: torch.Tensor, cell_size: float, params
                                     particles_per_cell, step_limit, seed & (2**64 - 1), run_id,
                                     out.counts.data_ptr(), out.vmax.data_ptr(), out.stats.data_ptr(), ws.data_ptr(),
                                     ws.numel(), _stream(dem.device)), "avl_trajectories")
+    return out
+
+
+def snow_cover(nrm: torch.Tensor, dem: torch.Tensor, snow_line: float, alt_blend: float, max_slope_deg: float,
+               slope_blend_deg: float) -> torch.Tensor:
+    """Snow-cover alpha: float32 (H, W) in [0, 1]."""
+    _need(nrm, "normals", torch.float32, 3)
+    _need(dem, "dem", torch.float32, 2)
+    h, w = dem.shape
+    if nrm.shape != (h, w, 4):
+        raise ValueError("normals must be (H, W, 4)")
+    out = torch.empty((h, w), dtype=torch.float32, device=dem.device)
+    with torch.cuda.device(dem.device):
+        _check(lib.avl_snow_cover(nrm.data_ptr(), dem.data_ptr(), h, w, snow_line, alt_blend, max_slope_deg,
+                                  slope_blend_deg, out.data_ptr(), _stream(dem.device)), "avl_snow_cover")
     return out
 
 

@@ -525,6 +525,26 @@ int avl_trajectories(const float* dem, const uint8_t* mask, int32_t H, int32_t W
                        seed, run_id, counts, vmax, stats, workspace, workspace_bytes, stream);
 }
 
+int avl_snow_cover(const float* normals4, const float* dem, int32_t H, int32_t W, float snow_line, float alt_blend,
+                   float max_slope_deg, float slope_blend_deg, float* alpha, void* stream) {
+    g_last_error.clear();
+    if (!normals4 || !dem || !alpha) return fail(AVL_EINVAL, "avl_snow_cover: null pointer");
+    if (!grid_ok(H, W, 1)) return fail(AVL_EINVAL, "avl_snow_cover: need H, W >= 1 and H*W < 2^31");
+    if (reinterpret_cast<uintptr_t>(normals4) & 15)
+        return fail(AVL_EINVAL, "avl_snow_cover: normals4 not 16-byte aligned");
+    if (!finite(snow_line) || !finite(alt_blend) || !(alt_blend >= 0.0f))
+        return fail(AVL_EINVAL, "avl_snow_cover: need a finite snow line and a finite alt_blend >= 0");
+    if (!(slope_blend_deg >= 0.0f && slope_blend_deg <= max_slope_deg && max_slope_deg <= 90.0f))
+        return fail(AVL_EINVAL, "avl_snow_cover: need 0 <= slope_blend_deg <= max_slope_deg <= 90");
+    const double d2r = 3.14159265358979323846 / 180.0;
+    const float c_lo = (float)std::cos((double)max_slope_deg * d2r);
+    const float c_hi = (float)std::cos(((double)max_slope_deg - (double)slope_blend_deg) * d2r);
+    const float z_hi = snow_line + alt_blend;
+    hipError_t e = avl::launch_snow_cover(normals4, dem, (int64_t)H * W, snow_line, z_hi, c_lo, c_hi, alpha,
+                                          static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? AVL_OK : hip_fail(e, "avl_snow_cover");
+}
+
 size_t avl_fine_workspace_bytes(int32_t H, int32_t W, int32_t mult) {
     if (H < 1 || W < 1 || mult < 1 || mult > AVL_MAX_RELEASE_MULT) return 0;
     return avl::workspace_bytes(H, W, mult);

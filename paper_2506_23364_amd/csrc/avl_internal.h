@@ -127,6 +127,8 @@ struct LaunchShape {
 hipError_t launch_normals(const float* dem, int H, int W, float cs, float* out4, hipStream_t s);
 hipError_t launch_release_mask(const float* normals4, const float* dem, int64_t n, float cmin, float cmax,
                                float zmin, float zmax, uint8_t* mask, hipStream_t s);
+hipError_t launch_snow_cover(const float* normals4, const float* dem, int64_t n, float z_lo, float z_hi, float c_lo,
+                             float c_hi, float* alpha, hipStream_t s);
 hipError_t launch_release_mask_fine(const float* normals4, const float* dem, int H, int W, int mult, float cmin,
                                     float cmax, float zmin, float zmax, uint8_t* mask, hipStream_t s);
 hipError_t launch_compact(const uint8_t* mask, int64_t n, int32_t* cells, int32_t* n_cells, uint32_t* blk,

@@ -103,6 +103,46 @@ hipError_t launch_release_mask(const float* normals4, const float* dem, int64_t 
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------------------------------------ snow cover
+// alpha = ramp(z; snow line, + alt blend) * ramp(nz; cos max slope, cos(max slope - slope blend)), a ramp
+// being (v - lo) / (hi - lo) clamped to [0, 1] (NaN -> 0), or the step v >= lo when hi <= lo. Four texels
+// per thread: four 16-byte normal loads, one 16-byte height load, one 16-byte alpha store.
+__device__ __forceinline__ float snow_ramp(float v, float lo, float hi, bool step) {
+    if (step) return v >= lo ? 1.0f : 0.0f;
+    const float t = (v - lo) / (hi - lo);
+    return t > 0.0f ? (t < 1.0f ? t : 1.0f) : 0.0f;
+}
+
+__global__ __launch_bounds__(256) void k_snow_cover(const float4* __restrict__ nrm, const float* __restrict__ dem,
+                                                    int64_t n, float z_lo, float z_hi, float c_lo, float c_hi,
+                                                    float* __restrict__ alpha) {
+    const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+    if (i0 >= n) return;
+    const bool zstep = !(z_hi > z_lo), cstep = !(c_hi > c_lo);
+    if (i0 + 4 <= n && (reinterpret_cast<uintptr_t>(dem + i0) & 15) == 0 &&
+        (reinterpret_cast<uintptr_t>(alpha + i0) & 15) == 0) {
+        const float4 z4 = *reinterpret_cast<const float4*>(dem + i0);
+        const float z[4] = {z4.x, z4.y, z4.z, z4.w};
+        float a[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            a[k] = snow_ramp(z[k], z_lo, z_hi, zstep) * snow_ramp(nrm[i0 + k].z, c_lo, c_hi, cstep);
+        *reinterpret_cast<float4*>(alpha + i0) = make_float4(a[0], a[1], a[2], a[3]);
+    } else {
+        for (int64_t i = i0; i < n && i < i0 + 4; ++i)
+            alpha[i] = snow_ramp(dem[i], z_lo, z_hi, zstep) * snow_ramp(nrm[i].z, c_lo, c_hi, cstep);
+    }
+}
+
+hipError_t launch_snow_cover(const float* normals4, const float* dem, int64_t n, float z_lo, float z_hi, float c_lo,
+                             float c_hi, float* alpha, hipStream_t s) {
+    const int64_t threads = (n + 3) / 4;
+    const unsigned blocks = (unsigned)((threads + 255) / 256);
+    hipLaunchKernelGGL(k_snow_cover, dim3(blocks), dim3(256), 0, s, reinterpret_cast<const float4*>(normals4), dem, n,
+                       z_lo, z_hi, c_lo, c_hi, alpha);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------------------------------ fine release map
 // Release texture with mult x mult texels per DEM cell: texel (R, C) is centred at ((C + 1/2) / mult,
 // (R + 1/2) / mult) in DEM cell units, where nz and the height are filtered bilinearly between texel centres

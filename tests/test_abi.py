@@ -182,3 +182,16 @@ def test_release_mask_fine_rejects_bad_arguments(L, args):
                                      a["zmax"], a["mask"], None)
     assert rc == L.AVL_EINVAL
     assert L.lib.avl_last_error()
+
+
+@pytest.mark.parametrize("args", [
+    dict(nrm=None), dict(dem=None), dict(alpha=None), dict(H=0), dict(nrm=FAKE + 8), dict(line=float("nan")),
+    dict(zb=-1.0), dict(zb=float("inf")), dict(smax=91.0), dict(sb=50.0, smax=40.0), dict(sb=-1.0),
+])
+def test_snow_cover_rejects_bad_arguments(L, args):
+    a = dict(nrm=FAKE, dem=FAKE, H=16, W=16, line=1000.0, zb=100.0, smax=40.0, sb=5.0, alpha=FAKE)
+    a.update(args)
+    rc = L.lib.avl_snow_cover(a["nrm"], a["dem"], a["H"], a["W"], a["line"], a["zb"], a["smax"], a["sb"],
+                              a["alpha"], None)
+    assert rc == L.AVL_EINVAL
+    assert L.lib.avl_last_error()
