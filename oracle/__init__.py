@@ -339,3 +339,79 @@ def smooth_particles(dem, mask, cell_size, params: OracleParams, particles_per_c
         _ptr(steps))
     assert rc == 0
     return Lp, reason, steps
+
+
+# ------------------------------------------------------------------------------------------ calibration loop
+# Calibration of the friction parameters against a target deposit: gradient descent with Adam (Kingma and
+# Ba, "Adam: a method for stochastic optimization", ICLR 2015, algorithm 1) on (mu, xi), each step taking
+# the loss and its gradient from the smooth forward and its adjoint.
+
+def deposit_of(dep_q: np.ndarray) -> np.ndarray:
+    """The float deposit of a fixed-point raster: q * 2^-24 in binary64, rounded once to binary32."""
+    return (dep_q.astype(np.float64) * 2.0 ** -24).astype(np.float32)
+
+
+def mse_grad(dep: np.ndarray, target: np.ndarray) -> tuple[float, np.ndarray]:
+    """L = mean((D - T)^2) (binary64 sum of the binary32 differences squared) and dL/dD = c (D - T) with
+    c = 2 / N rounded to binary32 and the product in binary32."""
+    d = dep.astype(np.float32) - target.astype(np.float32)
+    n = d.size
+    c = np.float32(2.0) / np.float32(n)
+    loss = float(np.sum(d.astype(np.float64) ** 2) / n)
+    return loss, (c * d).astype(np.float32)
+
+
+@dataclass
+class AdamState:
+    lr: tuple            # per-parameter step sizes
+    beta1: float
+    beta2: float
+    eps: float
+    m: list
+    v: list
+    b1t: float = 1.0     # beta1^t and beta2^t, kept as running products
+    b2t: float = 1.0
+    t: int = 0
+
+
+def adam_init(lr, beta1=0.9, beta2=0.999, eps=1e-8) -> AdamState:
+    """Adam state for len(lr) parameters; the decay rates and eps enter as binary32 values (as the C ABI
+    passes them)."""
+    f = lambda v: float(np.float32(v))  # noqa: E731
+    return AdamState(tuple(f(x) for x in lr), f(beta1), f(beta2), f(eps), [0.0] * len(lr), [0.0] * len(lr))
+
+
+def adam_step(s: AdamState, theta: list, grad: list) -> list:
+    """One Adam update in binary64: m <- b1 m + (1 - b1) g; v <- b2 v + (1 - b2) g^2; bias-corrected
+    m^ = m / (1 - b1^t), v^ = v / (1 - b2^t); theta <- theta - lr m^ / (sqrt(v^) + eps)."""
+    s.t += 1
+    s.b1t *= s.beta1
+    s.b2t *= s.beta2
+    out = []
+    for i, (th, g) in enumerate(zip(theta, grad)):
+        s.m[i] = s.beta1 * s.m[i] + (1.0 - s.beta1) * g
+        s.v[i] = s.beta2 * s.v[i] + (1.0 - s.beta2) * (g * g)
+        mh = s.m[i] / (1.0 - s.b1t)
+        vh = s.v[i] / (1.0 - s.b2t)
+        out.append(th - s.lr[i] * mh / (float(np.sqrt(vh)) + s.eps))
+    return out
+
+
+def calibrate(dem, mask, cell_size, base: dict, particles_per_cell, step_limit, seed, target, mu0, xi0, n_iters,
+              lr=(0.005, 50.0), beta1=0.9, beta2=0.999, eps=1e-8, mu_min=0.0, xi_min=1.0, run=0, mass=None):
+    """Adam on (mu, xi) against `target` (float32 (H, W)). Returns the history, one row per iteration:
+    (loss, mu, xi, dL/dmu, dL/dxi) at the iterate before its update, and the final (mu, xi). The model
+    sees mu and xi rounded to binary32; after each update they are clamped to mu >= mu_min, xi >= xi_min."""
+    s = adam_init(lr, beta1, beta2, eps)
+    mu, xi = float(mu0), float(xi0)
+    mu_lo, xi_lo = float(np.float32(mu_min)), float(np.float32(xi_min))
+    hist = []
+    for _ in range(n_iters):
+        p = make_params(**dict(base, mu=float(np.float32(mu)), xi=float(np.float32(xi))))
+        fwd = smooth_forward(dem, mask, cell_size, p, particles_per_cell, step_limit, seed, run, mass=mass)
+        loss, gD = mse_grad(deposit_of(fwd.dep_q), target)
+        g = smooth_backward(dem, mask, cell_size, p, particles_per_cell, step_limit, seed, gD, run, mass=mass)
+        hist.append((loss, mu, xi, g.dmu, g.dxi))
+        mu, xi = adam_step(s, [mu, xi], [g.dmu, g.dxi])
+        mu, xi = max(mu, mu_lo), max(xi, xi_lo)
+    return np.array(hist, np.float64), (mu, xi)
