@@ -238,6 +238,34 @@ def snow_leg(avl, torch, w, dem, reps: int) -> dict:
             "note": "per call, launch included (one kernel)"}
 
 
+def calibration_leg(avl, torch, iters: int = 60) -> dict:
+    """Calibration loop on the calibration scene: Adam on (mu, xi) from (0.26, 1400) against the deposit made
+    at (0.22, 1800), each iteration a smooth forward, the loss gradient and the adjoint."""
+    import synth
+    c = synth.make_calibration()
+    dem = torch.from_numpy(c.dem).cuda()
+    mask = torch.from_numpy(c.mask).cuda()
+    mass = torch.from_numpy(c.mass).cuda()
+    base = dict(flow_height=c.flow_height, persistence=0.9, randomness=0.16)
+    P, S, seed = c.particles_per_cell, c.step_limit, c.seed
+    target = avl.trajectories_smooth(dem, mask, c.cell_size, avl.Params.make(**dict(base, mu=c.mu_star, xi=c.xi_star)),
+                                     P, S, seed, mass=mass).deposit
+    start = avl.Params.make(**dict(base, mu=c.mu0, xi=c.xi0))
+    adam = avl.Adam.make(lr_mu=0.003, lr_xi=30.0)
+    avl.calibrate(dem, mask, c.cell_size, start, P, S, seed, target, 2, adam, mass=mass)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist, res = avl.calibrate(dem, mask, c.cell_size, start, P, S, seed, target, iters, adam, mass=mass)
+    dt = time.perf_counter() - t0
+    best = int(np.argmin(hist[:, 0]))
+    return {"iterations": iters, "s_total": dt, "ms_per_iteration": dt / iters * 1e3,
+            "start": {"mu": c.mu0, "xi": c.xi0}, "target": {"mu": c.mu_star, "xi": c.xi_star},
+            "final": {"mu": float(res.mu), "xi": float(res.xi)},
+            "loss_first": float(hist[0, 0]), "loss_last": float(hist[-1, 0]),
+            "best": {"iteration": best, "loss": float(hist[best, 0]), "mu": float(hist[best, 1]),
+                     "xi": float(hist[best, 2])}}
+
+
 def batched_leg(avl, torch, reps: int) -> dict:
     """Ensemble sweep: 16 ridged-fBm tiles of 1024^2 at 10 m, one release scenario each (103-26,397
     cells), crossed with 64 (mu, xi, h) sets: 1024 runs of 32 particles per cell and 2000 steps. Timed
@@ -476,6 +504,7 @@ def main() -> int:
         out["batched"] = batched_leg(avl, torch, 3)
     if not args.no_gradient:
         out["gradient"] = gradient_leg(avl, torch, 5)
+        out["calibration"] = calibration_leg(avl, torch)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, mask_np, args.cpu_stride)
         if args.cpu_procs > 0:

@@ -130,7 +130,8 @@ AVL_API int avl_trajectories(const float* dem, const uint8_t* mask, int32_t H, i
  * linear texture filter with clamp-to-edge addressing takes; nz is not renormalised), in binary32 as
  * top = a + fx(b - a), bottom = c + fx(d - c), value = top + fy(bottom - top), and tested as in
  * avl_release_mask. mult = 1 gives avl_release_mask's map. 1 <= mult <= AVL_MAX_RELEASE_MULT,
- * (mult H)(mult W) < 2^31; mask: (mult*H)*(mult*W) bytes; other arguments as avl_release_mask. */
+ * (mult H)(mult W) < 2^31, mult H and mult W < 2^23; mask: (mult*H)*(mult*W) bytes; other arguments as
+ * avl_release_mask. */
 AVL_API int avl_release_mask_fine(const float* normals4, const float* dem, int32_t H, int32_t W, int32_t mult,
                                   float slope_min_deg, float slope_max_deg, float z_min, float z_max, uint8_t* mask,
                                   void* stream);
@@ -221,6 +222,37 @@ AVL_API int avl_trajectories_backward(const float* dem, const uint8_t* mask, con
                                       uint32_t step_limit, uint64_t seed, uint32_t run_id, int32_t max_release_cells,
                                       const float* grad_deposit, double* dparams, float* dmass, float* per_particle,
                                       void* workspace, size_t workspace_bytes, void* stream);
+
+/* ---- Calibration loop: Adam (Kingma and Ba, ICLR 2015, algorithm 1) on (mu, xi) against a target deposit,
+ * the use the smooth variant and its adjoint exist for. Each iteration runs avl_trajectories_smooth at the
+ * current (mu, xi) rounded to binary32, the loss L = sum (D - T)^2 / N over the H*W deposit D (the fixed
+ * point raster as float) and its gradient dL/dD = c (D - T) with c = 2/N in binary32 (L summed in binary64
+ * in a fixed order), then avl_trajectories_backward, and updates (mu, xi) in binary64 on the host:
+ *   m <- b1 m + (1 - b1) g;  v <- b2 v + (1 - b2) g^2;  theta <- theta - lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps),
+ * then clamps mu >= mu_min and xi >= xi_min. The other parameters stay those of *start. */
+typedef struct avl_adam {
+    float lr_mu, lr_xi;      /* step sizes, finite, > 0 (e.g. 0.003 and 30) */
+    float beta1, beta2;      /* moment decay rates in [0, 1) (e.g. 0.9 and 0.999) */
+    float eps;               /* denominator guard, finite, > 0 (e.g. 1e-8) */
+    float mu_min, xi_min;    /* lower bounds of the iterates: finite, mu_min >= 0, xi_min > 0 */
+} avl_adam;
+
+/* Workspace bytes avl_calibrate needs (0 if an argument is out of range): the smooth pass's workspace plus
+ * the deposit, its gradient and the reductions. */
+AVL_API size_t avl_calibrate_workspace_bytes(int32_t H, int32_t W, int32_t max_release_cells,
+                                             uint32_t particles_per_cell, uint32_t step_limit);
+
+/* n_iters Adam iterations from (start->mu, start->xi) (start->xi finite). target: H*W float deposit on the
+ * device. history (host, nullable when n_iters = 0): n_iters rows of 5 doubles, (L, mu, xi, dL/dmu, dL/dxi)
+ * at each iterate before its update. result (host): *start with the final mu and xi (binary32). The other
+ * arguments are those of avl_trajectories_smooth. The call waits for the stream once per iteration (the
+ * update needs the gradient on the host). A mask with more release cells than max_release_cells returns
+ * AVL_EINVAL after the first iteration. */
+AVL_API int avl_calibrate(const float* dem, const uint8_t* mask, const float* mass, int32_t H, int32_t W,
+                          float cell_size, const avl_params* start, uint32_t particles_per_cell, uint32_t step_limit,
+                          uint64_t seed, uint32_t run_id, int32_t max_release_cells, const float* target,
+                          int32_t n_iters, const avl_adam* adam, double* history, avl_params* result,
+                          void* workspace, size_t workspace_bytes, void* stream);
 
 /* Overlay mipmap (section 3: a mipmap of the full-resolution overlay texture is the multi-resolution
  * overlay the renderer samples). Level l + 1 halves level l, rounding up: its cell (r, c) covers cells

@@ -46,6 +46,16 @@ class Params(ctypes.Structure):
         return cls(mu, xi, flow_height, persistence, randomness, step_cells, tan_alpha, flags)
 
 
+class Adam(ctypes.Structure):
+    _fields_ = [("lr_mu", ctypes.c_float), ("lr_xi", ctypes.c_float), ("beta1", ctypes.c_float),
+                ("beta2", ctypes.c_float), ("eps", ctypes.c_float), ("mu_min", ctypes.c_float),
+                ("xi_min", ctypes.c_float)]
+
+    @classmethod
+    def make(cls, lr_mu=0.003, lr_xi=30.0, beta1=0.9, beta2=0.999, eps=1e-8, mu_min=0.0, xi_min=1.0):
+        return cls(lr_mu, lr_xi, beta1, beta2, eps, mu_min, xi_min)
+
+
 class Run(ctypes.Structure):
     """Mirror of ``avl_run``: one run of a batch."""
     _fields_ = [("tile", ctypes.c_uint32), ("scenario", ctypes.c_uint32), ("param", ctypes.c_uint32),
@@ -92,6 +102,11 @@ def _load() -> ctypes.CDLL:
     L.avl_trajectories_backward.argtypes = [vp, vp, vp, i32, i32, f32, ctypes.POINTER(Params), u32, u32, u64, u32,
                                             i32, vp, vp, vp, vp, vp, sz, vp]
     L.avl_trajectories_backward.restype = ctypes.c_int
+    L.avl_calibrate_workspace_bytes.argtypes = [i32, i32, i32, u32, u32]
+    L.avl_calibrate_workspace_bytes.restype = sz
+    L.avl_calibrate.argtypes = [vp, vp, vp, i32, i32, f32, ctypes.POINTER(Params), u32, u32, u64, u32, i32, vp, i32,
+                                ctypes.POINTER(Adam), vp, ctypes.POINTER(Params), vp, sz, vp]
+    L.avl_calibrate.restype = ctypes.c_int
     L.avl_set_tuning.argtypes = [i32, i32]
     L.avl_set_tuning.restype = ctypes.c_int
     L.avl_tuning_variants.argtypes = []
@@ -453,6 +468,34 @@ def trajectories_backward(run: SmoothRun, dem: torch.Tensor, mask: torch.Tensor,
                                              run.workspace.data_ptr(), run.workspace.numel(), _stream(dev)),
                "avl_trajectories_backward")
     return dparams, dmass, pp
+
+
+def calibrate(dem: torch.Tensor, mask: torch.Tensor, cell_size: float, start: Params, particles_per_cell: int,
+              step_limit: int, seed: int, target: torch.Tensor, n_iters: int, adam: Adam | None = None,
+              run_id: int = 0, mass: torch.Tensor | None = None, max_release_cells: int | None = None):
+    """Adam on (mu, xi) against `target`: (history float64 (n_iters, 5) of (L, mu, xi, dL/dmu, dL/dxi) per
+    iterate, final Params)."""
+    import numpy as np
+    _need(dem, "dem", torch.float32, 2)
+    _need(mask, "mask", torch.uint8, 2)
+    _need(target, "target", torch.float32, 2)
+    h, w = dem.shape
+    if mass is not None:
+        _need(mass, "mass", torch.float32, 2)
+    if max_release_cells is None:
+        max_release_cells = int(mask.count_nonzero().item())
+    adam = adam or Adam.make()
+    nb = int(lib.avl_calibrate_workspace_bytes(h, w, max_release_cells, particles_per_cell, step_limit))
+    hist = np.zeros((max(n_iters, 1), 5), np.float64)
+    result = Params()
+    with torch.cuda.device(dem.device):
+        ws = _workspace(dem.device, max(nb, 256))
+        _check(lib.avl_calibrate(dem.data_ptr(), mask.data_ptr(), mass.data_ptr() if mass is not None else None, h, w,
+                                 cell_size, ctypes.byref(start), particles_per_cell, step_limit, seed & (2**64 - 1),
+                                 run_id, max_release_cells, target.data_ptr(), n_iters, ctypes.byref(adam),
+                                 hist.ctypes.data_as(ctypes.c_void_p), ctypes.byref(result), ws.data_ptr(), ws.numel(),
+                                 _stream(dem.device)), "avl_calibrate")
+    return hist[:n_iters], result
 
 
 class SmoothDeposit(torch.autograd.Function):

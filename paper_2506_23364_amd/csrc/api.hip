@@ -560,6 +560,8 @@ int avl_release_mask_fine(const float* normals4, const float* dem, int32_t H, in
         return fail(AVL_EINVAL, "avl_release_mask_fine: mult must be in [1, %d]", AVL_MAX_RELEASE_MULT);
     if ((int64_t)H * W * mult * mult >= (int64_t(1) << 31))
         return fail(AVL_EINVAL, "avl_release_mask_fine: need (mult H)(mult W) < 2^31");
+    if ((int64_t)mult * W >= (int64_t(1) << 23) || (int64_t)mult * H >= (int64_t(1) << 23))
+        return fail(AVL_EINVAL, "avl_release_mask_fine: need mult W and mult H < 2^23");
     if (reinterpret_cast<uintptr_t>(normals4) & 15)
         return fail(AVL_EINVAL, "avl_release_mask_fine: normals4 not 16-byte aligned");
     if (!(slope_min_deg >= 0.0f && slope_min_deg <= slope_max_deg && slope_max_deg <= 90.0f))
@@ -860,5 +862,141 @@ int avl_trajectories_batched(const float* dems, int32_t n_tiles, const uint8_t* 
     if ((e = hipGraphLaunch(it->second.exec, s)) != hipSuccess) return hip_fail(e, "avl_trajectories_batched: launch");
     return AVL_OK;
 }
+
+// ------------------------------------------------------------------ calibration loop
+namespace {
+
+struct CalibWs {
+    char* smooth;      // the smooth pass's own workspace (checkpoints for the adjoint)
+    size_t smooth_bytes;
+    int64_t* dep_q;    // H*W
+    float* dep;        // H*W
+    float* gD;         // H*W
+    float* dmass;      // H*W
+    double* part;      // loss partial sums
+    double* scal;      // [loss, dL/dmu, dL/dxi, dL/dh]
+    int32_t* status;   // smooth pass status
+};
+
+size_t calib_layout(int32_t H, int32_t W, int32_t max_cells, uint32_t P, uint32_t S, char* base, CalibWs* c) {
+    const int64_t n = (int64_t)H * W;
+    const size_t sm = avl::round256(avl_smooth_workspace_bytes(H, W, max_cells, P, S));
+    size_t off = sm;
+    auto take = [&](size_t bytes) {
+        char* p = base ? base + off : nullptr;
+        off += avl::round256(bytes);
+        return p;
+    };
+    char* dq = take((size_t)n * 8);
+    char* d = take((size_t)n * 4);
+    char* g = take((size_t)n * 4);
+    char* dm = take((size_t)n * 4);
+    char* pt = take(avl::mse_partials() * sizeof(double));
+    char* sc = take(4 * sizeof(double) + sizeof(int32_t));
+    if (c) {
+        c->smooth = base;
+        c->smooth_bytes = sm;
+        c->dep_q = reinterpret_cast<int64_t*>(dq);
+        c->dep = reinterpret_cast<float*>(d);
+        c->gD = reinterpret_cast<float*>(g);
+        c->dmass = reinterpret_cast<float*>(dm);
+        c->part = reinterpret_cast<double*>(pt);
+        c->scal = reinterpret_cast<double*>(sc);
+        c->status = reinterpret_cast<int32_t*>(sc + 4 * sizeof(double));
+    }
+    return off;
+}
+
+}  // namespace
+
+size_t avl_calibrate_workspace_bytes(int32_t H, int32_t W, int32_t max_release_cells, uint32_t particles_per_cell,
+                                     uint32_t step_limit) {
+    if (avl_smooth_workspace_bytes(H, W, max_release_cells, particles_per_cell, step_limit) == 0) return 0;
+    return calib_layout(H, W, max_release_cells, particles_per_cell, step_limit, nullptr, nullptr);
+}
+
+int avl_calibrate(const float* dem, const uint8_t* mask, const float* mass, int32_t H, int32_t W, float cell_size,
+                  const avl_params* start, uint32_t particles_per_cell, uint32_t step_limit, uint64_t seed,
+                  uint32_t run_id, int32_t max_release_cells, const float* target, int32_t n_iters,
+                  const avl_adam* adam, double* history, avl_params* result, void* workspace, size_t workspace_bytes,
+                  void* stream) {
+    g_last_error.clear();
+    const char* where = "avl_calibrate";
+    if (!target || !adam || !result || !workspace || !start) return fail(AVL_EINVAL, "%s: null pointer", where);
+    if (n_iters < 0) return fail(AVL_EINVAL, "%s: n_iters must be >= 0", where);
+    if (n_iters > 0 && !history) return fail(AVL_EINVAL, "%s: history is NULL", where);
+    if (!(finite(adam->lr_mu) && adam->lr_mu > 0.0f && finite(adam->lr_xi) && adam->lr_xi > 0.0f))
+        return fail(AVL_EINVAL, "%s: step sizes must be finite and > 0", where);
+    if (!(adam->beta1 >= 0.0f && adam->beta1 < 1.0f && adam->beta2 >= 0.0f && adam->beta2 < 1.0f))
+        return fail(AVL_EINVAL, "%s: need 0 <= beta1, beta2 < 1", where);
+    if (!(finite(adam->eps) && adam->eps > 0.0f)) return fail(AVL_EINVAL, "%s: eps must be finite and > 0", where);
+    if (!(finite(adam->mu_min) && adam->mu_min >= 0.0f && finite(adam->xi_min) && adam->xi_min > 0.0f))
+        return fail(AVL_EINVAL, "%s: need finite mu_min >= 0 and xi_min > 0", where);
+    if (!finite(start->xi)) return fail(AVL_EINVAL, "%s: the start xi must be finite", where);
+    if (workspace_bytes < avl_calibrate_workspace_bytes(H, W, max_release_cells, particles_per_cell, step_limit))
+        return fail(AVL_ENOMEM, "%s: workspace too small", where);
+    CalibWs c;
+    calib_layout(H, W, max_release_cells, particles_per_cell, step_limit, static_cast<char*>(workspace), &c);
+    int rc = smooth_checks(where, dem, mask, H, W, cell_size, start, particles_per_cell, step_limit,
+                           max_release_cells, c.smooth, c.smooth_bytes);
+    if (rc != AVL_OK) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t n = (int64_t)H * W;
+    const float cgrad = 2.0f / (float)n;
+    const double lr[2] = {(double)adam->lr_mu, (double)adam->lr_xi};
+    const double b1 = adam->beta1, b2 = adam->beta2, eps = adam->eps;
+    const double lo[2] = {(double)adam->mu_min, (double)adam->xi_min};
+    double th[2] = {(double)start->mu, (double)start->xi};
+    double m[2] = {0.0, 0.0}, v[2] = {0.0, 0.0};
+    double b1t = 1.0, b2t = 1.0;
+    for (int32_t t = 0; t < n_iters; ++t) {
+        avl_params p = *start;
+        p.mu = (float)th[0];
+        p.xi = (float)th[1];
+        if ((rc = avl_trajectories_smooth(dem, mask, mass, H, W, cell_size, &p, particles_per_cell, step_limit, seed,
+                                          run_id, max_release_cells, 0u, c.dep_q, c.dep, nullptr, nullptr, nullptr,
+                                          c.status, c.smooth, c.smooth_bytes, stream)) != AVL_OK)
+            return rc;
+        hipError_t e = avl::launch_mse_grad(c.dep, target, n, cgrad, c.gD, c.part, c.scal, s);
+        if (e != hipSuccess) return hip_fail(e, "avl_calibrate: loss");
+        if ((rc = avl_trajectories_backward(dem, mask, mass, H, W, cell_size, &p, particles_per_cell, step_limit, seed,
+                                            run_id, max_release_cells, c.gD, c.scal + 1, c.dmass, nullptr, c.smooth,
+                                            c.smooth_bytes, stream)) != AVL_OK)
+            return rc;
+        struct {
+            double v[4];
+            int32_t status;
+        } h{};
+        if ((e = hipMemcpyAsync(&h, c.scal, 4 * sizeof(double) + sizeof(int32_t), hipMemcpyDeviceToHost, s)) !=
+                hipSuccess ||
+            (e = hipStreamSynchronize(s)) != hipSuccess)
+            return hip_fail(e, "avl_calibrate: read back");
+        if (h.status != 0)
+            return fail(AVL_EINVAL, "%s: the mask has more release cells than max_release_cells", where);
+        double* row = history + 5 * (int64_t)t;
+        row[0] = h.v[0];
+        row[1] = th[0];
+        row[2] = th[1];
+        row[3] = h.v[1];
+        row[4] = h.v[2];
+        // Adam (Kingma and Ba 2015, algorithm 1), bias corrections from running products of the rates
+        b1t *= b1;
+        b2t *= b2;
+        for (int k = 0; k < 2; ++k) {
+            const double g = h.v[1 + k];
+            m[k] = b1 * m[k] + (1.0 - b1) * g;
+            v[k] = b2 * v[k] + (1.0 - b2) * (g * g);
+            const double mh = m[k] / (1.0 - b1t);
+            const double vh = v[k] / (1.0 - b2t);
+            th[k] = th[k] - lr[k] * mh / (std::sqrt(vh) + eps);
+            if (th[k] < lo[k]) th[k] = lo[k];
+        }
+    }
+    *result = *start;
+    result->mu = (float)th[0];
+    result->xi = (float)th[1];
+    return AVL_OK;
+}
+
 
 }  // extern "C"

@@ -194,6 +194,10 @@ hipError_t launch_smooth_forward(const SmoothArgs& a, hipStream_t s);
 hipError_t launch_smooth_backward(const SmoothArgs& a, const int32_t* n_cells, float* dmass, int64_t n_grid,
                                   double* part, double* dparams, hipStream_t s);
 hipError_t launch_q_to_float(const unsigned long long* q, int64_t n, float* out, hipStream_t s);
+// calibration loss: gD = c (D - T) and L = sum (D - T)^2 / N (binary64, fixed order) into *loss
+hipError_t launch_mse_grad(const float* dep, const float* target, int64_t n, float c, float* gD, double* part,
+                           double* loss, hipStream_t s);
+size_t mse_partials();
 hipError_t launch_finalize_vmax(uint32_t* vmax_bits, int64_t n, hipStream_t s);
 
 // Persistent-grid shape of kernel variant `variant` on the current device; number of variants.

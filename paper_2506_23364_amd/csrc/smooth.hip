@@ -420,6 +420,57 @@ __global__ __launch_bounds__(256) void k_q_to_float(const unsigned long long* __
     if (i < n) out[i] = (float)((double)(long long)q[i] * 0x1p-24);
 }
 
+// ------------------------------------------------------------------------------------------ calibration loss
+// L = sum (D - T)^2 / N and dL/dD = c (D - T), c = 2/N rounded to binary32. The differences are binary32;
+// their squares are exact in binary64 and summed in a fixed order (per thread over a fixed grid stride,
+// then over the wave, the block, and the kMseBlocks block sums), so L does not depend on timing.
+constexpr int kMseBlocks = 1024;
+constexpr int kMseThreads = 256;
+
+__device__ __forceinline__ double block_sum_f64(double v, double* lds) {
+#pragma unroll
+    for (int d = kWave / 2; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    if (lane == 0) lds[wid] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < (int)(blockDim.x / kWave); ++k) t += lds[k];
+    return t;  // valid in thread 0
+}
+
+__global__ __launch_bounds__(kMseThreads) void k_mse_partial(const float* __restrict__ dep,
+                                                           const float* __restrict__ tgt, int64_t n, float c,
+                                                           float* __restrict__ gD, double* __restrict__ part) {
+    __shared__ double lds[kMseThreads / kWave];
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kMseThreads + threadIdx.x; i < n; i += (int64_t)kMseBlocks * kMseThreads) {
+        const float d = dep[i] - tgt[i];
+        gD[i] = c * d;
+        acc += (double)d * (double)d;
+    }
+    const double t = block_sum_f64(acc, lds);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(kMseThreads) void k_mse_final(const double* __restrict__ part, double n,
+                                                         double* __restrict__ loss) {
+    __shared__ double lds[kMseThreads / kWave];
+    double acc = 0.0;
+    for (int k = threadIdx.x; k < kMseBlocks; k += kMseThreads) acc += part[k];
+    const double t = block_sum_f64(acc, lds);
+    if (threadIdx.x == 0) *loss = t / n;
+}
+
+hipError_t launch_mse_grad(const float* dep, const float* target, int64_t n, float c, float* gD, double* part,
+                           double* loss, hipStream_t s) {
+    hipLaunchKernelGGL(k_mse_partial, dim3(kMseBlocks), dim3(kMseThreads), 0, s, dep, target, n, c, gD, part);
+    hipLaunchKernelGGL(k_mse_final, dim3(1), dim3(kMseThreads), 0, s, part, (double)n, loss);
+    return hipGetLastError();
+}
+
+size_t mse_partials() { return kMseBlocks; }
+
 // ------------------------------------------------------------------------------------------ launchers
 
 size_t smooth_checkpoints(uint32_t S) { return S == 0 ? 0 : (S + kCkpt - 1) / kCkpt; }

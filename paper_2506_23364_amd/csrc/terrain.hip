@@ -146,20 +146,34 @@ hipError_t launch_snow_cover(const float* normals4, const float* dem, int64_t n,
 // ------------------------------------------------------------------------------------------ fine release map
 // Release texture with mult x mult texels per DEM cell: texel (R, C) is centred at ((C + 1/2) / mult,
 // (R + 1/2) / mult) in DEM cell units, where nz and the height are filtered bilinearly between texel centres
-// with clamped indices and tested against the same bounds as the plain map. Four consecutive texels of a
-// row per thread (one 4-byte store); the row's vertical weights and rows are shared by the four, and the
-// DEM cells a thread reads are re-read by its neighbours from L1/L2.
-__global__ __launch_bounds__(256) void k_release_mask_fine(const float4* __restrict__ nrm,
-                                                           const float* __restrict__ dem, int H, int W, int mult,
-                                                           int64_t quads_per_row, int64_t n_quads, float cmin,
-                                                           float cmax, float zmin, float zmax,
-                                                           uint8_t* __restrict__ mask) {
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= n_quads) return;
+// with clamped indices and tested against the same bounds as the plain map. A block covers kFineSpan
+// consecutive texels of one row (row and span from the block index, once per block). The block first
+// stages nz and the height of the two DEM rows and the column range its texels touch in LDS (coalesced
+// reads; the column range is exact because the texel centres and their floors grow with C), then each
+// thread filters four texels from LDS and stores their four bytes at once.
+constexpr int kFineThreads = 256;
+constexpr int kFineSpan = 4 * kFineThreads;
+constexpr int kFineCols = kFineSpan + 3;  // columns a span can touch at mult = 1 (kFineSpan + 1), with margin
+
+__device__ __forceinline__ int fine_col(int64_t C, float fm) {  // floor(x - 1/2) of texel column C's centre
+    const float x = ((float)C + 0.5f) / fm;
+    return (int)floorf(x - 0.5f);
+}
+
+__global__ __launch_bounds__(kFineThreads) void k_release_mask_fine(const float4* __restrict__ nrm,
+                                                                    const float* __restrict__ dem, int H, int W,
+                                                                    int mult, uint32_t spans_per_row, float cmin,
+                                                                    float cmax, float zmin, float zmax,
+                                                                    uint8_t* __restrict__ mask) {
+    __shared__ float s_n[2][kFineCols], s_z[2][kFineCols];
+    const uint32_t rr = blockIdx.x / spans_per_row;  // uniform
+    const uint32_t span = blockIdx.x - rr * spans_per_row;
     const int64_t Wf = (int64_t)W * mult;
-    const int64_t rr = q / quads_per_row;
-    const int64_t c0 = (q - rr * quads_per_row) * 4;
+    const int64_t cs0 = (int64_t)span * kFineSpan;
+    const int64_t cs1 = min(cs0 + kFineSpan, Wf) - 1;  // last texel column of the span
     const float fm = (float)mult;
+    const int lo = min(max(fine_col(cs0, fm), 0), W - 1);
+    const int hi = min(max(fine_col(cs1, fm) + 1, 0), W - 1);
     const float y = ((float)rr + 0.5f) / fm;
     const float sy = y - 0.5f;
     const float fr = floorf(sy);
@@ -167,25 +181,37 @@ __global__ __launch_bounds__(256) void k_release_mask_fine(const float4* __restr
     const int r0 = (int)fr;
     const int64_t ra = (int64_t)min(max(r0, 0), H - 1) * W;
     const int64_t rb = (int64_t)min(max(r0 + 1, 0), H - 1) * W;
+    for (int k = threadIdx.x; k <= hi - lo; k += kFineThreads) {
+        s_n[0][k] = nrm[ra + lo + k].z;
+        s_n[1][k] = nrm[rb + lo + k].z;
+        s_z[0][k] = dem[ra + lo + k];
+        s_z[1][k] = dem[rb + lo + k];
+    }
+    __syncthreads();
+    const int64_t c0 = cs0 + 4 * threadIdx.x;
+    if (c0 >= Wf) return;
     uint32_t packed = 0;
     const int nk = (int)min((int64_t)4, Wf - c0);
-    for (int k = 0; k < nk; ++k) {
-        const float x = ((float)(c0 + k) + 0.5f) / fm;
-        const float sx = x - 0.5f;
-        const float fc = floorf(sx);
-        const float fx = sx - fc;
-        const int cc = (int)fc;
-        const int ca = min(max(cc, 0), W - 1), cb = min(max(cc + 1, 0), W - 1);
-        const float n00 = nrm[ra + ca].z, n01 = nrm[ra + cb].z, n10 = nrm[rb + ca].z, n11 = nrm[rb + cb].z;
-        const float ntop = n00 + fx * (n01 - n00), nbot = n10 + fx * (n11 - n10);
-        const float nz = ntop + fy * (nbot - ntop);
-        const float z00 = dem[ra + ca], z01 = dem[ra + cb], z10 = dem[rb + ca], z11 = dem[rb + cb];
-        const float ztop = z00 + fx * (z01 - z00), zbot = z10 + fx * (z11 - z10);
-        const float z = ztop + fy * (zbot - ztop);
-        const uint32_t m = (cmin <= nz && nz <= cmax && zmin <= z && z <= zmax) ? 1u : 0u;
-        packed |= m << (8 * k);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (k < nk) {
+            const float x = ((float)(c0 + k) + 0.5f) / fm;
+            const float sx = x - 0.5f;
+            const float fc = floorf(sx);
+            const float fx = sx - fc;
+            const int cc = (int)fc;
+            const int ca = min(max(cc, 0), W - 1) - lo, cb = min(max(cc + 1, 0), W - 1) - lo;
+            const float n00 = s_n[0][ca], n01 = s_n[0][cb], n10 = s_n[1][ca], n11 = s_n[1][cb];
+            const float ntop = n00 + fx * (n01 - n00), nbot = n10 + fx * (n11 - n10);
+            const float nz = ntop + fy * (nbot - ntop);
+            const float z00 = s_z[0][ca], z01 = s_z[0][cb], z10 = s_z[1][ca], z11 = s_z[1][cb];
+            const float ztop = z00 + fx * (z01 - z00), zbot = z10 + fx * (z11 - z10);
+            const float z = ztop + fy * (zbot - ztop);
+            const uint32_t m = (cmin <= nz && nz <= cmax && zmin <= z && z <= zmax) ? 1u : 0u;
+            packed |= m << (8 * k);
+        }
     }
-    uint8_t* out = mask + rr * Wf + c0;
+    uint8_t* out = mask + (int64_t)rr * Wf + c0;
     if (nk == 4 && (reinterpret_cast<uintptr_t>(out) & 3) == 0) {
         *reinterpret_cast<uint32_t*>(out) = packed;
     } else {
@@ -196,12 +222,11 @@ __global__ __launch_bounds__(256) void k_release_mask_fine(const float4* __restr
 hipError_t launch_release_mask_fine(const float* normals4, const float* dem, int H, int W, int mult, float cmin,
                                     float cmax, float zmin, float zmax, uint8_t* mask, hipStream_t s) {
     const int64_t Wf = (int64_t)W * mult, Hf = (int64_t)H * mult;
-    const int64_t qpr = (Wf + 3) / 4;
-    const int64_t nq = qpr * Hf;
-    const int64_t blocks = (nq + 255) / 256;
-    hipLaunchKernelGGL(k_release_mask_fine, dim3((unsigned)blocks), dim3(256), 0, s,
-                       reinterpret_cast<const float4*>(normals4), dem, H, W, mult, qpr, nq, cmin, cmax, zmin, zmax,
-                       mask);
+    const int64_t spans = (Wf + kFineSpan - 1) / kFineSpan;
+    const int64_t blocks = spans * Hf;  // < 2^31 / 1024 * 2 + Hf: fits a 32-bit grid
+    hipLaunchKernelGGL(k_release_mask_fine, dim3((unsigned)blocks), dim3(kFineThreads), 0, s,
+                       reinterpret_cast<const float4*>(normals4), dem, H, W, mult, (uint32_t)spans, cmin, cmax, zmin,
+                       zmax, mask);
     return hipGetLastError();
 }
 

@@ -172,7 +172,8 @@ def test_trajectories_fine_small_workspace(L):
 
 @pytest.mark.parametrize("args", [
     dict(nrm=None), dict(dem=None), dict(mask=None), dict(mult=0), dict(mult=17), dict(H=0),
-    dict(H=30000, W=30000, mult=2), dict(nrm=FAKE + 4), dict(smin=50.0, smax=40.0), dict(smax=91.0),
+    dict(H=30000, W=30000, mult=2), dict(H=(1 << 22), W=2, mult=2), dict(nrm=FAKE + 4),
+    dict(smin=50.0, smax=40.0), dict(smax=91.0),
     dict(zmin=float("nan")),
 ])
 def test_release_mask_fine_rejects_bad_arguments(L, args):
@@ -195,3 +196,44 @@ def test_snow_cover_rejects_bad_arguments(L, args):
                               a["alpha"], None)
     assert rc == L.AVL_EINVAL
     assert L.lib.avl_last_error()
+
+
+def _calib(L, **kw):
+    a = dict(dem=FAKE, mask=FAKE, mass=None, H=16, W=16, cs=10.0, start=L.Params.make(), P=4, S=100, seed=1, run=0,
+             cap=10, target=FAKE, iters=3, adam=L.Adam.make(), hist=FAKE, res=L.Params(), ws=FAKE,
+             wsb=L.lib.avl_calibrate_workspace_bytes(16, 16, 10, 4, 100), stream=None)
+    a.update(kw)
+    return L.lib.avl_calibrate(a["dem"], a["mask"], a["mass"], a["H"], a["W"], a["cs"],
+                               ctypes.byref(a["start"]) if a["start"] else None, a["P"], a["S"], a["seed"], a["run"],
+                               a["cap"], a["target"], a["iters"], ctypes.byref(a["adam"]) if a["adam"] else None,
+                               a["hist"], ctypes.byref(a["res"]) if a["res"] is not None else None, a["ws"], a["wsb"],
+                               a["stream"])
+
+
+def test_calibrate_workspace_size(L):
+    assert L.lib.avl_calibrate_workspace_bytes(16, 16, 10, 4, 100) >= \
+        L.smooth_workspace_bytes(16, 16, 10, 4, 100) + 16 * 16 * 20
+    assert L.lib.avl_calibrate_workspace_bytes(0, 16, 10, 4, 100) == 0
+
+
+@pytest.mark.parametrize("kw", [
+    dict(dem=None), dict(target=None), dict(adam=None), dict(res=None), dict(ws=None), dict(start=None),
+    dict(hist=None), dict(iters=-1), dict(H=0), dict(P=0), dict(cs=0.0),
+])
+def test_calibrate_rejects_bad_arguments(L, kw):
+    assert _calib(L, **kw) == L.AVL_EINVAL
+    assert L.lib.avl_last_error()
+
+
+@pytest.mark.parametrize("field,value", [
+    ("lr_mu", 0.0), ("lr_xi", float("inf")), ("beta1", 1.0), ("beta2", -0.1), ("eps", 0.0), ("mu_min", -1.0),
+    ("xi_min", 0.0),
+])
+def test_calibrate_rejects_bad_adam(L, field, value):
+    adam = L.Adam.make()
+    setattr(adam, field, value)
+    assert _calib(L, adam=adam) == L.AVL_EINVAL
+
+
+def test_calibrate_small_workspace(L):
+    assert _calib(L, wsb=L.lib.avl_calibrate_workspace_bytes(16, 16, 10, 4, 100) - 1) == L.AVL_ENOMEM

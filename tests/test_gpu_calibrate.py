@@ -1,0 +1,115 @@
+"""GPU parity of the calibration loop (avl_calibrate) and of a runout-angle sweep as a model variant.
+
+* calibration: the per-iteration history (loss, mu, xi, dL/dmu, dL/dxi) against the oracle's Adam loop on
+  the same scene. The deposits are bit-exact, so the losses differ only in the order of the binary64 sum
+  (1e-12 relative) and the gradients in the order of the per-particle sums (1e-9 of the sum of their
+  magnitudes, as for the adjoint alone); the iterates follow within 1e-9 relative. At the full calibration
+  size the first iteration is checked against the oracle and 60 iterations must bring (mu, xi) from
+  (0.26, 1400) to within (0.01, 200) of the target's (0.22, 1800), with the loss down a hundredfold.
+* runout angle: one batched call sweeping tan(alpha) (off, 0.3 ... 0.6) over one release scenario equals
+  the oracle run by run, and a larger angle never lengthens the runout (fewer visited cells and steps).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def avl():
+    import paper_2506_23364_amd as m
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return m
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def f32(v):
+    return float(np.float32(v))
+
+
+@pytest.fixture(scope="module")
+def scene():
+    c = synth.make_calibration()
+    base = dict(flow_height=c.flow_height, persistence=0.9, randomness=0.16)
+    return c, base
+
+
+def target_for(c, base, P):
+    pt = oracle.make_params(**dict(base, mu=c.mu_star, xi=c.xi_star))
+    fwd = oracle.smooth_forward(c.dem, c.mask, c.cell_size, pt, P, c.step_limit, c.seed, mass=c.mass)
+    return oracle.deposit_of(fwd.dep_q)
+
+
+def compare(hist, ref, label):
+    assert hist.shape == ref.shape, label
+    np.testing.assert_allclose(hist[:, 0], ref[:, 0], rtol=1e-12, atol=0, err_msg=label)
+    np.testing.assert_allclose(hist[:, 1:3], ref[:, 1:3], rtol=1e-9, atol=0, err_msg=label)
+    np.testing.assert_allclose(hist[:, 3:5], ref[:, 3:5], rtol=1e-7, atol=1e-12, err_msg=label)
+
+
+def test_calibration_history_matches_oracle(avl, scene):
+    c, base = scene
+    P, iters = 4, 8
+    target = target_for(c, base, P)
+    mu0, xi0 = f32(c.mu0), f32(c.xi0)
+    ref, (mu_r, xi_r) = oracle.calibrate(c.dem, c.mask, c.cell_size, base, P, c.step_limit, c.seed, target, mu0, xi0,
+                                         iters, lr=(0.003, 30.0), mass=c.mass)
+    start = avl.Params.make(**dict(base, mu=mu0, xi=xi0))
+    hist, res = avl.calibrate(dev(c.dem), dev(c.mask), c.cell_size, start, P, c.step_limit, c.seed, dev(target),
+                              iters, avl.Adam.make(lr_mu=0.003, lr_xi=30.0), mass=dev(c.mass))
+    compare(hist, ref, "calibration P=4")
+    assert res.mu == f32(mu_r) and res.xi == f32(xi_r)
+    assert res.persistence == f32(0.9) and res.flow_height == f32(c.flow_height)
+
+
+def test_calibration_zero_iterations(avl, scene):
+    c, base = scene
+    start = avl.Params.make(**dict(base, mu=0.3, xi=1000.0))
+    hist, res = avl.calibrate(dev(c.dem), dev(c.mask), c.cell_size, start, 2, 100, c.seed,
+                              torch.zeros(c.dem.shape, dtype=torch.float32, device="cuda"), 0)
+    assert hist.shape == (0, 5) and res.mu == start.mu and res.xi == start.xi
+
+
+def test_calibration_full_size_recovers_target(avl, scene):
+    c, base = scene
+    P = c.particles_per_cell
+    target = target_for(c, base, P)
+    mu0, xi0 = f32(c.mu0), f32(c.xi0)
+    ref, _ = oracle.calibrate(c.dem, c.mask, c.cell_size, base, P, c.step_limit, c.seed, target, mu0, xi0, 1,
+                              lr=(0.003, 30.0), mass=c.mass)
+    start = avl.Params.make(**dict(base, mu=mu0, xi=xi0))
+    hist, res = avl.calibrate(dev(c.dem), dev(c.mask), c.cell_size, start, P, c.step_limit, c.seed, dev(target), 60,
+                              avl.Adam.make(lr_mu=0.003, lr_xi=30.0), mass=dev(c.mass))
+    compare(hist[:1], ref, "first iteration, full size")
+    assert hist[:, 0].min() < 0.01 * hist[0, 0]
+    assert abs(res.mu - c.mu_star) < 0.01 and abs(res.xi - c.xi_star) < 200.0
+
+
+def test_runout_angle_sweep(avl):
+    dem = synth.alpine_dem(160, 900.0, seed=71)[:150, :141].copy()
+    sl = synth.slope_deg(dem, 10.0)
+    mask = ((sl >= 28) & (sl <= 48) & (dem >= np.quantile(dem, 0.6))).astype(np.uint8)
+    angles = [-1.0, 0.3, 0.4, 0.5, 0.6]
+    params = [dict(synth.DEFAULT_PARAMS, mu=0.1, xi=2500.0, tan_alpha=a) for a in angles]
+    runs = [(0, 0, k, 0, 99) for k in range(len(angles))]  # one random stream: the paths agree until they stop
+    P, S = 8, 1500
+    res = avl.trajectories_batched(dev(dem[None]), dev(mask[None]), 10.0, avl.params_tensor(params, "cuda"),
+                                   avl.runs_tensor(runs, "cuda"), P, S)
+    counts, stats = res.counts.cpu().numpy(), res.stats.cpu().numpy()
+    visited, steps = [], []
+    for k, a in enumerate(angles):
+        ref = oracle.trajectories(dem, mask, 10.0, oracle.make_params(**params[k]), P, S, 99, 0)
+        assert np.array_equal(counts[k], ref.counts), f"tan_alpha {a}"
+        assert list(stats[k]) == [ref.steps, ref.n_exit, ref.n_stop, ref.n_limit]
+        visited.append(int((counts[k] > 0).sum()))
+        steps.append(int(stats[k][0]))
+    assert all(visited[i + 1] <= visited[i] for i in range(len(angles) - 1)), visited
+    assert all(steps[i + 1] <= steps[i] for i in range(len(angles) - 1)), steps
+    assert visited[-1] < visited[0]
