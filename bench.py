@@ -82,7 +82,9 @@ def parse():
                     help="processes of the full-pass oracle run (0 to skip it)")
     ap.add_argument("--cpu-stride", type=int, default=0, help="oracle sample: every n-th release cell (0 = auto)")
     ap.add_argument("--no-batched", action="store_true", help="skip the ensemble (batched vs plain) leg")
-    ap.add_argument("--no-gradient", action="store_true", help="skip the calibration-gradient leg")
+    ap.add_argument("--no-gradient", action="store_true", help="skip the calibration-gradient and calibration legs")
+    ap.add_argument("--main-only", action="store_true",
+                    help="only the timed passes: no mipmap, snow, fine-release, ensemble, gradient or CPU legs")
     ap.add_argument("--copy-probe", action="store_true",
                     help="copy 256 MiB once first: a plain copy of known size that calibrates HBM byte counters")
     return ap.parse_args()
@@ -496,6 +498,9 @@ def main() -> int:
                          "peak_GBs": HBM_PEAK_GBS},
         },
     }
+    if args.main_only:
+        print(json.dumps(out), flush=True)
+        return 0
     out["mipmap"] = mipmap_leg(avl, torch, res, 20)
     out["snow_cover"] = snow_leg(avl, torch, w, dem, 20)
     if args.workload == "alpine":
