@@ -380,7 +380,12 @@ void k_trajectories(TrajArgs a) {
                     ++st_steps;
                     uint32_t ux, uy;
                     if ((it & 1) == 0) {  // n is even
-                        const uint4 o = philox4x32_10(n >> 1, rep, cell_id, R.run, R.key0, R.key1);
+                        // the key is wave-uniform: pinning it to scalar registers here makes the round
+                        // keys scalar adds inside the block instead of 20 loop-invariant values hoisted
+                        // out of the loop, spilled to vector lanes and read back by VALU instructions
+                        uint32_t k0 = R.key0, k1 = R.key1;
+                        asm volatile("" : "+s"(k0), "+s"(k1));
+                        const uint4 o = philox4x32_10(n >> 1, rep, cell_id, R.run, k0, k1);
                         ux = o.x;
                         uy = o.y;
                         spare_x = o.z;
