@@ -29,6 +29,28 @@ __device__ __forceinline__ uint4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_
     return make_uint4(c0, c1, c2, c3);
 }
 
+// Correctly rounded square root for x >= 2^-96, +0 and +inf: the hardware estimate s (within 1 ulp) moved to
+// a neighbour when the residual x - s' s of that neighbour s' (exact through fma) shows the square root is
+// past the midpoint between them. This is the correction the compiler applies for sqrtf; its scaling of
+// tiny inputs and its special-value fix-up are identities in this range, so the bits are sqrtf's.
+__device__ __forceinline__ float sqrt_rn_big(float x) {
+    const float s = __builtin_amdgcn_sqrtf(x);
+    const float sm = __uint_as_float(__float_as_uint(s) - 1u);
+    const float sp = __uint_as_float(__float_as_uint(s) + 1u);
+    const float rm = __builtin_fmaf(-sm, s, x);
+    const float rp = __builtin_fmaf(-sp, s, x);
+    float r = rm <= 0.0f ? sm : s;
+    r = rp > 0.0f ? sp : r;
+    return r;
+}
+
+// sqrtf(x) for x >= 0 (or +inf): sqrt_rn_big, unless a lane of the wave holds 0 < x < 2^-96, when the whole
+// wave takes sqrtf (a wave-uniform branch, so the common case pays one compare)
+__device__ __forceinline__ float sqrt_rn(float x) {
+    if (__builtin_expect(__ballot(x > 0.0f && x < 0x1p-96f) != 0ull, 0)) return sqrtf(x);
+    return sqrt_rn_big(x);
+}
+
 // 24 random bits -> uniform in [-1, 1), exact in binary32
 __device__ __forceinline__ float signed_unit(uint32_t u) {
     return 2.0f * ((float)(u >> 8) * 5.9604644775390625e-8f) - 1.0f;

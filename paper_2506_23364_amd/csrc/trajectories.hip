@@ -396,12 +396,12 @@ void k_trajectories(TrajArgs a) {
                     }
                     const float rx = signed_unit(ux), ry = signed_unit(uy);
                     const float gg = gx * gx + gy * gy;
-                    const float t = gg > 0.0f ? R.Q / sqrtf(gg) : 0.0f;
+                    const float t = gg > 0.0f ? R.Q / sqrt_rn(gg) : 0.0f;
                     const float wx = (R.per * dx - t * gx) + R.rnd * rx;
                     const float wy = (R.per * dy - t * gy) + R.rnd * ry;
                     const float ww = wx * wx + wy * wy;
                     if (ww > 0.0f) {
-                        const float inv = 1.0f / sqrtf(ww);
+                        const float inv = 1.0f / sqrt_rn(ww);
                         dx = wx * inv;
                         dy = wy * inv;
                     }
@@ -414,7 +414,7 @@ void k_trajectories(TrajArgs a) {
                     } else {
                         const Sample s1 = bilinear_pad(dem_rs, Wp, row_bytes, x1, y1);
                         const float dz = z - s1.z;
-                        const float ds = sqrtf(R.dl2 + dz * dz);
+                        const float ds = sqrt_rn(R.dl2 + dz * dz);
                         const float num = v2 + a.g2 * (dz - R.mdl);
                         bool stop = !(num > 0.0f);
                         float v2n = 0.0f;

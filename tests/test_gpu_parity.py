@@ -187,6 +187,20 @@ def test_edge_cases(avl):
     assert not np.array_equal(g1[0], g2[0])
 
 
+@pytest.mark.parametrize("scale", [1e-16, 1e-22, 1e-35])
+def test_micro_relief(avl, scale):
+    """Relief of ~scale metres: squared gradients fall below 2^-96 (and to subnormals), where the kernel's
+    square root takes the compiler's full sequence for the wave instead of its short form."""
+    rng = np.random.default_rng(int(-np.log10(scale)))
+    dem = (rng.random((48, 40)) * scale).astype(np.float32)
+    assert (dem > 0).all()
+    mask = np.zeros(dem.shape, np.uint8)
+    mask[::3, ::4] = 1
+    params = dict(mu=0.0, xi=INF, randomness=0.2)
+    got, ref = both(avl, dem, mask, 10.0, params, 7, 60, 3, 0, f"relief {scale}")
+    assert ref.steps > 1000
+
+
 @pytest.mark.parametrize("P", [2, 5, 63, 64, 65, 127, 4099])
 def test_particles_per_cell_sweep(avl, P):
     """Slot decoding (release cell = slot / P, replica = slot mod P) for divisors around the 64-slot chunk
