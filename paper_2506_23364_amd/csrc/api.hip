@@ -482,6 +482,7 @@ int single_pass(const char* where, const float* dem, const uint8_t* mask, int32_
     a.pdiv = avl::make_divu32(particles_per_cell);
     a.dem_pad = ws.dem_pad;
     a.pad_bytes = (uint32_t)(avl::padded_cells(H, W) * sizeof(float));
+    a.runout_angle = params->tan_alpha >= 0.0f ? 1u : 0u;
 
     auto zero = [&]() -> hipError_t {
         hipError_t e;

@@ -115,6 +115,8 @@ struct TrajArgs {
     DivU32 pdiv;                                 // division by the particles per cell (same for every run)
     const float* __restrict__ dem_pad;           // the DEM tiles with a replicated border, (H + 2)(W + 2) each
     uint32_t pad_bytes;                          // bytes of one padded tile, (H + 2) (W + 2) x 4 < 2^32
+    uint32_t runout_angle;                       // single run: 1 if it uses the runout-angle stop (selects the
+                                                 // kernel instantiation; a batch always has the stop compiled in)
 };
 
 struct LaunchShape {

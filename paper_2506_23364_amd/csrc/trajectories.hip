@@ -73,7 +73,9 @@ struct Control {
     unsigned long long left;      // slots left in the partition after the window's last top-up
 };
 
-template <bool kBatch, int kBlock, int kFlush, int kTbl, int kProbes, int kWindow>
+// kAlpha: the runout-angle stop is compiled in (its release point and height then stay in registers);
+// a single run without it takes the instantiation without, three registers lighter.
+template <bool kBatch, bool kAlpha, int kBlock, int kFlush, int kTbl, int kProbes, int kWindow>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8)))
 void k_trajectories(TrajArgs a) {
     static_assert(kFlush % 2 == 0, "epochs keep the iteration parity");
@@ -349,9 +351,11 @@ void k_trajectories(TrajArgs a) {
                     gy = st.gy;
                     dx = st.dx;
                     dy = st.dy;
-                    x0 = x;
-                    y0 = y;
-                    zr = z;
+                    if (kAlpha) {
+                        x0 = x;
+                        y0 = y;
+                        zr = z;
+                    }
                     v2 = 0.0f;
                     cmax2 = 0.0f;
                     n = 0;
@@ -420,7 +424,7 @@ void k_trajectories(TrajArgs a) {
                         float v2n = 0.0f;
                         if (!stop) {
                             v2n = num / (1.0f + R.cd * ds);
-                            if (R.use_alpha) {
+                            if (kAlpha && R.use_alpha) {
                                 const float hx = x1 - x0, hy = y1 - y0;
                                 stop = (zr - s1.z) < R.tca * sqrtf(hx * hx + hy * hy);
                             }
@@ -637,20 +641,22 @@ struct Variant {
     const void* single;
     const void* batch;
     int block;
-    void (*launch_single)(dim3, dim3, hipStream_t, const TrajArgs&);
+    void (*launch_single)(dim3, dim3, hipStream_t, const TrajArgs&);        // runout-angle stop compiled in
+    void (*launch_single_plain)(dim3, dim3, hipStream_t, const TrajArgs&);  // without it
     void (*launch_batch)(dim3, dim3, hipStream_t, const TrajArgs&);
 };
 
-template <bool B, int Blk, int F, int T, int Q, int M>
+template <bool B, bool A, int Blk, int F, int T, int Q, int M>
 void launch_t(dim3 g, dim3 t, hipStream_t s, const TrajArgs& a) {
-    hipLaunchKernelGGL((k_trajectories<B, Blk, F, T, Q, M>), g, t, 0, s, a);
+    hipLaunchKernelGGL((k_trajectories<B, A, Blk, F, T, Q, M>), g, t, 0, s, a);
 }
 
 template <int Blk, int F, int T, int Q, int M>
 constexpr Variant make_variant() {
-    return Variant{reinterpret_cast<const void*>(&k_trajectories<false, Blk, F, T, Q, M>),
-                   reinterpret_cast<const void*>(&k_trajectories<true, Blk, F, T, Q, M>), Blk,
-                   &launch_t<false, Blk, F, T, Q, M>, &launch_t<true, Blk, F, T, Q, M>};
+    return Variant{reinterpret_cast<const void*>(&k_trajectories<false, true, Blk, F, T, Q, M>),
+                   reinterpret_cast<const void*>(&k_trajectories<true, true, Blk, F, T, Q, M>), Blk,
+                   &launch_t<false, true, Blk, F, T, Q, M>, &launch_t<false, false, Blk, F, T, Q, M>,
+                   &launch_t<true, true, Blk, F, T, Q, M>};
 }
 
 // candidates of the autotuner: (threads per block, iterations per epoch, table slots per block, probes,
@@ -685,8 +691,10 @@ hipError_t launch_trajectories(const TrajArgs& a, bool batched, const LaunchShap
     const Variant& v = kVariants[vi];
     if (batched)
         v.launch_batch(dim3(shape.grid), dim3(v.block), s, a);
-    else
+    else if (a.runout_angle)
         v.launch_single(dim3(shape.grid), dim3(v.block), s, a);
+    else
+        v.launch_single_plain(dim3(shape.grid), dim3(v.block), s, a);
     return hipGetLastError();
 }
 
