@@ -483,6 +483,7 @@ int single_pass(const char* where, const float* dem, const uint8_t* mask, int32_
     a.dem_pad = ws.dem_pad;
     a.pad_bytes = (uint32_t)(avl::padded_cells(H, W) * sizeof(float));
     a.runout_angle = params->tan_alpha >= 0.0f ? 1u : 0u;
+    a.wdiv = avl::make_divu32((uint32_t)W);
 
     auto zero = [&]() -> hipError_t {
         hipError_t e;
@@ -761,6 +762,7 @@ int avl_trajectories_batched(const float* dems, int32_t n_tiles, const uint8_t* 
     a.g2 = 9.81f + 9.81f;
     a.starts = nullptr;
     a.pdiv = avl::make_divu32(particles_per_cell);
+    a.wdiv = avl::make_divu32((uint32_t)W);
     a.dem_pad = ws.dem_pad;
     a.pad_bytes = (uint32_t)(np * sizeof(float));
     const int64_t raster = (int64_t)n_runs * n;

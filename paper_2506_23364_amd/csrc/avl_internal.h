@@ -117,6 +117,7 @@ struct TrajArgs {
     uint32_t pad_bytes;                          // bytes of one padded tile, (H + 2) (W + 2) x 4 < 2^32
     uint32_t runout_angle;                       // single run: 1 if it uses the runout-angle stop (selects the
                                                  // kernel instantiation; a batch always has the stop compiled in)
+    DivU32 wdiv;                                 // division by W (a batch's release cell -> row, column)
 };
 
 struct LaunchShape {

@@ -73,8 +73,9 @@ struct Control {
     unsigned long long left;      // slots left in the partition after the window's last top-up
 };
 
-// kAlpha: the runout-angle stop is compiled in (its release point and height then stay in registers);
-// a single run without it takes the instantiation without, three registers lighter.
+// kAlpha: the runout-angle stop is compiled in; a single run without it takes the instantiation without.
+// A single run with it keeps the release point and height in registers; a batch re-derives them from the
+// release cell when a run uses the stop, so its kernel carries no registers for them.
 template <bool kBatch, bool kAlpha, int kBlock, int kFlush, int kTbl, int kProbes, int kWindow>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8)))
 void k_trajectories(TrajArgs a) {
@@ -351,7 +352,7 @@ void k_trajectories(TrajArgs a) {
                     gy = st.gy;
                     dx = st.dx;
                     dy = st.dy;
-                    if (kAlpha) {
+                    if (kAlpha && !kBatch) {
                         x0 = x;
                         y0 = y;
                         zr = z;
@@ -425,8 +426,15 @@ void k_trajectories(TrajArgs a) {
                         if (!stop) {
                             v2n = num / (1.0f + R.cd * ds);
                             if (kAlpha && R.use_alpha) {
-                                const float hx = x1 - x0, hy = y1 - y0;
-                                stop = (zr - s1.z) < R.tca * sqrtf(hx * hx + hy * hy);
+                                float ax0 = x0, ay0 = y0, azr = zr;
+                                if (kBatch) {  // the release cell's centre and the height sampled there
+                                    const uint32_t rr = udiv(cell_id, a.wdiv), cc = cell_id - rr * (uint32_t)W;
+                                    ax0 = (float)cc + 0.5f;
+                                    ay0 = (float)rr + 0.5f;
+                                    azr = bilinear_pad(dem_rs, Wp, row_bytes, ax0, ay0).z;
+                                }
+                                const float hx = x1 - ax0, hy = y1 - ay0;
+                                stop = (azr - s1.z) < R.tca * sqrtf(hx * hx + hy * hy);
                             }
                         }
                         if (stop) {
