@@ -142,6 +142,49 @@ __device__ __forceinline__ void splat_q(unsigned long long* __restrict__ q, int 
     atomicAdd(q + (size_t)k.rb * W + k.cb, (unsigned long long)(long long)rintf((val * w11) * sc));
 }
 
+// Workgroup table of the forward's deposit: the particles of a block come from neighbouring release cells
+// and come to rest in overlapping cells, so their splats are summed in LDS (int64, order-independent like
+// the raster) and each touched cell reaches the raster with one atomic when the block ends. A corner
+// whose probe window is taken goes to the raster directly.
+constexpr int kDepLog2 = 12;
+constexpr int kDepSlots = 1 << kDepLog2;  // 4096 x (4-byte tag + 8-byte sum) = 48 KB
+constexpr int kDepProbes = 4;
+constexpr uint32_t kDepEmpty = 0xFFFFFFFFu;
+
+struct DepTable {
+    uint32_t tag[kDepSlots];
+    unsigned long long val[kDepSlots];
+};
+
+__device__ __forceinline__ void dep_add(DepTable& t, unsigned long long* __restrict__ q, uint32_t cell,
+                                        unsigned long long v) {
+    if (v == 0ull) return;
+    const uint32_t h = (cell * 2654435761u) >> (32 - kDepLog2);
+    for (int p = 0; p < kDepProbes; ++p) {
+        const uint32_t k = (h + (uint32_t)p) & (uint32_t)(kDepSlots - 1);
+        uint32_t cur = t.tag[k];
+        if (cur == kDepEmpty) cur = atomicCAS(&t.tag[k], kDepEmpty, cell);  // the old tag: empty if taken here
+        if (cur == kDepEmpty || cur == cell) {
+            atomicAdd(&t.val[k], v);
+            return;
+        }
+    }
+    atomicAdd(q + cell, v);
+}
+
+// splat_q through the block's table
+__device__ __forceinline__ void splat_q_table(DepTable& t, unsigned long long* __restrict__ q, int H, int W, float x,
+                                              float y, float val) {
+    const Corners k = corners(H, W, x, y);
+    const float w00 = (1.0f - k.fx) * (1.0f - k.fy), w01 = k.fx * (1.0f - k.fy);
+    const float w10 = (1.0f - k.fx) * k.fy, w11 = k.fx * k.fy;
+    const float sc = 16777216.0f;  // 2^24
+    dep_add(t, q, (uint32_t)(k.ra * W + k.ca), (unsigned long long)(long long)rintf((val * w00) * sc));
+    dep_add(t, q, (uint32_t)(k.ra * W + k.cb), (unsigned long long)(long long)rintf((val * w01) * sc));
+    dep_add(t, q, (uint32_t)(k.rb * W + k.ca), (unsigned long long)(long long)rintf((val * w10) * sc));
+    dep_add(t, q, (uint32_t)(k.rb * W + k.cb), (unsigned long long)(long long)rintf((val * w11) * sc));
+}
+
 __device__ __forceinline__ float mass_per_particle(const float* __restrict__ mass, uint32_t cell, uint32_t P) {
     return (mass ? mass[cell] : 1.0f) / (float)P;
 }
@@ -158,6 +201,12 @@ __global__ __launch_bounds__(kSmoothBlock) void k_smooth_forward(SmoothArgs a) {
     Dispenser disp;
     disp.init(wave_bcast64(a.run_off[1]), xcd_id());
     const size_t cplane = (size_t)a.C * a.cap;
+    __shared__ DepTable dep;
+    for (int k = threadIdx.x; k < kDepSlots; k += kSmoothBlock) {
+        dep.tag[k] = kDepEmpty;
+        dep.val[k] = 0ull;
+    }
+    __syncthreads();
 
     bool alive = false;
     State s{};
@@ -187,7 +236,7 @@ __global__ __launch_bounds__(kSmoothBlock) void k_smooth_forward(SmoothArgs a) {
         if (n >= a.S) {
             ++st_limit;
             a.end_rec[slot_id] = (n << 2) | kEndLimit;
-            splat_q(a.dep_q, H, W, s.x, s.y, mp);
+            splat_q_table(dep, a.dep_q, H, W, s.x, s.y, mp);
             alive = false;
             continue;
         }
@@ -215,13 +264,17 @@ __global__ __launch_bounds__(kSmoothBlock) void k_smooth_forward(SmoothArgs a) {
             ++st_stop;
             a.end_rec[slot_id] = (n << 2) | kEndStop;
             const float t = v2p > 0.0f ? v2p / (v2p - o.num) : 0.0f;
-            splat_q(a.dep_q, H, W, xp + t * (o.x1 - xp), yp + t * (o.y1 - yp), mp);
+            splat_q_table(dep, a.dep_q, H, W, xp + t * (o.x1 - xp), yp + t * (o.y1 - yp), mp);
         } else {
             ++st_stop;
             a.end_rec[slot_id] = (n << 2) | kEndAngle;
-            splat_q(a.dep_q, H, W, xp, yp, mp);
+            splat_q_table(dep, a.dep_q, H, W, xp, yp, mp);
         }
     }
+    // every wave of the block is done: the table's sums go to the raster
+    __syncthreads();
+    for (int k = threadIdx.x; k < kDepSlots; k += kSmoothBlock)
+        if (dep.tag[k] != kDepEmpty && dep.val[k] != 0ull) atomicAdd(a.dep_q + dep.tag[k], dep.val[k]);
     const uint64_t s0 = wave_sum64(st_steps), s1 = wave_sum64(st_exit), s2 = wave_sum64(st_stop);
     const uint64_t s3 = wave_sum64(st_limit);
     if (lane == 0) {
