@@ -113,3 +113,12 @@ def test_runout_angle_sweep(avl):
     assert all(visited[i + 1] <= visited[i] for i in range(len(angles) - 1)), visited
     assert all(steps[i + 1] <= steps[i] for i in range(len(angles) - 1)), steps
     assert visited[-1] < visited[0]
+
+
+def test_calibration_capacity_overflow_is_an_error(avl, scene):
+    c, base = scene
+    start = avl.Params.make(**dict(base, mu=0.3, xi=1000.0))
+    n = int(c.mask.sum())
+    with pytest.raises(avl.AvlError):
+        avl.calibrate(dev(c.dem), dev(c.mask), c.cell_size, start, 2, 100, c.seed,
+                      torch.zeros(c.dem.shape, dtype=torch.float32, device="cuda"), 2, max_release_cells=n - 1)

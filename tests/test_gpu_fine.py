@@ -102,3 +102,18 @@ def test_fine_user_texture_and_empty(avl):
     run_both(avl, dem, mask.astype(np.uint8), mult, cs, dict(mu=0.25, xi=1800.0), 2, 500, seed=5)
     counts, vmax, stats = run_both(avl, dem, np.zeros((hf, wf), np.uint8), mult, cs, dict(), 4, 100, seed=1)
     assert counts.sum() == 0 and vmax.max() == 0 and stats.sum() == 0
+
+
+def test_fine_largest_multiplier(avl):
+    # 16 x 16 texels per DEM cell (the maximum) on a small ragged tile, a sparse texture
+    dem = terrain(24, w=19, seed=12, relief=400.0)[:21].copy()
+    mult, cs = 16, 10.0
+    nrm = oracle.normals(dem, cs)
+    ref_map = oracle.release_mask_fine(nrm, dem, mult, 20.0, 60.0, float(np.quantile(dem, 0.3)), 1e9)
+    got_map = host(avl.release_mask_fine(avl.normals(dev(dem), cs), dev(dem), mult, 20.0, 60.0,
+                                         float(np.quantile(dem, 0.3)), 1e9))
+    assert np.array_equal(got_map, ref_map)
+    sparse = np.zeros_like(ref_map)
+    sparse[::4, ::3] = ref_map[::4, ::3]
+    assert sparse.sum() > 100
+    run_both(avl, dem, sparse, mult, cs, dict(mu=0.2, xi=2000.0), 3, 400, seed=9)
