@@ -91,6 +91,17 @@ def test_smooth_cases(avl, name, params, P, S):
     run_both(avl, dem, mask, mass, gD, dict(synth.DEFAULT_PARAMS, **params), P, S, 11, 2, label=name)
 
 
+def test_smooth_deposit_table_overflow(avl):
+    """Scattered single-particle releases: a block's ~2000 particles end in more distinct cells (4 corners
+    each) than its 4096-slot deposit table holds, so part of the splats take the direct raster atomics."""
+    dem = synth.alpine_dem(512, 900.0, seed=19)
+    mask = (np.random.default_rng(19).random(dem.shape) < 0.08).astype(np.uint8)
+    mass = np.random.default_rng(20).uniform(0.5, 1.5, dem.shape).astype(np.float32)
+    gD = np.random.default_rng(21).standard_normal(dem.shape).astype(np.float32)
+    run_both(avl, dem, mask, mass, gD, dict(mu=0.2, xi=1500.0, randomness=0.3), 1, 400, 4, vel=False,
+             label="scattered")
+
+
 def test_smooth_unit_mass_empty_and_capacity(avl):
     dem, mask, mass, gD = case(seed=9, size=64)
     p = dict(synth.DEFAULT_PARAMS, mu=0.2)
