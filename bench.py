@@ -371,7 +371,7 @@ def gradient_leg(avl, torch, reps: int) -> dict:
 def main() -> int:
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+        print(json.dumps({"error": "this benchmark runs on one GPU; --gpus must be 1",
                           "detail": "particles are independent; a multi-GPU run would split particle ranges and "
                                     "all-reduce the integer rasters (see the design notes)"}))
         return 2
