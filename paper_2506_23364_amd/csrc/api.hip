@@ -81,9 +81,12 @@ struct SmoothWs {
     float* pp;
     double* part;
     float2* scratch;
+    float* dem_pad;
 };
 
-static size_t smooth_layout(int64_t n, int64_t cap_cells, uint32_t P, uint32_t S, char* base, SmoothWs* out) {
+static size_t smooth_layout(int64_t H, int64_t W, int64_t cap_cells, uint32_t P, uint32_t S, char* base,
+                            SmoothWs* out) {
+    const int64_t n = H * W;
     const unsigned long long cap = (unsigned long long)cap_cells * P;
     const size_t C = smooth_checkpoints(S);
     size_t off = 0;
@@ -100,6 +103,7 @@ static size_t smooth_layout(int64_t n, int64_t cap_cells, uint32_t P, uint32_t S
     const size_t o_pp = take(4 * (size_t)cap * sizeof(float));
     const size_t o_part = take(3 * smooth_reduce_blocks(cap) * sizeof(double));
     const size_t o_scr = take(smooth_scratch_bytes());
+    const size_t o_pad = take((size_t)padded_cells(H, W) * sizeof(float));
     if (base && out) {
         char* p = base + o_ctrl;
         out->w = Workspace{};
@@ -115,6 +119,7 @@ static size_t smooth_layout(int64_t n, int64_t cap_cells, uint32_t P, uint32_t S
         out->pp = reinterpret_cast<float*>(base + o_pp);
         out->part = reinterpret_cast<double*>(base + o_part);
         out->scratch = reinterpret_cast<float2*>(base + o_scr);
+        out->dem_pad = reinterpret_cast<float*>(base + o_pad);
     }
     return off;
 }
@@ -592,7 +597,7 @@ int avl_trajectories_fine(const float* dem, const uint8_t* mask, int32_t H, int3
 size_t avl_smooth_workspace_bytes(int32_t H, int32_t W, int32_t max_release_cells, uint32_t particles_per_cell,
                                   uint32_t step_limit) {
     if (H < 1 || W < 1 || max_release_cells < 0 || particles_per_cell == 0) return 0;
-    return avl::smooth_layout((int64_t)H * W, max_release_cells, particles_per_cell, step_limit, nullptr, nullptr);
+    return avl::smooth_layout(H, W, max_release_cells, particles_per_cell, step_limit, nullptr, nullptr);
 }
 
 namespace {
@@ -602,7 +607,8 @@ int smooth_checks(const char* where, const float* dem, const uint8_t* mask, int3
                   const avl_params* params, uint32_t P, uint32_t S, int32_t max_release_cells, void* workspace,
                   size_t workspace_bytes) {
     if (!dem || !mask || !workspace) return fail(AVL_EINVAL, "%s: null pointer", where);
-    if (!grid_ok(H, W, 1)) return fail(AVL_EINVAL, "%s: need H, W >= 1 and H*W < 2^31", where);
+    if (!grid_ok(H, W, 1) || avl::padded_cells(H, W) >= (int64_t(1) << 30))
+        return fail(AVL_EINVAL, "%s: need H, W >= 1 and (H + 2)(W + 2) < 2^30", where);
     if (!finite(cell_size) || !(cell_size > 0.0f)) return fail(AVL_EINVAL, "%s: cell_size must be > 0", where);
     if (P == 0) return fail(AVL_EINVAL, "%s: particles_per_cell must be >= 1", where);
     if (max_release_cells < 0 || (int64_t)max_release_cells > (int64_t)H * W)
@@ -641,6 +647,8 @@ avl::SmoothArgs smooth_args(const float* dem, const float* mass, int32_t H, int3
     a.g2dl = a.g2 * dl;
     a.xi = params->xi;
     a.h = params->flow_height;
+    a.dem_pad = sw.dem_pad;
+    a.pad_bytes = (uint32_t)(avl::padded_cells(H, W) * sizeof(float));
     return a;
 }
 
@@ -662,7 +670,7 @@ int avl_trajectories_smooth(const float* dem, const uint8_t* mask, const float* 
     const int64_t n = (int64_t)H * W;
     hipStream_t s = static_cast<hipStream_t>(stream);
     avl::SmoothWs sw;
-    avl::smooth_layout(n, max_release_cells, particles_per_cell, step_limit, static_cast<char*>(workspace), &sw);
+    avl::smooth_layout(H, W, max_release_cells, particles_per_cell, step_limit, static_cast<char*>(workspace), &sw);
     avl::SmoothArgs a = smooth_args(dem, mass, H, W, cell_size, params, particles_per_cell, step_limit,
                                     max_release_cells, sw);
     a.dep_q = reinterpret_cast<unsigned long long*>(deposit_q);
@@ -681,6 +689,8 @@ int avl_trajectories_smooth(const float* dem, const uint8_t* mask, const float* 
         (e = avl::launch_fill_u64(sw.w.queues, 0ull, avl::kXcds, s)) != hipSuccess ||
         (e = avl::launch_fill_u64(a.stats, 0ull, 4, s)) != hipSuccess)
         return hip_fail(e, "avl_trajectories_smooth: zero");
+    if ((e = avl::launch_pad_dem(dem, H, W, sw.dem_pad, s)) != hipSuccess)
+        return hip_fail(e, "avl_trajectories_smooth: padded DEM");
     if ((e = avl::launch_smooth_forward(a, s)) != hipSuccess) return hip_fail(e, "avl_trajectories_smooth: launch");
     if (deposit && (e = avl::launch_q_to_float(a.dep_q, n, deposit, s)) != hipSuccess)
         return hip_fail(e, "avl_trajectories_smooth: deposit");
@@ -704,7 +714,7 @@ int avl_trajectories_backward(const float* dem, const uint8_t* mask, const float
     const int64_t n = (int64_t)H * W;
     hipStream_t s = static_cast<hipStream_t>(stream);
     avl::SmoothWs sw;
-    avl::smooth_layout(n, max_release_cells, particles_per_cell, step_limit, static_cast<char*>(workspace), &sw);
+    avl::smooth_layout(H, W, max_release_cells, particles_per_cell, step_limit, static_cast<char*>(workspace), &sw);
     avl::SmoothArgs a = smooth_args(dem, mass, H, W, cell_size, params, particles_per_cell, step_limit,
                                     max_release_cells, sw);
     a.gD = grad_deposit;

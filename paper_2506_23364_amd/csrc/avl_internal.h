@@ -187,6 +187,8 @@ struct SmoothArgs {
     uint32_t S, C;                          // step limit, checkpoints per particle
     unsigned long long cap;                 // particle capacity of ck / end_rec / pp
     float g2, g2dl, xi, h;                  // 2g, 2g * dl (dl = step_cells * cell_size), xi, h
+    const float* dem_pad;                   // the DEM with a replicated border, (H + 2) x (W + 2)
+    uint32_t pad_bytes;                     // its bytes, < 2^32
 };
 
 

@@ -44,13 +44,32 @@ struct StepOut {
     float a;            // drag term a = 2g ds / (xi h) of an accepted step
 };
 
+// The DEM with its replicated border, read through a buffer resource (no clamps, 32-bit offsets, both
+// rows of the patch in flight), as in the plain pass; the same values as the clamped patch.
+struct PadDem {
+    __amdgpu_buffer_rsrc_t rs;
+    uint32_t Wp, row_bytes;
+};
+
+__device__ __forceinline__ PadDem pad_dem(const SmoothArgs& a) {
+    PadDem d;
+    d.rs = buffer_rsrc(a.dem_pad, a.pad_bytes);
+    d.Wp = (uint32_t)a.W + 2u;
+    d.row_bytes = 4u * d.Wp;
+    return d;
+}
+
+__device__ __forceinline__ Sample sample(const PadDem& d, float x, float y) {
+    return bilinear_pad(d.rs, d.Wp, d.row_bytes, x, y);
+}
+
 // Release state of particle (cell_id, ...) at the texel centre, heading downslope.
-__device__ __forceinline__ void release(State& s, const float* __restrict__ dem, int H, int W, uint32_t cell_id) {
+__device__ __forceinline__ void release(State& s, const PadDem& dem, int W, uint32_t cell_id) {
     const int r = (int)(cell_id / (uint32_t)W);
     const int c = (int)(cell_id - (uint32_t)r * (uint32_t)W);
     s.x = (float)c + 0.5f;
     s.y = (float)r + 0.5f;
-    const Sample s0 = bilinear(dem, H, W, s.x, s.y);
+    const Sample s0 = sample(dem, s.x, s.y);
     s.z = s0.z;
     s.gx = s0.gx;
     s.gy = s0.gy;
@@ -71,7 +90,7 @@ __device__ __forceinline__ void release(State& s, const float* __restrict__ dem,
 
 // Step n of the model (the same binary32 operations as the plain pass). Updates s when accepted.
 __device__ __forceinline__ StepOut step(State& s, uint32_t n, uint32_t rep, uint32_t cell_id, const RunConst& rc,
-                                        const float* __restrict__ dem, int H, int W, float g2) {
+                                        const PadDem& dem, int H, int W, float g2) {
     StepOut o;
     uint32_t ux, uy;
     if ((n & 1u) == 0u) {
@@ -104,7 +123,7 @@ __device__ __forceinline__ StepOut step(State& s, uint32_t n, uint32_t rep, uint
         o.outcome = kExit;
         return o;
     }
-    const Sample s1 = bilinear(dem, H, W, o.x1, o.y1);
+    const Sample s1 = sample(dem, o.x1, o.y1);
     const float dz = s.z - s1.z;
     const float ds = sqrtf(rc.dl2 + dz * dz);
     o.num = s.v2 + g2 * (dz - rc.mdl);
@@ -198,6 +217,7 @@ __global__ __launch_bounds__(kSmoothBlock) void k_smooth_forward(SmoothArgs a) {
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
     const RunConst rc = uniform_run(a.runs[0]);
     const int H = a.H, W = a.W;
+    const PadDem dd = pad_dem(a);
     Dispenser disp;
     disp.init(wave_bcast64(a.run_off[1]), xcd_id());
     const size_t cplane = (size_t)a.C * a.cap;
@@ -227,7 +247,7 @@ __global__ __launch_bounds__(kSmoothBlock) void k_smooth_forward(SmoothArgs a) {
                 cell_id = (uint32_t)a.cells[i];
                 slot_id = slot;
                 mp = mass_per_particle(a.mass, cell_id, rc.P);
-                release(s, a.dem, H, W, cell_id);
+                release(s, dd, W, cell_id);
                 n = 0;
                 alive = true;
             }
@@ -250,7 +270,7 @@ __global__ __launch_bounds__(kSmoothBlock) void k_smooth_forward(SmoothArgs a) {
         }
         ++st_steps;
         const float xp = s.x, yp = s.y, v2p = s.v2;
-        const StepOut o = step(s, n, rep, cell_id, rc, a.dem, H, W, a.g2);
+        const StepOut o = step(s, n, rep, cell_id, rc, dd, H, W, a.g2);
         if (o.outcome == kAccept) {
             ++n;
             if (a.vel_q) splat_q(a.vel_q, H, W, s.x, s.y, mp * sqrtf(s.v2));
@@ -291,6 +311,7 @@ __global__ __launch_bounds__(kSmoothBlock) void k_smooth_backward(SmoothArgs a) 
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
     const RunConst rc = uniform_run(a.runs[0]);
     const int H = a.H, W = a.W;
+    const PadDem dd = pad_dem(a);
     const size_t T = (size_t)gridDim.x * blockDim.x;
     const size_t gtid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     const size_t cplane = (size_t)a.C * a.cap;
@@ -318,7 +339,7 @@ __global__ __launch_bounds__(kSmoothBlock) void k_smooth_backward(SmoothArgs a) 
             uint32_t n0 = 0;
             auto load = [&](int32_t c) {
                 if (c < 0) {
-                    release(s, a.dem, H, W, cell_id);
+                    release(s, dd, W, cell_id);
                     return;
                 }
                 const size_t at = (size_t)c * a.cap + slot;
@@ -327,7 +348,7 @@ __global__ __launch_bounds__(kSmoothBlock) void k_smooth_backward(SmoothArgs a) 
                 s.dx = a.ck[2 * cplane + at];
                 s.dy = a.ck[3 * cplane + at];
                 s.v2 = a.ck[4 * cplane + at];
-                const Sample sm = bilinear(a.dem, H, W, s.x, s.y);
+                const Sample sm = sample(dd, s.x, s.y);
                 s.z = sm.z;
                 s.gx = sm.gx;
                 s.gy = sm.gy;
@@ -336,12 +357,12 @@ __global__ __launch_bounds__(kSmoothBlock) void k_smooth_backward(SmoothArgs a) 
                 const int cc = (int)(cell_id - (uint32_t)r * (uint32_t)W);
                 s.x0 = (float)cc + 0.5f;
                 s.y0 = (float)r + 0.5f;
-                s.zr = bilinear(a.dem, H, W, s.x0, s.y0).z;
+                s.zr = sample(dd, s.x0, s.y0).z;
             };
             load(c_last);
             n0 = c_last < 0 ? 0u : (uint32_t)c_last * kCkpt;
             for (uint32_t k = n0; k < n_end; ++k) {
-                const StepOut o = step(s, k, rep, cell_id, rc, a.dem, H, W, a.g2);
+                const StepOut o = step(s, k, rep, cell_id, rc, dd, H, W, a.g2);
                 a.scratch[(size_t)(k - n0) * T + gtid] = make_float2(o.a, s.v2);
             }
             float px = s.x, py = s.y;
@@ -349,7 +370,7 @@ __global__ __launch_bounds__(kSmoothBlock) void k_smooth_backward(SmoothArgs a) 
             bool stop = false;
             if (reason == kEndStop) {
                 const float xp = s.x, yp = s.y, v2p = s.v2;
-                const StepOut o = step(s, n_end, rep, cell_id, rc, a.dem, H, W, a.g2);
+                const StepOut o = step(s, n_end, rep, cell_id, rc, dd, H, W, a.g2);
                 const float t = v2p > 0.0f ? v2p / (v2p - o.num) : 0.0f;
                 px = xp + t * (o.x1 - xp);
                 py = yp + t * (o.y1 - yp);
@@ -386,7 +407,7 @@ __global__ __launch_bounds__(kSmoothBlock) void k_smooth_backward(SmoothArgs a) 
                     if (c != c_last) {
                         load(c);
                         for (uint32_t k = c0; k < c1; ++k) {
-                            const StepOut o = step(s, k, rep, cell_id, rc, a.dem, H, W, a.g2);
+                            const StepOut o = step(s, k, rep, cell_id, rc, dd, H, W, a.g2);
                             a.scratch[(size_t)(k - c0) * T + gtid] = make_float2(o.a, s.v2);
                         }
                     }
