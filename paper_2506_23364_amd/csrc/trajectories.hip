@@ -388,7 +388,8 @@ void k_trajectories(TrajArgs a) {
                         // the key is wave-uniform: pinning it to scalar registers here makes the round
                         // keys scalar adds inside the block instead of 20 loop-invariant values hoisted
                         // out of the loop, spilled to vector lanes and read back by VALU instructions
-                        uint32_t k0 = R.key0, k1 = R.key1;
+                        uint32_t k0 = __builtin_amdgcn_readfirstlane(R.key0);
+                        uint32_t k1 = __builtin_amdgcn_readfirstlane(R.key1);
                         asm volatile("" : "+s"(k0), "+s"(k1));
                         const uint4 o = philox4x32_10(n >> 1, rep, cell_id, R.run, k0, k1);
                         ux = o.x;
