@@ -117,3 +117,36 @@ def test_fine_largest_multiplier(avl):
     sparse[::4, ::3] = ref_map[::4, ::3]
     assert sparse.sum() > 100
     run_both(avl, dem, sparse, mult, cs, dict(mu=0.2, xi=2000.0), 3, 400, seed=9)
+
+
+def test_fine_alpine_full_size_sampled(avl):
+    """The benchmark's fine-release leg: the 2048^2 alpine tile at 2 x 2 release texels per cell and 64
+    particles per texel. The oracle runs every 389th release texel; the GPU runs that sample, its
+    complement and the whole texture, whose rasters must be the sum (counts, statistics) and the maximum
+    (speeds) of the two parts."""
+    w = synth.make_workload("alpine")
+    mult, P = 2, 64
+    nrm = oracle.normals(w.dem, w.cell_size)
+    fine = oracle.release_mask_fine(nrm, w.dem, mult, w.slope_min_deg, w.slope_max_deg, w.z_min, w.z_max)
+    del nrm
+    got_map = host(avl.release_mask_fine(avl.normals(dev(w.dem), w.cell_size), dev(w.dem), mult, w.slope_min_deg,
+                                         w.slope_max_deg, w.z_min, w.z_max))
+    assert np.array_equal(got_map, fine)
+    texels = np.flatnonzero(fine)
+    assert 2e5 < len(texels) < 8e5
+    sample = np.zeros(fine.size, np.uint8)
+    sample[texels[::389]] = 1
+    sample = sample.reshape(fine.shape)
+    rest = (fine & (1 - sample)).astype(np.uint8)
+    got_s = run_both(avl, w.dem, sample, mult, w.cell_size, w.params, P, w.step_limit, w.seed)
+    p = avl.Params.make(**w.params)
+
+    def gpu(m):
+        r = avl.trajectories_fine(dev(w.dem), dev(m), mult, w.cell_size, p, P, w.step_limit, w.seed)
+        return host(r.counts), host(r.vmax), host(r.stats)
+
+    got_r = gpu(rest)
+    got_f = gpu(fine)
+    assert np.array_equal(got_f[0], got_s[0] + got_r[0])
+    assert np.array_equal(got_f[1], np.maximum(got_s[1], got_r[1]))
+    assert np.array_equal(got_f[2], got_s[2] + got_r[2])
