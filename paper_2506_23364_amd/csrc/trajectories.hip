@@ -55,10 +55,13 @@ __device__ __forceinline__ void global_max(uint32_t* __restrict__ p, uint32_t bi
 using namespace dev;
 
 // Workgroup-shared accumulation table: kTbl slots of (cell key, entry count, max v^2 bits) in LDS,
-// open addressing with a few linear probes. Cleared at every epoch boundary after its flush.
+// open addressing with a few linear probes. Slots are emptied only at epoch boundaries: each boundary
+// flushes a slot to the rasters and empties it, except (with retention on) a slot whose cell was entered
+// often enough in the epoch that ended, which keeps its key, count and maximum into the next epoch.
+// With retention the count word holds two 16-bit halves: the entries so far (low) and their number at
+// the last boundary (high).
 template <int kTbl>
 struct Table {
-    static_assert((kTbl & (kTbl - 1)) == 0, "table size must be a power of two");
     uint32_t tag[kTbl], cnt[kTbl], vmx[kTbl];
 };
 
@@ -76,10 +79,16 @@ struct Control {
 // kAlpha: the runout-angle stop is compiled in; a single run without it takes the instantiation without.
 // A single run with it keeps the release point and height in registers; a batch re-derives them from the
 // release cell when a run uses the stop, so its kernel carries no registers for them.
-template <bool kBatch, bool kAlpha, int kBlock, int kFlush, int kTbl, int kProbes, int kWindow>
+// kKeep: table retention, 0 off; else a slot whose cell was entered at least kKeep times in the epoch
+// that ended stays in the table (its count and maximum reach the rasters at a later boundary).
+template <bool kBatch, bool kAlpha, int kBlock, int kFlush, int kTbl, int kProbes, int kWindow, int kKeep>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8)))
 void k_trajectories(TrajArgs a) {
     static_assert(kFlush % 2 == 0, "epochs keep the iteration parity");
+    // a lane enters a given cell at most once per iteration, so a slot gains at most kBlock * kFlush
+    // entries per epoch; a retained count stays below kKeepCap, so the low half never carries
+    static_assert(kKeep == 0 || kBlock * kFlush <= 32768, "retention needs 16-bit counts per epoch");
+    constexpr uint32_t kKeepCap = 65536u - (uint32_t)(kBlock * kFlush);
     constexpr uint32_t kSuper = (uint32_t)kWindow * kBlock;  // slots per window top-up
     static_assert(kTbl % kBlock == 0, "every thread flushes the same number of table slots");
     constexpr int kPer = kTbl / kBlock;
@@ -126,13 +135,15 @@ void k_trajectories(TrajArgs a) {
     };
 
     // table slot of `key`, claimed if a probe finds an empty slot first; -1 if every probe is held by
-    // another cell. Slots are only filled within an epoch, so a key's first probe that is empty or
-    // holds it is the same for every lane.
+    // another cell. Within an epoch slots are only filled, never emptied, so a key's first probe that is
+    // empty or holds it is the same for every lane. (A retained key can find an earlier probe emptied at
+    // the boundary and take that one as well: two slots of one cell, both flushed, the sums unchanged.)
     auto claim = [&](uint32_t key) -> int {
-        const uint32_t h = (key * 0x9E3779B1u) >> (32 - __builtin_ctz(kTbl));
+        const uint32_t h = (uint32_t)(((uint64_t)(key * 0x9E3779B1u) * (uint64_t)kTbl) >> 32);
 #pragma unroll
         for (int q = 0; q < kProbes; ++q) {
-            const uint32_t sl = (h + (uint32_t)q) & (uint32_t)(kTbl - 1);
+            uint32_t sl = h + (uint32_t)q;
+            if (sl >= (uint32_t)kTbl) sl -= (uint32_t)kTbl;
             uint32_t t = lds_ld(tb.tag + sl);
             if (t == kEmpty) {
                 const uint32_t old = atomicCAS(tb.tag + sl, kEmpty, key);
@@ -493,22 +504,34 @@ void k_trajectories(TrajArgs a) {
             refill_window(false);
         }
         // flush this thread's kPer slots: all raster reads of the max check are issued before any is
-        // used, so the flush costs one memory round trip rather than one per slot
+        // used, so the flush costs one memory round trip rather than one per slot. The last boundary
+        // (no wave has work left) flushes every slot.
+        const bool last = ctl.busy[epoch & 1u] == 0u;
         uint32_t ft[kPer], fc[kPer], fv[kPer], fg[kPer];
+        bool keep[kPer];
 #pragma unroll
         for (int j = 0; j < kPer; ++j) {
             const int k = threadIdx.x + j * kBlock;
             ft[j] = tb.tag[k];
             fc[j] = tb.cnt[k];
             fv[j] = tb.vmx[k];
+            if constexpr (kKeep > 0) {
+                const uint32_t c = fc[j] & 0xFFFFu, seen = fc[j] >> 16;
+                keep[j] = !last && ft[j] != kEmpty && c - seen >= (uint32_t)kKeep && c < kKeepCap;
+                fc[j] = c;
+            } else {
+                keep[j] = false;
+            }
         }
 #pragma unroll
-        for (int j = 0; j < kPer; ++j)  // unconditional (an empty slot reads cell 0): no branch between the loads
-            fg[j] = __builtin_nontemporal_load(vmax2 + (ft[j] != kEmpty ? ft[j] : 0u));
+        for (int j = 0; j < kPer; ++j)  // an empty slot reads cell 0: no branch between the loads
+            fg[j] = keep[j] ? 0u : __builtin_nontemporal_load(vmax2 + (ft[j] != kEmpty ? ft[j] : 0u));
 #pragma unroll
         for (int j = 0; j < kPer; ++j) {
             const int k = threadIdx.x + j * kBlock;
-            if (ft[j] != kEmpty) {
+            if (keep[j]) {
+                tb.cnt[k] = fc[j] | (fc[j] << 16);
+            } else if (ft[j] != kEmpty) {
                 if (fc[j]) atomicAdd(counts + ft[j], fc[j]);
                 tb.tag[k] = kEmpty;
                 tb.cnt[k] = 0u;
@@ -516,8 +539,8 @@ void k_trajectories(TrajArgs a) {
             }
         }
 #pragma unroll
-        for (int j = 0; j < kPer; ++j)
-            if (ft[j] != kEmpty && fg[j] < fv[j]) atomicMax(vmax2 + ft[j], fv[j]);  // a stale read >= v suffices
+        for (int j = 0; j < kPer; ++j)  // a stale read >= v suffices
+            if (!keep[j] && ft[j] != kEmpty && fg[j] < fv[j]) atomicMax(vmax2 + ft[j], fv[j]);
         my_slot = -1;
         __syncthreads();
         if (ctl.busy[epoch & 1u] == 0u) break;
@@ -655,24 +678,26 @@ struct Variant {
     void (*launch_batch)(dim3, dim3, hipStream_t, const TrajArgs&);
 };
 
-template <bool B, bool A, int Blk, int F, int T, int Q, int M>
+template <bool B, bool A, int Blk, int F, int T, int Q, int M, int K>
 void launch_t(dim3 g, dim3 t, hipStream_t s, const TrajArgs& a) {
-    hipLaunchKernelGGL((k_trajectories<B, A, Blk, F, T, Q, M>), g, t, 0, s, a);
+    hipLaunchKernelGGL((k_trajectories<B, A, Blk, F, T, Q, M, K>), g, t, 0, s, a);
 }
 
-template <int Blk, int F, int T, int Q, int M>
+template <int Blk, int F, int T, int Q, int M, int K>
 constexpr Variant make_variant() {
-    return Variant{reinterpret_cast<const void*>(&k_trajectories<false, true, Blk, F, T, Q, M>),
-                   reinterpret_cast<const void*>(&k_trajectories<true, true, Blk, F, T, Q, M>), Blk,
-                   &launch_t<false, true, Blk, F, T, Q, M>, &launch_t<false, false, Blk, F, T, Q, M>,
-                   &launch_t<true, true, Blk, F, T, Q, M>};
+    return Variant{reinterpret_cast<const void*>(&k_trajectories<false, true, Blk, F, T, Q, M, K>),
+                   reinterpret_cast<const void*>(&k_trajectories<true, true, Blk, F, T, Q, M, K>), Blk,
+                   &launch_t<false, true, Blk, F, T, Q, M, K>, &launch_t<false, false, Blk, F, T, Q, M, K>,
+                   &launch_t<true, true, Blk, F, T, Q, M, K>};
 }
 
 // candidates of the autotuner: (threads per block, iterations per epoch, table slots per block, probes,
-// window top-up in blocks of slots)
+// window top-up in blocks of slots, retention threshold). Two blocks share a CU: 6144 slots of 12 bytes
+// are 72 KiB of LDS per block.
 const Variant kVariants[] = {
-    make_variant<1024, 32, 4096, 4, 4>(), make_variant<1024, 64, 4096, 8, 4>(), make_variant<1024, 32, 4096, 4, 2>(),
-    make_variant<1024, 16, 4096, 4, 4>(), make_variant<512, 32, 2048, 4, 4>(),
+    make_variant<1024, 32, 6144, 4, 4, 1>(), make_variant<1024, 32, 6144, 4, 4, 2>(),
+    make_variant<1024, 16, 6144, 4, 4, 2>(), make_variant<1024, 32, 6144, 6, 4, 2>(),
+    make_variant<1024, 32, 4096, 4, 4, 0>(), make_variant<512, 32, 3072, 4, 4, 2>(),
 };
 
 }  // namespace

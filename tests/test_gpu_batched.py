@@ -120,6 +120,48 @@ def test_every_variant_gives_identical_rasters(avl):
     assert np.array_equal(ref_p[0], ref.counts)
 
 
+def cone_scene():
+    """16 x 16 cone (8 m of height per cell of radius, ~39 degrees) with a pit of four cells at its
+    centre; the 32 cells within 3 cells of the axis release."""
+    yy, xx = np.mgrid[0:16, 0:16].astype(np.float64)
+    r = np.sqrt((xx - 7.5) ** 2 + (yy - 7.5) ** 2)
+    return (r * 8.0).astype(np.float32), (r < 3.0).astype(np.uint8)
+
+
+def test_table_retention_every_variant(avl):
+    """The accumulation table may keep a busy cell's slot from one epoch to the next, its count held in 16
+    bits until it reaches the rasters. On a cone every path ends in the pit: at 2,000 particles per cell
+    every variant equals the oracle; at 1,000,000 per cell (32 M particles, a full grid) the blocks enter a
+    pit cell more often than a retained count may reach, and every variant must equal the one without
+    retention."""
+    dem, mask = cone_scene()
+    d, m = torch.from_numpy(dem).cuda(), torch.from_numpy(mask).cuda()
+    p = dict(synth.DEFAULT_PARAMS)
+    ref = oracle.trajectories(dem, mask, 10.0, oracle.make_params(**p), 2000, 200, 5)
+    try:
+        for v in range(avl.tuning_variants()):
+            avl.set_tuning(v, True)
+            r = avl.trajectories(d, m, 10.0, avl.Params.make(**p), 2000, 200, 5)
+            assert np.array_equal(host(r.counts), ref.counts), f"variant {v}"
+            np.testing.assert_allclose(host(r.vmax), ref.vmax, rtol=1e-5, atol=0, err_msg=f"variant {v}")
+            assert list(host(r.stats)) == [ref.steps, ref.n_exit, ref.n_stop, ref.n_limit], f"variant {v}"
+        outs = []
+        for v in range(avl.tuning_variants()):
+            avl.set_tuning(v, True)
+            r = avl.trajectories(d, m, 10.0, avl.Params.make(**p), 1_000_000, 200, 5)
+            outs.append([host(r.counts), host(r.vmax), host(r.stats)])
+        counts = outs[0][0]
+        # 512 blocks: some block enters the pit cell more often than a retained count may reach (2^15)
+        assert int(counts.max()) > 512 * 32768, int(counts.max())
+        assert int(outs[0][2][0]) > 32_000_000
+        plain = outs[4]  # variant 4 keeps no slot across epochs and counts in 32 bits
+        for v, o in enumerate(outs):
+            for a, b in zip(o, plain):
+                assert np.array_equal(a, b), f"variant {v}"
+    finally:
+        avl.set_tuning(-1, True)
+
+
 def test_graph_replay_with_new_parameters(avl):
     dems, masks, params, runs = small_ensemble()
     d = torch.from_numpy(dems).cuda()
