@@ -693,11 +693,11 @@ constexpr Variant make_variant() {
 
 // candidates of the autotuner: (threads per block, iterations per epoch, table slots per block, probes,
 // window top-up in blocks of slots, retention threshold). Two blocks share a CU: 6144 slots of 12 bytes
-// are 72 KiB of LDS per block.
+// are 72 KiB of LDS per block. The fifth keeps no slot across epochs.
 const Variant kVariants[] = {
-    make_variant<1024, 32, 6144, 4, 4, 1>(), make_variant<1024, 32, 6144, 4, 4, 2>(),
+    make_variant<1024, 16, 6144, 4, 4, 1>(), make_variant<1024, 32, 6144, 4, 4, 2>(),
     make_variant<1024, 16, 6144, 4, 4, 2>(), make_variant<1024, 32, 6144, 6, 4, 2>(),
-    make_variant<1024, 32, 4096, 4, 4, 0>(), make_variant<512, 32, 3072, 4, 4, 2>(),
+    make_variant<1024, 32, 4096, 4, 4, 0>(), make_variant<1024, 16, 6144, 8, 4, 2>(),
 };
 
 }  // namespace
