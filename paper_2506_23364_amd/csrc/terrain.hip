@@ -3,61 +3,69 @@
 // the row-major list of release texels. Plus the fill, padded-DEM and finalize helpers of the trajectory
 // pass.
 //
-// All of these are streaming passes bound by HBM bandwidth; each is written for 64-wide wavefronts
-// with every wave touching whole 256-byte stretches of consecutive cells.
+// These are streaming passes, written for 64-wide wavefronts with every wave touching whole 256-byte
+// stretches of consecutive cells; all but the normals (bound by their correctly rounded arithmetic) are
+// bound by HBM bandwidth.
 #include "avl_internal.h"
 
 namespace avl {
 
 // ------------------------------------------------------------------------------------------ normals
-// Block = 64 x 4 texels (one wave per row of the tile); the tile plus a one-texel halo is staged in LDS
-// so every DEM value is read from L2/HBM once per tile. Gradient: central difference inside, one-sided
-// at the grid edges (the textbook finite difference); n = (-gx, -gy, 1)/sqrt(gx^2 + gy^2 + 1).
-constexpr int kNTX = 64, kNTY = 4;
-
-__global__ __launch_bounds__(kNTX * kNTY) void k_normals(const float* __restrict__ dem, int H, int W, float cs,
-                                                         float cs2, float4* __restrict__ out) {
+// Block = 64 x 16 texels, 256 threads (one wave per row, four rows per thread); the tile plus a
+// one-texel halo is staged in LDS so every DEM value is read from L2/HBM about once. Gradient: central
+// difference inside, one-sided at the grid edges (the textbook finite difference);
+// n = (-gx, -gy, 1)/sqrt(gx^2 + gy^2 + 1). Each texel takes five correctly rounded divisions, two square
+// roots and an arctangent, so the pass is bound by VALU issue; a thread's four texels are independent
+// chains the compiler interleaves.
+constexpr int kNTX = 64, kNTY = 16, kNRows = 4;  // tile columns, tile rows, rows of threads
+__global__ __launch_bounds__(kNTX * kNRows) void k_normals(const float* __restrict__ dem, int H, int W, float cs,
+                                                           float cs2, float4* __restrict__ out) {
     __shared__ float tile[kNTY + 2][kNTX + 2];
     const int tx = threadIdx.x & (kNTX - 1), ty = threadIdx.x / kNTX;
     const int c0 = blockIdx.x * kNTX, r0 = blockIdx.y * kNTY;
     // stage (kNTY + 2) x (kNTX + 2) texels with clamped indices
-    for (int i = threadIdx.x; i < (kNTY + 2) * (kNTX + 2); i += kNTX * kNTY) {
+    for (int i = threadIdx.x; i < (kNTY + 2) * (kNTX + 2); i += kNTX * kNRows) {
         int lr = i / (kNTX + 2), lc = i - lr * (kNTX + 2);
         int r = min(max(r0 + lr - 1, 0), H - 1);
         int c = min(max(c0 + lc - 1, 0), W - 1);
         tile[lr][lc] = dem[(size_t)r * W + c];
     }
     __syncthreads();
-    const int r = r0 + ty, c = c0 + tx;
-    if (r >= H || c >= W) return;
-    const int lr = ty + 1, lc = tx + 1;
-    float gx, gy;
-    if (c == 0)
-        gx = (tile[lr][lc + 1] - tile[lr][lc]) / cs;
-    else if (c == W - 1)
-        gx = (tile[lr][lc] - tile[lr][lc - 1]) / cs;
-    else
-        gx = (tile[lr][lc + 1] - tile[lr][lc - 1]) / cs2;
-    if (r == 0)
-        gy = (tile[lr + 1][lc] - tile[lr][lc]) / cs;
-    else if (r == H - 1)
-        gy = (tile[lr][lc] - tile[lr - 1][lc]) / cs;
-    else
-        gy = (tile[lr + 1][lc] - tile[lr - 1][lc]) / cs2;
-    const float gg = gx * gx + gy * gy;
-    const float l = sqrtf(gg + 1.0f);
-    float4 o;
-    o.x = -(gx / l);
-    o.y = -(gy / l);
-    o.z = 1.0f / l;
-    o.w = atanf(sqrtf(gg)) * 57.295779513082320876798f;
-    out[(size_t)r * W + c] = o;
+    const int c = c0 + tx;
+    if (c >= W) return;
+#pragma unroll
+    for (int k = 0; k < kNTY / kNRows; ++k) {
+        const int r = r0 + ty + k * kNRows;
+        if (r >= H) break;
+        const int lr = ty + k * kNRows + 1, lc = tx + 1;
+        float gx, gy;
+        if (c == 0)
+            gx = (tile[lr][lc + 1] - tile[lr][lc]) / cs;
+        else if (c == W - 1)
+            gx = (tile[lr][lc] - tile[lr][lc - 1]) / cs;
+        else
+            gx = (tile[lr][lc + 1] - tile[lr][lc - 1]) / cs2;
+        if (r == 0)
+            gy = (tile[lr + 1][lc] - tile[lr][lc]) / cs;
+        else if (r == H - 1)
+            gy = (tile[lr][lc] - tile[lr - 1][lc]) / cs;
+        else
+            gy = (tile[lr + 1][lc] - tile[lr - 1][lc]) / cs2;
+        const float gg = gx * gx + gy * gy;
+        const float l = sqrtf(gg + 1.0f);
+        float4 o;
+        o.x = -(gx / l);
+        o.y = -(gy / l);
+        o.z = 1.0f / l;
+        o.w = atanf(sqrtf(gg)) * 57.295779513082320876798f;
+        out[(size_t)r * W + c] = o;
+    }
 }
 
 hipError_t launch_normals(const float* dem, int H, int W, float cs, float* out4, hipStream_t s) {
     dim3 grid((W + kNTX - 1) / kNTX, (H + kNTY - 1) / kNTY);
     const float cs2 = 2.0f * cs;
-    hipLaunchKernelGGL(k_normals, grid, dim3(kNTX * kNTY), 0, s, dem, H, W, cs, cs2,
+    hipLaunchKernelGGL(k_normals, grid, dim3(kNTX * kNRows), 0, s, dem, H, W, cs, cs2,
                        reinterpret_cast<float4*>(out4));
     return hipGetLastError();
 }
