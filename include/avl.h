@@ -162,7 +162,9 @@ typedef struct avl_run {
     uint64_t seed;     /* Philox key */
 } avl_run;
 
-/* Workspace bytes that avl_trajectories_batched needs (0 if a count is < 1). */
+/* Workspace bytes that avl_trajectories_batched needs (0 if a count is < 1): per mask, room for the
+ * release-cell list and the particles' start states of every cell (36 bytes per DEM cell), plus a padded
+ * copy of every tile and the run table. */
 AVL_API size_t avl_batched_workspace_bytes(int32_t H, int32_t W, int32_t n_tiles, int32_t n_masks, int32_t n_runs);
 
 /* Batched ensembles (section 5.2 motivates interactive sweeps of the trajectory parameters; section 3

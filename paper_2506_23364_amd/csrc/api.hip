@@ -46,7 +46,8 @@ size_t batched_workspace_bytes(int64_t H, int64_t W, int64_t n_tiles, int64_t n_
     return kControl + round256((size_t)scan_blocks(n) * sizeof(uint32_t)) +
            round256((size_t)n_masks * n * sizeof(int32_t)) + round256((size_t)n_masks * sizeof(int32_t)) +
            round256((size_t)n_runs * sizeof(RunConst)) + round256((size_t)(n_runs + 1) * sizeof(unsigned long long)) +
-           round256((size_t)n_runs * 4 * sizeof(unsigned long long)) +
+           round256((size_t)n_runs * 4 * sizeof(unsigned long long)) + round256((size_t)n_masks * sizeof(int32_t)) +
+           round256((size_t)n_masks * n * sizeof(StartRec)) +
            round256((size_t)n_tiles * padded_cells(H, W) * sizeof(float));
 }
 
@@ -68,6 +69,10 @@ Workspace carve_batched(void* base, int64_t H, int64_t W, int64_t n_masks, int64
     p += round256((size_t)(n_runs + 1) * sizeof(unsigned long long));
     w.stats = reinterpret_cast<unsigned long long*>(p);
     p += round256((size_t)n_runs * 4 * sizeof(unsigned long long));
+    w.rec_run = reinterpret_cast<int32_t*>(p);
+    p += round256((size_t)n_masks * sizeof(int32_t));
+    w.starts = reinterpret_cast<StartRec*>(p);
+    p += round256((size_t)n_masks * n * sizeof(StartRec));
     w.dem_pad = reinterpret_cast<float*>(p);
     return w;
 }
@@ -773,7 +778,7 @@ int avl_trajectories_batched(const float* dems, int32_t n_tiles, const uint8_t* 
     a.n_runs = (uint32_t)n_runs;
     a.S = step_limit;
     a.g2 = 9.81f + 9.81f;
-    a.starts = nullptr;
+    a.starts = ws.starts;
     a.pdiv = avl::make_divu32(particles_per_cell);
     a.wdiv = avl::make_divu32((uint32_t)W);
     a.dem_pad = ws.dem_pad;
@@ -799,9 +804,15 @@ int avl_trajectories_batched(const float* dems, int32_t n_tiles, const uint8_t* 
                 return e;
         const avl::RunSpec none{};
         const avl_params none_p{};
-        return avl::launch_setup_runs(reinterpret_cast<const avl::RunSpec*>(runs), params, (uint32_t)n_params, none,
-                                      none_p, ws.n_cells, (uint32_t)n_masks, (uint32_t)n_tiles, (uint32_t)n_runs, H, W,
-                                      cell_size, particles_per_cell, true, ws.runs, ws.run_off, run_status, s);
+        if ((e = avl::launch_fill_u32(reinterpret_cast<uint32_t*>(ws.rec_run), 0x7FFFFFFFu, n_masks, s)) != hipSuccess)
+            return e;
+        if ((e = avl::launch_setup_runs(reinterpret_cast<const avl::RunSpec*>(runs), params, (uint32_t)n_params, none,
+                                        none_p, ws.n_cells, (uint32_t)n_masks, (uint32_t)n_tiles, (uint32_t)n_runs, H,
+                                        W, cell_size, particles_per_cell, true, ws.runs, ws.run_off, run_status, s, -1,
+                                        ws.rec_run)) != hipSuccess)
+            return e;
+        return avl::launch_batch_records(reinterpret_cast<const avl::RunSpec*>(runs), ws.rec_run, ws.n_cells,
+                                         (uint32_t)n_masks, ws.cells, ws.dem_pad, H, W, ws.starts, s);
     };
     auto body = [&](const avl::LaunchShape& shape) -> hipError_t {
         hipError_t e;

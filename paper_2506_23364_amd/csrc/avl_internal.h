@@ -45,7 +45,8 @@ struct Workspace {
     RunConst* runs;               // n_runs
     uint32_t* blk;
     int32_t* cells;               // single: mult^2 H W; batch: n_masks x H*W
-    StartRec* starts;             // single only: mult^2 H W
+    StartRec* starts;             // single: mult^2 H W; batch: n_masks x H*W, parallel to cells
+    int32_t* rec_run;             // batch only: per scenario, the first valid run that uses it
     float* dem_pad;               // single: (H + 2) x (W + 2); batch: n_tiles of them
 };
 
@@ -70,7 +71,7 @@ struct RunConst {
     uint32_t P;                // particles per release cell
     unsigned long long n_slots;  // release cells x P
     uint32_t pad_off;          // element offset of the run's padded DEM tile
-    uint32_t pad2;
+    uint32_t use_rec;          // batch: its scenario's start records were made on its tile
 };
 static_assert(sizeof(RunConst) == 80, "RunConst layout");
 
@@ -160,11 +161,18 @@ struct RunSpec {
 };
 // specs/params: device arrays (batched) or NULL, then one_spec/one_param are used for the single run.
 // cap_cells >= 0: a run whose scenario has more release cells than cap_cells gets no slots (status 3).
+// rec_run (batched, n_scen entries filled with INT32_MAX beforehand, or NULL): receives per scenario the
+// lowest valid run index that uses it; a run whose tile is that run's tile gets use_rec = 1.
 hipError_t launch_setup_runs(const RunSpec* specs, const ::avl_params* params, uint32_t n_params, RunSpec one_spec,
                              ::avl_params one_param, const int32_t* n_cells_per_scen, uint32_t n_scen, uint32_t n_tiles,
                              uint32_t n_runs, int32_t H, int32_t W, float cell_size, uint32_t P, bool batched,
                              RunConst* runs, unsigned long long* run_off, int32_t* status, hipStream_t s,
-                             int64_t cap_cells = -1);
+                             int64_t cap_cells = -1, int32_t* rec_run = nullptr);
+// Batch: start records of every scenario's release cells on the tile of the scenario's first valid run
+// (rec_run from the run setup), read from the padded tiles; starts and cells are n_scen x HW arrays.
+hipError_t launch_batch_records(const RunSpec* specs, const int32_t* rec_run, const int32_t* n_cells_per_scen,
+                                uint32_t n_scen, const int32_t* cells, const float* dem_pad, int32_t H, int32_t W,
+                                StartRec* starts, hipStream_t s);
 hipError_t launch_trajectories(const TrajArgs& a, bool batched, const LaunchShape& shape, hipStream_t s);
 
 // Smooth forward and adjoint (smooth.hip)

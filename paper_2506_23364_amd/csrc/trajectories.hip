@@ -350,11 +350,13 @@ void k_trajectories(TrajArgs a) {
                     }
                 }
                 if (fresh) {
-                    // a single run reads the start state from its per-cell records; a batch computes it
-                    // (the DEM tile differs between runs), from the same padded tile the steps read
-                    const StartRec st = kBatch ? start_state_pad(dem_rs, Wp, row_bytes, W,
-                                                                 (uint32_t)a.cells[rc.cells_off + i])
-                                               : a.starts[i];
+                    // a single run reads the start state from its per-cell records, and so does a batch run
+                    // whose scenario's records were made on its tile (a uniform branch); any other batch run
+                    // computes it from the same padded tile the steps read
+                    const StartRec st = !kBatch     ? a.starts[i]
+                                        : rc.use_rec ? a.starts[rc.cells_off + i]
+                                                     : start_state_pad(dem_rs, Wp, row_bytes, W,
+                                                                       (uint32_t)a.cells[rc.cells_off + i]);
                     cell_id = st.cell;
                     x = st.x;
                     y = st.y;
@@ -579,7 +581,8 @@ __global__ __launch_bounds__(1024) void k_setup_runs(const RunSpec* __restrict__
                                                      float cs, uint32_t P, int32_t batched,
                                                      RunConst* __restrict__ runs,
                                                      unsigned long long* __restrict__ run_off,
-                                                     int32_t* __restrict__ status, int64_t cap_cells) {
+                                                     int32_t* __restrict__ status, int64_t cap_cells,
+                                                     int32_t* __restrict__ rec_run) {
     __shared__ unsigned long long wsum[1024 / kWave];
     const uint32_t per_thread = (n_runs + 1023) / 1024;
     const uint32_t b0 = threadIdx.x * per_thread;
@@ -627,6 +630,7 @@ __global__ __launch_bounds__(1024) void k_setup_runs(const RunSpec* __restrict__
         c.n_slots = bad ? 0ull : (unsigned long long)(uint32_t)n_cells_per_scen[sp.scenario] * P;
         runs[r] = c;
         if (status) status[r] = bad;
+        if (!bad && rec_run) atomicMin(rec_run + sp.scenario, (int32_t)r);
         local += (c.n_slots + kChunk - 1) / kChunk * kChunk;
     }
     // exclusive scan of the per-thread sums
@@ -650,6 +654,12 @@ __global__ __launch_bounds__(1024) void k_setup_runs(const RunSpec* __restrict__
         if (r >= n_runs) break;
         run_off[r] = run;
         run += (runs[r].n_slots + kChunk - 1) / kChunk * kChunk;
+        // every run's atomicMin has completed at the barrier above; read the result past the L1
+        if (rec_run && specs && specs[r].scenario < n_scen && specs[r].tile < n_tiles) {
+            const int32_t first =
+                __hip_atomic_load(rec_run + specs[r].scenario, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            runs[r].use_rec = (first != 0x7FFFFFFF && specs[first].tile == specs[r].tile) ? 1u : 0u;
+        }
     }
     if (threadIdx.x == 0) run_off[n_runs] = tot;
 }
@@ -658,10 +668,40 @@ hipError_t launch_setup_runs(const RunSpec* specs, const ::avl_params* params, u
                              ::avl_params one_param, const int32_t* n_cells_per_scen, uint32_t n_scen, uint32_t n_tiles,
                              uint32_t n_runs, int32_t H, int32_t W, float cell_size, uint32_t P, bool batched,
                              RunConst* runs, unsigned long long* run_off, int32_t* status, hipStream_t s,
-                             int64_t cap_cells) {
+                             int64_t cap_cells, int32_t* rec_run) {
     hipLaunchKernelGGL(k_setup_runs, dim3(1), dim3(1024), 0, s, specs, params, n_params, one_spec, one_param,
                        n_cells_per_scen, n_scen, n_tiles, n_runs, H, W, cell_size, P, batched ? 1 : 0, runs, run_off,
-                       status, cap_cells);
+                       status, cap_cells, rec_run);
+    return hipGetLastError();
+}
+
+// Batch start records: scenario s's cells on the tile of its first valid run, from the padded tile (the
+// same values the trajectory kernel would read, so the same start states).
+__global__ __launch_bounds__(256) void k_batch_records(const RunSpec* __restrict__ specs,
+                                                       const int32_t* __restrict__ rec_run,
+                                                       const int32_t* __restrict__ n_cells_per_scen, uint32_t n_scen,
+                                                       const int32_t* __restrict__ cells, const float* dem_pad, int H,
+                                                       int W, StartRec* __restrict__ starts) {
+    const uint64_t HW = (uint64_t)H * W;
+    const uint32_t Wp = (uint32_t)W + 2u, row_bytes = 4u * Wp;
+    const uint64_t np = (uint64_t)padded_cells(H, W);
+    for (uint32_t sc = blockIdx.y; sc < n_scen; sc += gridDim.y) {
+        const int32_t first = rec_run[sc];
+        if (first == 0x7FFFFFFF) continue;  // no valid run uses this scenario
+        const __amdgpu_buffer_rsrc_t rs =
+            buffer_rsrc(dem_pad + (uint64_t)specs[first].tile * np, (uint32_t)(np * sizeof(float)));
+        const int64_t nc = n_cells_per_scen[sc];
+        for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nc; i += (int64_t)gridDim.x * blockDim.x)
+            starts[sc * HW + i] = start_state_pad(rs, Wp, row_bytes, W, (uint32_t)cells[sc * HW + i]);
+    }
+}
+
+hipError_t launch_batch_records(const RunSpec* specs, const int32_t* rec_run, const int32_t* n_cells_per_scen,
+                                uint32_t n_scen, const int32_t* cells, const float* dem_pad, int32_t H, int32_t W,
+                                StartRec* starts, hipStream_t s) {
+    const uint32_t gy = n_scen < 1024u ? n_scen : 1024u;
+    hipLaunchKernelGGL(k_batch_records, dim3(64, gy), dim3(256), 0, s, specs, rec_run, n_cells_per_scen, n_scen, cells,
+                       dem_pad, H, W, starts);
     return hipGetLastError();
 }
 
