@@ -96,6 +96,28 @@ def test_batch_bad_runs_are_flagged(avl):
         assert np.array_equal(counts[k], ref.counts)
 
 
+def test_start_records_owner_and_other_tiles(avl):
+    """Start states of a scenario are recorded on the tile of its first valid run and read by the runs on
+    that tile; runs that pair the scenario with another tile compute them. Here scenario 0's first run is
+    invalid (bad parameters), so its records belong to the second run's tile (2); runs on tiles 0 and 1
+    compute, and every valid run equals the oracle."""
+    dems, masks, params, runs = small_ensemble()
+    ps = params + [dict(synth.DEFAULT_PARAMS, mu=-1.0)]
+    runs2 = [(0, 0, 4, 50, 9), (2, 0, 0, 51, 9), (0, 0, 1, 52, 9), (2, 0, 2, 53, 9), (1, 0, 3, 54, 9),
+             (2, 1, 0, 55, 9)]
+    res = run_batch(avl, dems, masks, ps, runs2, 4, 300)
+    status = host(res.status)
+    assert list(status) == [2, 0, 0, 0, 0, 0]
+    valid = [(k, r) for k, r in enumerate(runs2) if status[k] == 0]
+    counts, vmax, stats = host(res.counts), host(res.vmax), host(res.stats)
+    for k, run in valid:
+        ref = oracle_run(dems, masks, ps, run, 4, 300)
+        assert np.array_equal(counts[k], ref.counts), f"run {k}"
+        np.testing.assert_allclose(vmax[k], ref.vmax, rtol=1e-5, atol=0, err_msg=f"run {k}")
+        assert list(stats[k]) == [ref.steps, ref.n_exit, ref.n_stop, ref.n_limit], f"run {k}"
+    assert counts[0].sum() == 0
+
+
 def test_every_variant_gives_identical_rasters(avl):
     dems, masks, params, runs = small_ensemble()
     w = synth.make_workload("tiny")
