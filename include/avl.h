@@ -176,8 +176,8 @@ AVL_API size_t avl_batched_workspace_bytes(int32_t H, int32_t W, int32_t n_tiles
  * counts, vmax: n_runs*H*W (run r at r*H*W), as in avl_trajectories. stats (nullable): n_runs*4 uint64.
  * run_status (nullable): n_runs int32, 0 = ran, 1 = an index out of range, 2 = invalid parameters (such a
  * run releases no particle and leaves zero rasters). particles_per_cell and step_limit are shared.
- * Need n_runs*H*W, n_tiles*H*W, n_masks*H*W and n_tiles*(H+2)*(W+2) all < 2^32 - 1 and (H+2)*(W+2) < 2^30
- * (the kernel reads padded copies of the tiles through 32-bit offsets). When `stream` is not the null stream, the
+ * Need H, W < 2^23, n_runs*H*W, n_tiles*H*W, n_masks*H*W and n_tiles*(H+2)*(W+2) all < 2^32 - 1 and
+ * (H+2)*(W+2) < 2^30 (the kernel reads padded copies of the tiles through 32-bit offsets). When `stream` is not the null stream, the
  * whole sequence (zero fills, compactions, run setup, trajectory kernel, finalize) is captured once into
  * a HIP graph per argument set and replayed on later calls. */
 AVL_API int avl_trajectories_batched(const float* dems, int32_t n_tiles, const uint8_t* masks, int32_t n_masks,
@@ -199,8 +199,9 @@ AVL_API int avl_trajectories_batched(const float* dems, int32_t n_tiles, const u
  * also splats (mass per particle) * v at the new position into velocity_q / velocity.
  * max_release_cells: an upper bound on the number of release cells (it sizes the checkpoints); a mask with
  * more release cells releases nothing and sets *status = 3 (status: device int32, nullable).
- * stats as in avl_trajectories. workspace: avl_smooth_workspace_bytes(...) bytes; it keeps the
- * per-particle checkpoints (every 64 steps) that avl_trajectories_backward reads. */
+ * stats as in avl_trajectories. H, W >= 1, both < 2^23, (H + 2)(W + 2) < 2^30 (as avl_trajectories; the same
+ * limits hold for avl_trajectories_backward and avl_calibrate). workspace: avl_smooth_workspace_bytes(...) bytes;
+ * it keeps the per-particle checkpoints (every 64 steps) that avl_trajectories_backward reads. */
 #define AVL_SMOOTH_VELOCITY 1u
 AVL_API size_t avl_smooth_workspace_bytes(int32_t H, int32_t W, int32_t max_release_cells,
                                           uint32_t particles_per_cell, uint32_t step_limit);

@@ -614,6 +614,8 @@ int smooth_checks(const char* where, const float* dem, const uint8_t* mask, int3
     if (!dem || !mask || !workspace) return fail(AVL_EINVAL, "%s: null pointer", where);
     if (!grid_ok(H, W, 1) || avl::padded_cells(H, W) >= (int64_t(1) << 30))
         return fail(AVL_EINVAL, "%s: need H, W >= 1 and (H + 2)(W + 2) < 2^30", where);
+    // the padded patch's row offset is a 24-bit product (W + 2 < 2^24), and positions are binary32
+    if (H >= (1 << 23) || W >= (1 << 23)) return fail(AVL_EINVAL, "%s: need H, W < 2^23", where);
     if (!finite(cell_size) || !(cell_size > 0.0f)) return fail(AVL_EINVAL, "%s: cell_size must be > 0", where);
     if (P == 0) return fail(AVL_EINVAL, "%s: particles_per_cell must be >= 1", where);
     if (max_release_cells < 0 || (int64_t)max_release_cells > (int64_t)H * W)
@@ -747,6 +749,8 @@ int avl_trajectories_batched(const float* dems, int32_t n_tiles, const uint8_t* 
     if (!dems || !masks || !params || !runs || !counts || !vmax || !workspace)
         return fail(AVL_EINVAL, "avl_trajectories_batched: null pointer");
     if (!grid_ok(H, W, 1)) return fail(AVL_EINVAL, "avl_trajectories_batched: need H, W >= 1 and H*W < 2^31");
+    // the padded patch's row offset is a 24-bit product (W + 2 < 2^24), and positions are binary32
+    if (H >= (1 << 23) || W >= (1 << 23)) return fail(AVL_EINVAL, "avl_trajectories_batched: need H, W < 2^23");
     if (n_tiles < 1 || n_masks < 1 || n_params < 1 || n_runs < 1)
         return fail(AVL_EINVAL, "avl_trajectories_batched: need n_tiles, n_masks, n_params, n_runs >= 1");
     const int64_t n = (int64_t)H * W;

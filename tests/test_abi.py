@@ -237,3 +237,49 @@ def test_calibrate_rejects_bad_adam(L, field, value):
 
 def test_calibrate_small_workspace(L):
     assert _calib(L, wsb=L.lib.avl_calibrate_workspace_bytes(16, 16, 10, 4, 100) - 1) == L.AVL_ENOMEM
+
+
+def _smooth(L, fn, **kw):
+    a = dict(dem=FAKE, mask=FAKE, mass=None, H=16, W=16, cs=10.0, params=L.Params.make(), P=4, S=100, seed=1, run=0,
+             cap=10, ws=FAKE, stream=None)
+    a.update(kw)
+    wsb = a.get("wsb", L.smooth_workspace_bytes(a["H"], a["W"], a["cap"], a["P"], a["S"]))
+    p = ctypes.byref(a["params"])
+    if fn == "smooth":
+        return L.lib.avl_trajectories_smooth(a["dem"], a["mask"], a["mass"], a["H"], a["W"], a["cs"], p, a["P"],
+                                             a["S"], a["seed"], a["run"], a["cap"], 0, FAKE, None, None, None, None,
+                                             None, a["ws"], wsb, a["stream"])
+    return L.lib.avl_trajectories_backward(a["dem"], a["mask"], a["mass"], a["H"], a["W"], a["cs"], p, a["P"], a["S"],
+                                           a["seed"], a["run"], a["cap"], FAKE, FAKE, FAKE, None, a["ws"], wsb,
+                                           a["stream"])
+
+
+# The padded patch's row offset is formed with a 24-bit multiply, so every particle pass needs W + 2 < 2^24;
+# the entry points require H, W < 2^23. A 3 x 2^24 grid passes every other size check.
+WIDE = dict(H=3, W=1 << 24)
+
+
+def test_wide_grid_rejected_by_every_particle_pass(L):
+    assert _traj(L, **WIDE, wsb=L.workspace_bytes(3, 1 << 24)) == L.AVL_EINVAL
+    assert "2^23" in L.lib.avl_last_error().decode()
+    assert _smooth(L, "smooth", **WIDE) == L.AVL_EINVAL
+    assert "2^23" in L.lib.avl_last_error().decode()
+    assert _smooth(L, "backward", **WIDE) == L.AVL_EINVAL
+    assert "2^23" in L.lib.avl_last_error().decode()
+    assert _calib(L, **WIDE, wsb=L.lib.avl_calibrate_workspace_bytes(3, 1 << 24, 10, 4, 100)) == L.AVL_EINVAL
+    assert "2^23" in L.lib.avl_last_error().decode()
+    h, w = WIDE["H"], WIDE["W"]
+    rc = L.lib.avl_trajectories_batched(FAKE, 1, FAKE, 1, h, w, 10.0, FAKE, 1, FAKE, 1, 4, 100, FAKE, FAKE, None,
+                                        None, FAKE, L.batched_workspace_bytes(h, w, 1, 1, 1), None)
+    assert rc == L.AVL_EINVAL
+    assert "2^23" in L.lib.avl_last_error().decode()
+
+
+def test_grid_just_below_the_width_limit_passes_the_size_checks(L):
+    # 2 x (2^23 - 1): accepted by the size checks, so a too-small workspace is what the calls report
+    h, w = 2, (1 << 23) - 1
+    assert _smooth(L, "smooth", H=h, W=w, wsb=1) == L.AVL_ENOMEM
+    rc = L.lib.avl_trajectories_batched(FAKE, 1, FAKE, 1, h, w, 10.0, FAKE, 1, FAKE, 1, 4, 100, FAKE, FAKE, None,
+                                        None, FAKE, 1, None)
+    assert rc == L.AVL_ENOMEM
+
