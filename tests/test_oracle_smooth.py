@@ -7,7 +7,8 @@ of its gradient with respect to mu, xi, h and the per-cell release mass.
   step makes the resting point continuous);
 * conservation: the deposit holds exactly the mass of the particles that did not leave the grid (and the
   fixed-point raster agrees with the unquantised one to 2^-24 per splat corner);
-* velocity splat: equals a brute-force rebuild from per-particle traces;
+* velocity splat: its total equals the sum of speeds over per-particle traces, and its first moments put each
+  speed at the position its step moved to;
 * gradient: the closed-form derivative -z_r / (mu^2 cs) of the resting point on the plane-to-flat; the
   reverse sweep against an independent forward-mode derivation; against central finite differences of
   the binary64 forward; the mass gradient against the exact linear response.
@@ -92,6 +93,51 @@ def test_velocity_splat_matches_traces():
             tot += (1.0 / P) * np.sqrt(tr.v2[1:]).sum()
     assert abs(res.vel.sum() - tot) < 1e-9 * tot
     assert tot > 0
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_velocity_splat_first_moments_put_it_after_the_move(prec):
+    """Where each speed lands. A bilinear splat reproduces linear functions: for a point p at least half a
+    texel inside the grid, the weights w_q(p) of its four texels satisfy sum_q w_q (c_q + 1/2) = p_x and
+    sum_q w_q (r_q + 1/2) = p_y. So the raster's first moments are sum mp v_k x_k and sum mp v_k y_k over the
+    accepted steps k, with (x_k, y_k) the position the step moved to and v_k the speed after it. A splat at
+    the position before the move, or at the release point, gives other moments (checked to differ here by
+    far more than the tolerance), which the total alone cannot show."""
+    n = 160
+    dem = synth.alpine_dem(n, 900.0, seed=5)
+    mask = np.zeros((n, n), np.uint8)
+    mask[78:82, 78:82] = 1
+    p = oracle.make_params(mu=0.1, xi=1500.0, randomness=0.2)
+    P, S = 3, 60  # paths of at most 60 one-cell steps stay inside [18, 142]^2
+    res = oracle.smooth_forward(dem, mask, 10.0, p, P, S, 9, vel_splat=True, prec=prec)
+    mp = 1.0 / P
+    m0 = mx = my = 0.0
+    pre_x = pre_y = rel_x = 0.0
+    for cell in np.flatnonzero(mask):
+        r, c = divmod(int(cell), n)
+        for j in range(P):
+            tr = oracle.trace(dem, 10.0, p, r, c, j, S, 9, prec=prec)
+            x, y = tr.x.astype(np.float64), tr.y.astype(np.float64)
+            v = np.sqrt(tr.v2[1:].astype(np.float64))
+            assert x.min() > 0.5 and x.max() < n - 0.5 and y.min() > 0.5 and y.max() < n - 0.5
+            m0 += mp * v.sum()
+            mx += mp * (v * x[1:]).sum()
+            my += mp * (v * y[1:]).sum()
+            pre_x += mp * (v * x[:-1]).sum()
+            pre_y += mp * (v * y[:-1]).sum()
+            rel_x += mp * (v * x[0]).sum()
+    centres = np.arange(n) + 0.5
+    vel = res.vel.astype(np.float64)
+    tol = 1e-9 if prec == "f64" else 2e-6
+    assert abs(vel.sum() - m0) <= tol * m0
+    assert abs((vel.sum(axis=0) * centres).sum() - mx) <= tol * mx
+    assert abs((vel.sum(axis=1) * centres).sum() - my) <= tol * my
+    # the moments tell the placements apart
+    assert abs(pre_x - mx) + abs(pre_y - my) > 1e3 * tol * (mx + my)
+    assert abs(rel_x - mx) > 1e3 * tol * mx
+    # the fixed-point raster carries the same splat: within 2^-24 per corner of every splat
+    n_splat = int(res.steps)
+    assert abs(res.vel_q.sum() * 2.0 ** -24 - vel.sum()) <= 4 * n_splat * 2.0 ** -24 + tol * m0
 
 
 @pytest.mark.parametrize("mu", [0.15, 0.3])
