@@ -44,8 +44,10 @@ _libs: dict = {}
 
 def _lib(prec: str):
     if prec not in _libs:
-        path = os.path.join(_HERE, f"liboracle_{prec}.so")
-        if not os.path.exists(path):
+        # AVL_ORACLE_LIBDIR: load the twins from another directory (the sanitizer build of the tests)
+        libdir = os.environ.get("AVL_ORACLE_LIBDIR")
+        path = os.path.join(libdir or _HERE, f"liboracle_{prec}.so")
+        if not libdir and not os.path.exists(path):
             _build.build()
         lib = ctypes.CDLL(path)
         _libs[prec] = lib

@@ -380,7 +380,11 @@ static int particle_at(const model* m, int tr, int tc, int mult, uint32_t replic
     }
     *steps += n_steps;
     if (rows) *rows = nrow;
-    if (ei) { ei->reason = reason; ei->x = x; ei->y = y; ei->v2 = v2; }
+    if (ei) {
+        ei->reason = reason; ei->x = x; ei->y = y; ei->v2 = v2;
+        /* only an energy stop has a rejected target (set above); the other ends rest where they are */
+        if (reason != END_STOP) { ei->x1 = x; ei->y1 = y; ei->num = 0; }
+    }
     return reason;
 }
 
@@ -512,9 +516,13 @@ static void splat(const model* m, int64_t* q, real* f, real x, real y, real val)
 static void rest_point(const end_info* e, real* px, real* py, real* tstar)
 {
     real t = 0;
-    if (e->reason == END_STOP && e->v2 > 0) t = e->v2 / (e->v2 - e->num);
-    *px = e->x + t * (e->x1 - e->x);
-    *py = e->y + t * (e->y1 - e->y);
+    *px = e->x;
+    *py = e->y;
+    if (e->reason == END_STOP) {
+        if (e->v2 > 0) t = e->v2 / (e->v2 - e->num);
+        *px = e->x + t * (e->x1 - e->x);
+        *py = e->y + t * (e->y1 - e->y);
+    }
     *tstar = t;
 }
 
