@@ -119,6 +119,22 @@ AVL_API int avl_trajectories(const float* dem, const uint8_t* mask, int32_t H, i
                      uint32_t run_id, uint32_t* counts, float* vmax, uint64_t* stats, void* workspace,
                      size_t workspace_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): avl_trajectories without a workspace argument. The workspace lives in
+ * a scratch array of avl_noalloc_scratch_bytes() bytes (64 MiB) that the library holds on each GPU it runs
+ * on until the process ends; the call allocates nothing, creates no HIP event and does not autotune (it
+ * takes the variant an earlier avl_trajectories call tuned for a problem of this size, else variant 0;
+ * results are the same for every variant). Arguments, results and errors are those of avl_trajectories,
+ * plus AVL_EINVAL when avl_workspace_bytes(H, W) exceeds the scratch (about 1.6 M texels, e.g. 1280 x 1280)
+ * and AVL_EHIP when the scratch's device address cannot be found. Every call on one GPU uses that GPU's
+ * one scratch array, so calls that overlap on one GPU (other streams, other threads) race: serialise them.
+ * Each call re-initialises what it reads from the scratch. */
+AVL_API int avl_trajectories_noalloc(const float* dem, const uint8_t* mask, int32_t H, int32_t W, float cell_size,
+                                     const avl_params* params, uint32_t particles_per_cell, uint32_t step_limit,
+                                     uint64_t seed, uint32_t run_id, uint32_t* counts, float* vmax, uint64_t* stats,
+                                     void* stream);
+AVL_API size_t avl_noalloc_scratch_bytes(void);
+
 /* Release texture at a finer resolution than the DEM (section 5.2: the user picks the texture resolution
  * at which release points are evaluated; a known release area, as for the historic event of figure 1, can
  * be handed in as a texture of its own). The texture has mult x mult texels per DEM cell, row-major,

@@ -76,6 +76,10 @@ def _load() -> ctypes.CDLL:
     L.avl_release_cells.argtypes = [vp, i32, i32, vp, vp, vp, sz, vp]
     L.avl_trajectories.argtypes = [vp, vp, i32, i32, f32, ctypes.POINTER(Params), u32, u32, u64, u32, vp, vp, vp,
                                    vp, sz, vp]
+    L.avl_trajectories_noalloc.argtypes = [vp, vp, i32, i32, f32, ctypes.POINTER(Params), u32, u32, u64, u32, vp,
+                                           vp, vp, vp]
+    L.avl_noalloc_scratch_bytes.argtypes = []
+    L.avl_noalloc_scratch_bytes.restype = sz
     L.avl_snow_cover.argtypes = [vp, vp, i32, i32, f32, f32, f32, f32, vp, vp]
     L.avl_release_mask_fine.argtypes = [vp, vp, i32, i32, i32, f32, f32, f32, f32, vp, vp]
     L.avl_fine_workspace_bytes.argtypes = [i32, i32, i32]
@@ -118,7 +122,7 @@ def _load() -> ctypes.CDLL:
     L.avl_last_error.argtypes = []
     L.avl_last_error.restype = ctypes.c_char_p
     for name in ("avl_normals", "avl_release_mask", "avl_release_cells", "avl_trajectories", "avl_release_mask_fine",
-                 "avl_trajectories_fine", "avl_snow_cover"):
+                 "avl_trajectories_fine", "avl_snow_cover", "avl_trajectories_noalloc"):
         getattr(L, name).restype = ctypes.c_int
     return L
 
@@ -283,6 +287,28 @@ def trajectories(dem: torch.Tensor, mask: torch.Tensor, cell_size: float, params
                                     particles_per_cell, step_limit, seed & (2**64 - 1), run_id,
                                     out.counts.data_ptr(), out.vmax.data_ptr(), out.stats.data_ptr(), ws.data_ptr(),
                                     ws.numel(), _stream(dem.device)), "avl_trajectories")
+    return out
+
+
+def trajectories_noalloc(dem: torch.Tensor, mask: torch.Tensor, cell_size: float, params: Params,
+                         particles_per_cell: int, step_limit: int, seed: int, run_id: int = 0,
+                         out: RunResult | None = None) -> RunResult:
+    """:func:`trajectories` through the allocation-free entry point: the library works in its own per-GPU
+    scratch instead of a workspace (the outputs are still the caller's; pass ``out`` to allocate nothing)."""
+    _need(dem, "dem", torch.float32, 2)
+    _need(mask, "mask", torch.uint8, 2)
+    h, w = dem.shape
+    if mask.shape != (h, w):
+        raise ValueError("mask must have the DEM's shape")
+    if out is None:
+        out = RunResult(torch.empty((h, w), dtype=torch.uint32, device=dem.device),
+                        torch.empty((h, w), dtype=torch.float32, device=dem.device),
+                        torch.empty(4, dtype=torch.uint64, device=dem.device))
+    with torch.cuda.device(dem.device):
+        _check(lib.avl_trajectories_noalloc(dem.data_ptr(), mask.data_ptr(), h, w, cell_size, ctypes.byref(params),
+                                            particles_per_cell, step_limit, seed & (2**64 - 1), run_id,
+                                            out.counts.data_ptr(), out.vmax.data_ptr(), out.stats.data_ptr(),
+                                            _stream(dem.device)), "avl_trajectories_noalloc")
     return out
 
 

@@ -12,6 +12,13 @@
 
 #include "avl_internal.h"
 
+// Scratch of avl_trajectories_noalloc: the single-run workspace in a file-scope device array, one copy per
+// GPU, which the code object's loader places in device memory and which lives until the process ends.
+// Host code never passes `scratch` itself to a kernel (on the host it only names the symbol): the device
+// address comes from hipGetSymbolAddress, taken once per device with that device current.
+static constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 namespace avl {
 
 size_t workspace_bytes(int64_t H, int64_t W, int64_t mult) {
@@ -222,9 +229,11 @@ bool capturing(hipStream_t s) {
 // Variant for this problem: the override, the cached choice, or (first time, not under capture) the
 // fastest of all variants, each timed once with HIP events after `zero` re-zeroes what the kernel
 // accumulates into. The inputs of the kernel (cell lists, run table) must already be enqueued.
+// may_tune = false: never time the variants here (the allocation-free entry point creates no events); an
+// uncached problem then takes variant 0.
 template <class Zero>
 hipError_t choose_variant(const avl::TrajArgs& a, bool batched, const std::vector<int64_t>& key, hipStream_t s,
-                          Zero zero, int* variant) {
+                          Zero zero, int* variant, bool may_tune = true) {
     {
         std::lock_guard<std::mutex> lk(g_mu);
         if (g_variant_override >= 0) {
@@ -237,7 +246,7 @@ hipError_t choose_variant(const avl::TrajArgs& a, bool batched, const std::vecto
             return hipSuccess;
         }
     }
-    if (capturing(s)) {
+    if (!may_tune || capturing(s)) {
         *variant = 0;
         return hipSuccess;
     }
@@ -451,12 +460,36 @@ int avl_release_cells(const uint8_t* mask, int32_t H, int32_t W, int32_t* cells,
 
 namespace {
 
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_ptr;  // device ordinal -> address of that device's copy of `scratch`
+
+hipError_t scratch_address(void** out) {
+    int dev = 0;
+    hipError_t e;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(dev);
+    if (it != g_scratch_ptr.end()) {
+        *out = it->second;
+        return hipSuccess;
+    }
+    void* ptr = nullptr;
+    if ((e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch))) != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = ptr;
+    *out = ptr;
+    return hipSuccess;
+}
+
 // One trajectory pass from a release texture with mult x mult texels per DEM cell (mask: mult*H x mult*W).
+// noalloc: ignore workspace / workspace_bytes and run in the current device's `scratch` (no allocation,
+// no event creation, no tuning).
 int single_pass(const char* where, const float* dem, const uint8_t* mask, int32_t H, int32_t W, int32_t mult,
                 float cell_size, const avl_params* params, uint32_t particles_per_cell, uint32_t step_limit,
                 uint64_t seed, uint32_t run_id, uint32_t* counts, float* vmax, uint64_t* stats, void* workspace,
-                size_t workspace_bytes, void* stream) {
-    if (!dem || !mask || !counts || !vmax || !workspace) return fail(AVL_EINVAL, "%s: null pointer", where);
+                size_t workspace_bytes, void* stream, bool noalloc = false) {
+    if (!dem || !mask || !counts || !vmax || (!noalloc && !workspace))
+        return fail(AVL_EINVAL, "%s: null pointer", where);
     if (!grid_ok(H, W, 1) || avl::padded_cells(H, W) >= (int64_t(1) << 30))
         return fail(AVL_EINVAL, "%s: need H, W >= 1 and (H + 2)(W + 2) < 2^30", where);
     if (mult < 1 || mult > AVL_MAX_RELEASE_MULT)
@@ -473,6 +506,15 @@ int single_pass(const char* where, const float* dem, const uint8_t* mask, int32_
     if (const char* why = check_params(params)) return fail(AVL_EINVAL, "%s: %s", where, why);
     const int64_t n = (int64_t)H * W;
     const int64_t nf = n * mult * mult;
+    if (noalloc) {
+        const size_t need = avl::workspace_bytes(H, W, mult);
+        if (need > kScratchBytes)
+            return fail(AVL_EINVAL, "%s: the grid needs %zu bytes of scratch, more than the %zu bytes it holds", where,
+                        need, kScratchBytes);
+        hipError_t e = scratch_address(&workspace);
+        if (e != hipSuccess) return hip_fail(e, (std::string(where) + ": scratch address").c_str());
+        workspace_bytes = kScratchBytes;
+    }
     if (workspace_bytes < avl::workspace_bytes(H, W, mult)) return fail(AVL_ENOMEM, "%s: workspace too small", where);
     hipStream_t s = static_cast<hipStream_t>(stream);
     avl::Workspace ws = avl::carve(workspace, H, W, mult);
@@ -517,8 +559,8 @@ int single_pass(const char* where, const float* dem, const uint8_t* mask, int32_
                                     particles_per_cell, false, ws.runs, ws.run_off, nullptr, s)) != hipSuccess)
         return hip_fail(e, (std::string(where) + ": run setup").c_str());
     int variant = 0;
-    if ((e = choose_variant(a, false, tune_key(false, nf, 1, particles_per_cell, step_limit), s, zero, &variant)) !=
-        hipSuccess)
+    if ((e = choose_variant(a, false, tune_key(false, nf, 1, particles_per_cell, step_limit), s, zero, &variant,
+                            !noalloc)) != hipSuccess)
         return hip_fail(e, (std::string(where) + ": autotune").c_str());
     g_last_variant = variant;
     if ((e = zero()) != hipSuccess) return hip_fail(e, (std::string(where) + ": zero").c_str());
@@ -539,6 +581,17 @@ int avl_trajectories(const float* dem, const uint8_t* mask, int32_t H, int32_t W
     return single_pass("avl_trajectories", dem, mask, H, W, 1, cell_size, params, particles_per_cell, step_limit,
                        seed, run_id, counts, vmax, stats, workspace, workspace_bytes, stream);
 }
+
+int avl_trajectories_noalloc(const float* dem, const uint8_t* mask, int32_t H, int32_t W, float cell_size,
+                             const avl_params* params, uint32_t particles_per_cell, uint32_t step_limit,
+                             uint64_t seed, uint32_t run_id, uint32_t* counts, float* vmax, uint64_t* stats,
+                             void* stream) {
+    g_last_error.clear();
+    return single_pass("avl_trajectories_noalloc", dem, mask, H, W, 1, cell_size, params, particles_per_cell,
+                       step_limit, seed, run_id, counts, vmax, stats, nullptr, 0, stream, true);
+}
+
+size_t avl_noalloc_scratch_bytes(void) { return kScratchBytes; }
 
 int avl_snow_cover(const float* normals4, const float* dem, int32_t H, int32_t W, float snow_line, float alt_blend,
                    float max_slope_deg, float slope_blend_deg, float* alpha, void* stream) {

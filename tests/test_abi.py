@@ -283,3 +283,30 @@ def test_grid_just_below_the_width_limit_passes_the_size_checks(L):
                                         None, FAKE, 1, None)
     assert rc == L.AVL_ENOMEM
 
+
+def _noalloc(L, **kw):
+    a = dict(dem=FAKE, mask=FAKE, H=16, W=16, cs=10.0, params=L.Params.make(), P=4, S=10, seed=1, run=0,
+             counts=FAKE, vmax=FAKE, stats=None, stream=None)
+    a.update(kw)
+    p = a["params"]
+    return L.lib.avl_trajectories_noalloc(a["dem"], a["mask"], a["H"], a["W"], a["cs"], ctypes.byref(p) if p else None,
+                                          a["P"], a["S"], a["seed"], a["run"], a["counts"], a["vmax"], a["stats"],
+                                          a["stream"])
+
+
+def test_noalloc_scratch_size(L):
+    assert L.lib.avl_noalloc_scratch_bytes() == 64 << 20
+    # 1280^2 fits the scratch; 1296^2 needs more than it holds
+    assert L.workspace_bytes(1280, 1280) <= L.lib.avl_noalloc_scratch_bytes() < L.workspace_bytes(1296, 1296)
+
+
+@pytest.mark.parametrize("kw", [
+    dict(dem=None), dict(mask=None), dict(counts=None), dict(vmax=None), dict(params=None), dict(H=0), dict(W=-3),
+    dict(cs=0.0), dict(P=0), dict(params="bad_mu"), dict(H=3, W=1 << 24),
+    dict(H=1296, W=1296), dict(H=4096, W=420),  # more scratch than the library holds
+])
+def test_noalloc_rejects_bad_arguments_before_touching_the_gpu(L, kw):
+    if kw.get("params") == "bad_mu":
+        kw["params"] = L.Params.make(mu=-1.0)
+    assert _noalloc(L, **kw) == L.AVL_EINVAL
+    assert L.lib.avl_last_error()
