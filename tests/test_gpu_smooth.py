@@ -139,16 +139,21 @@ def test_autograd_function(avl):
 
 
 def test_calibration_gradient_vs_fp64_and_finite_differences(avl):
-    """The calibration workload (1024^2, 5000 release cells; 16 particles per cell here to keep the FP64
-    oracle short): the gradient of L = sum gD * D with gD = dMSE/dD at (mu0, xi0).
+    """The calibration workload (1024^2, 5000 release cells x 128 particles, 3000 steps): the gradient of
+    L = sum gD * D with gD = dMSE/dD at (mu0, xi0), against the FP64 oracle and central differences.
 
-    The deposit is piecewise smooth in (mu, xi): a particle that barely reaches a bump crest with v^2 -> 0
-    may restart downhill, so L jumps where such a particle's end changes. Central differences therefore
-    use steps of 4 binary32 ulps and are taken per particle, over the particles whose end (reason, steps
-    completed) is the same on both sides (all of them here). The FP64 adjoint must match them to 1e-3;
-    the GPU's FP32 gradient must match the FP64 adjoint to 1e-3 of the sum of |per-particle terms|
-    (a few FP32 paths diverge from FP64 at texel-edge crossings)."""
-    c = synth.make_calibration(particles_per_cell=16)
+    * The GPU's per-particle terms equal the FP32 oracle's bit for bit.
+    * FP32 against FP64: 0.11 % of the particles take another path in binary32 (a texel-edge crossing
+      rounds the other way), which moves dL/dmu by 1.2e-3 of itself and dL/dxi, dL/dh by 6e-4. Over the
+      particles whose FP32 and FP64 paths end alike (same end, same steps) the two agree to 3e-5. The bar:
+      1e-3 of the gradient over those particles, and 1e-3 (xi, h) and 1.5e-3 (mu) over all of them.
+    * The deposit is piecewise smooth in (mu, xi): a particle that barely reaches a bump crest with
+      v^2 -> 0 may restart downhill, so L jumps where such a particle's end changes. Per-particle central
+      differences of the FP64 forward at 4-ulp steps, over particles whose end does not change (all but a
+      few), match the FP64 adjoint to 1e-3. The whole loss's central difference at steps of 1e-3 of the
+      parameter includes the jumps: it exceeds the pathwise gradient by about 1 % (mu) and 1.3 % (xi), the
+      jump contribution the adjoint leaves out; the bar is 3 %."""
+    c = synth.make_calibration()
     d, m, mass = dev(c.dem), dev(c.mask), dev(c.mass)
     P, S, seed = c.particles_per_cell, c.step_limit, c.seed
     target = avl.smooth_deposit(torch.tensor(c.mu_star), torch.tensor(c.xi_star), torch.tensor(1.0), mass, d, m,
@@ -160,12 +165,27 @@ def test_calibration_gradient_vs_fp64_and_finite_differences(avl):
                                                mass=mass, per_particle=True)
     g_gpu = host(dparams)
     gD_np = host(gD)
-    g64 = oracle.smooth_backward(c.dem, c.mask, c.cell_size, oracle.make_params(**p0), P, S, seed, gD_np,
-                                 mass=c.mass, prec="f64")
-    g32 = oracle.smooth_backward(c.dem, c.mask, c.cell_size, oracle.make_params(**p0), P, S, seed, gD_np,
-                                 mass=c.mass, prec="f32")
+    op = oracle.make_params(**p0)
+    g64 = oracle.smooth_backward(c.dem, c.mask, c.cell_size, op, P, S, seed, gD_np, mass=c.mass, prec="f64")
+    g32 = oracle.smooth_backward(c.dem, c.mask, c.cell_size, op, P, S, seed, gD_np, mass=c.mass, prec="f32")
     n = g32.per_particle.shape[0]
-    assert np.array_equal(host(pp)[:, :n].T, g32.per_particle)       # GPU == FP32 oracle, bit for bit
+    pp_gpu = host(pp)[:, :n].T
+    assert np.array_equal(pp_gpu, g32.per_particle)       # GPU == FP32 oracle, bit for bit
+    _, r32, s32 = oracle.smooth_particles(c.dem, c.mask, c.cell_size, op, P, S, seed, gD_np, mass=c.mass, prec="f32")
+    _, r64, s64 = oracle.smooth_particles(c.dem, c.mask, c.cell_size, op, P, S, seed, gD_np, mass=c.mass, prec="f64")
+    same_path = (r32 == r64) & (s32 == s64)
+    diverged = 1.0 - same_path.mean()
+    print(f"FP32 paths that differ from FP64: {int((~same_path).sum())} of {n} ({diverged:.2e})")
+    assert diverged < 2e-3
+    g64_tot = (g64.dmu, g64.dxi, g64.dh)
+    for i, (name, bar) in enumerate((("mu", 1.5e-3), ("xi", 1e-3), ("h", 1e-3))):
+        rel = abs(g_gpu[i] - g64_tot[i]) / abs(g64_tot[i])
+        sp = pp_gpu[same_path, i].astype(np.float64).sum()
+        sp64 = g64.per_particle[same_path, i].sum()
+        rel_same = abs(sp - sp64) / abs(sp64)
+        print(f"dL/d{name}: GPU {g_gpu[i]:.9g} FP64 {g64_tot[i]:.9g} rel {rel:.2e}; same-path rel {rel_same:.2e}")
+        assert rel_same <= 1e-3, (name, rel_same)
+        assert rel <= bar, (name, rel)
     for i, name in enumerate(("mu", "xi")):
         v = np.float32(p0[name])
         hi, lo = v, v
@@ -181,5 +201,12 @@ def test_calibration_gradient_vs_fp64_and_finite_differences(avl):
         fd = (Lh - Ll) / (float(hi) - float(lo))
         adj = g64.per_particle[:, i]
         assert abs(fd[same].sum() - adj[same].sum()) <= 1e-3 * abs(fd[same].sum()), (name, fd[same].sum(), adj[same].sum())
-        scale = np.abs(adj).sum()
-        assert abs(g_gpu[i] - (g64.dmu, g64.dxi)[i]) <= 1e-3 * scale, (name, g_gpu[i], (g64.dmu, g64.dxi)[i], scale)
+        # the whole loss, jumps included, at steps of 1e-3 of the parameter
+        h = 1e-3 * p0[name]
+        L = [float((gD_np.astype(np.float64) *
+                    oracle.smooth_forward(c.dem, c.mask, c.cell_size, oracle.make_params(**dict(p0, **{name: p0[name] + sgn * h})),
+                                          P, S, seed, mass=c.mass, prec="f64").dep).sum()) for sgn in (1, -1)]
+        fd_whole = (L[0] - L[1]) / (2 * h)
+        jump = (fd_whole - g64_tot[i]) / fd_whole
+        print(f"dL/d{name}: whole-loss central difference {fd_whole:.9g}, pathwise {g64_tot[i]:.9g}, jump part {jump:.2%}")
+        assert abs(jump) <= 0.03, (name, jump)
