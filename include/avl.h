@@ -135,6 +135,50 @@ AVL_API int avl_trajectories_noalloc(const float* dem, const uint8_t* mask, int3
                                      void* stream);
 AVL_API size_t avl_noalloc_scratch_bytes(void);
 
+/* Debug paths (diagnostics: localising a difference from the model to one particle and one step, and the
+ * real access pattern of a pass for the memory microbenchmarks): avl_trajectories with the paths of the
+ * particles first .. first + n_rec - 1 recorded, particle k of the run being replica k % P of the k / P-th
+ * release texel in row-major order. The pass runs the trajectory kernel's recording instantiation, whose
+ * arithmetic is that of every other instantiation, so counts, vmax and stats are avl_trajectories' results.
+ * ends (n_rec uint32, required): (accepted steps << 2) | end, end 0 = step limit, 1 = left the grid, 2 =
+ *   stopped (energy line or runout angle); 0xFFFFFFFF for a k past the run's last particle.
+ * points (nullable, float pairs (x, y) in cell units): point 0 is the release point, point m the position
+ *   after the m-th accepted step, and a stopped particle's last point (m = steps + 1) the target of the
+ *   step that stopped it. Particle k - first's point m goes to points[2 (offsets[k - first] + m)] when
+ *   offsets (n_rec uint64) is given (the caller sizes each run of points from an earlier call's ends:
+ *   steps + 1, plus 1 for a stop), else to points[2 ((k - first) stride + m)] for m < stride only.
+ * speeds2 (nullable, needs points): v^2 at each point (0 at the release point and at a stop's target).
+ * Other arguments, limits and errors as avl_trajectories; AVL_EINVAL also for n_rec = 0, no ends, or points
+ * with neither offsets nor a stride >= 1. Every array is device memory. */
+AVL_API int avl_trajectories_record(const float* dem, const uint8_t* mask, int32_t H, int32_t W, float cell_size,
+                                    const avl_params* params, uint32_t particles_per_cell, uint32_t step_limit,
+                                    uint64_t seed, uint32_t run_id, uint64_t first, uint32_t n_rec,
+                                    const uint64_t* offsets, uint32_t stride, float* points, float* speeds2,
+                                    uint32_t* ends, uint32_t* counts, float* vmax, uint64_t* stats, void* workspace,
+                                    size_t workspace_bytes, void* stream);
+
+/* ---- Memory microbenchmarks (measurement: the ceilings of the trajectory node's memory traffic on this
+ * chip, for a pass's own access stream). They replay the output of avl_trajectories_record's two calls
+ * (ends, then points with the offsets sized from them; speeds2 for the atomics), of the run on the same grid,
+ * over particles 0 .. n_particles - 1; the offsets must be those the points were written with. Nothing of the
+ * model is computed. With avl_set_profiling on, avl_last_kernel_ms gives the replay kernel's duration.
+ *
+ * avl_bench_gather: every 2 x 2 patch read of the pass (each accepted step's position and a stopped
+ *   particle's rejected target), as two 8-byte loads from a padded copy of dem (H*W floats), lanes taking
+ *   particles in slot order, 64 consecutive per wave; *checksum (device u32) gets the XOR of the bits of
+ *   every texel read. workspace: avl_workspace_bytes(H, W).
+ * avl_bench_atomics: the raster accumulation without aggregation: a device-scope u32 add per cell entry and
+ *   a u32 max of the v^2 bits per cell left; counts and vmax2_bits (H*W u32 each, overwritten) end equal to
+ *   the pass's counts and the bits of its v^2 maxima. workspace: at least 512 bytes.
+ * avl_bench_stream: copies `bytes` (a multiple of 16; 16-byte aligned pointers) from src to dst. */
+AVL_API int avl_bench_gather(const float* dem, int32_t H, int32_t W, const float* points, const uint64_t* offsets,
+                             const uint32_t* ends, uint64_t n_particles, uint32_t* checksum, void* workspace,
+                             size_t workspace_bytes, void* stream);
+AVL_API int avl_bench_atomics(int32_t H, int32_t W, const float* points, const float* speeds2, const uint64_t* offsets,
+                              const uint32_t* ends, uint64_t n_particles, uint32_t* counts, uint32_t* vmax2_bits,
+                              void* workspace, size_t workspace_bytes, void* stream);
+AVL_API int avl_bench_stream(const void* src, void* dst, size_t bytes, void* stream);
+
 /* Release texture at a finer resolution than the DEM (section 5.2: the user picks the texture resolution
  * at which release points are evaluated; a known release area, as for the historic event of figure 1, can
  * be handed in as a texture of its own). The texture has mult x mult texels per DEM cell, row-major,

@@ -78,6 +78,15 @@ def _load() -> ctypes.CDLL:
                                    vp, sz, vp]
     L.avl_trajectories_noalloc.argtypes = [vp, vp, i32, i32, f32, ctypes.POINTER(Params), u32, u32, u64, u32, vp,
                                            vp, vp, vp]
+    L.avl_trajectories_record.argtypes = [vp, vp, i32, i32, f32, ctypes.POINTER(Params), u32, u32, u64, u32, u64, u32,
+                                          vp, u32, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    L.avl_trajectories_record.restype = ctypes.c_int
+    L.avl_bench_gather.argtypes = [vp, i32, i32, vp, vp, vp, u64, vp, vp, sz, vp]
+    L.avl_bench_gather.restype = ctypes.c_int
+    L.avl_bench_atomics.argtypes = [i32, i32, vp, vp, vp, vp, u64, vp, vp, vp, sz, vp]
+    L.avl_bench_atomics.restype = ctypes.c_int
+    L.avl_bench_stream.argtypes = [vp, vp, sz, vp]
+    L.avl_bench_stream.restype = ctypes.c_int
     L.avl_noalloc_scratch_bytes.argtypes = []
     L.avl_noalloc_scratch_bytes.restype = sz
     L.avl_snow_cover.argtypes = [vp, vp, i32, i32, f32, f32, f32, f32, vp, vp]
@@ -310,6 +319,102 @@ def trajectories_noalloc(dem: torch.Tensor, mask: torch.Tensor, cell_size: float
                                             out.counts.data_ptr(), out.vmax.data_ptr(), out.stats.data_ptr(),
                                             _stream(dem.device)), "avl_trajectories_noalloc")
     return out
+
+
+@dataclass
+class Paths:
+    ends: torch.Tensor            # (n,) uint32: (accepted steps << 2) | end (0 limit, 1 exit, 2 stop); ~0 = none
+    points: torch.Tensor | None   # (total, 2) float32 (x, y) in cell units, particle by particle
+    speeds2: torch.Tensor | None  # (total,) float32 v^2 at each point
+    offsets: torch.Tensor | None  # (n + 1,) int64: particle j's points are points[offsets[j]:offsets[j + 1]]
+    run: RunResult
+
+
+def _record_call(dem, mask, cell_size, params, P, S, seed, run_id, first, n, offsets, stride, points, speeds2, ends,
+                 out):
+    h, w = dem.shape
+    nb = workspace_bytes(h, w)
+    with torch.cuda.device(dem.device):
+        ws = _workspace(dem.device, nb)
+        _check(lib.avl_trajectories_record(dem.data_ptr(), mask.data_ptr(), h, w, cell_size, ctypes.byref(params), P, S,
+                                           seed & (2**64 - 1), run_id, first, n,
+                                           offsets.data_ptr() if offsets is not None else None, stride,
+                                           points.data_ptr() if points is not None else None,
+                                           speeds2.data_ptr() if speeds2 is not None else None, ends.data_ptr(),
+                                           out.counts.data_ptr(), out.vmax.data_ptr(), out.stats.data_ptr(),
+                                           ws.data_ptr(), ws.numel(), _stream(dem.device)), "avl_trajectories_record")
+
+
+def trajectory_paths(dem: torch.Tensor, mask: torch.Tensor, cell_size: float, params: Params, particles_per_cell: int,
+                     step_limit: int, seed: int, run_id: int = 0, first: int = 0, n: int | None = None,
+                     points: bool = True, speeds: bool = True) -> Paths:
+    """Debug paths of particles [first, first + n) of a pass (n = None: to the last particle): one recording
+    pass for the end records, then (points=True) a second one that writes every particle's points into a
+    packed array sized from them. The rasters of the pass come with it."""
+    _need(dem, "dem", torch.float32, 2)
+    _need(mask, "mask", torch.uint8, 2)
+    h, w = dem.shape
+    if mask.shape != (h, w):
+        raise ValueError("mask must have the DEM's shape")
+    dev = dem.device
+    if n is None:
+        n = max(0, int(mask.count_nonzero().item()) * particles_per_cell - first)
+    if n <= 0:
+        raise ValueError("no particle in the recorded range")
+    out = RunResult(torch.empty((h, w), dtype=torch.uint32, device=dev),
+                    torch.empty((h, w), dtype=torch.float32, device=dev), torch.empty(4, dtype=torch.uint64, device=dev))
+    ends = torch.empty(n, dtype=torch.uint32, device=dev)
+    _record_call(dem, mask, cell_size, params, particles_per_cell, step_limit, seed, run_id, first, n, None, 0, None,
+                 None, ends, out)
+    if not points:
+        return Paths(ends, None, None, None, out)
+    e = ends.view(torch.int32).to(torch.int64) & 0xFFFFFFFF
+    valid = e != 0xFFFFFFFF
+    npts = torch.where(valid, (e >> 2) + 1 + ((e & 3) == 2).to(torch.int64), torch.zeros_like(e))
+    offsets = torch.zeros(n + 1, dtype=torch.int64, device=dev)
+    offsets[1:] = torch.cumsum(npts, 0)
+    total = int(offsets[-1].item())
+    pts = torch.empty((max(total, 1), 2), dtype=torch.float32, device=dev)
+    sp = torch.empty(max(total, 1), dtype=torch.float32, device=dev) if speeds else None
+    _record_call(dem, mask, cell_size, params, particles_per_cell, step_limit, seed, run_id, first, n, offsets, 0, pts,
+                 sp, ends, out)
+    return Paths(ends, pts[:total], sp[:total] if sp is not None else None, offsets, out)
+
+
+def bench_gather(dem: torch.Tensor, paths: Paths) -> torch.Tensor:
+    """Replay of the gathers of a recorded pass (memory microbenchmark); returns the device checksum."""
+    _need(dem, "dem", torch.float32, 2)
+    h, w = dem.shape
+    chk = torch.empty(1, dtype=torch.uint32, device=dem.device)
+    with torch.cuda.device(dem.device):
+        ws = _workspace(dem.device, workspace_bytes(h, w))
+        _check(lib.avl_bench_gather(dem.data_ptr(), h, w, paths.points.data_ptr(), paths.offsets.data_ptr(),
+                                    paths.ends.data_ptr(), paths.ends.numel(), chk.data_ptr(), ws.data_ptr(),
+                                    ws.numel(), _stream(dem.device)), "avl_bench_gather")
+    return chk
+
+
+def bench_atomics(shape, paths: Paths, out: tuple | None = None) -> tuple[torch.Tensor, torch.Tensor]:
+    """Replay of the raster atomics of a recorded pass without aggregation: (counts, v^2 max bits)."""
+    h, w = shape
+    dev = paths.points.device
+    counts, bits = out if out is not None else (torch.empty((h, w), dtype=torch.uint32, device=dev),
+                                                torch.empty((h, w), dtype=torch.uint32, device=dev))
+    with torch.cuda.device(dev):
+        ws = _workspace(dev, 512)
+        _check(lib.avl_bench_atomics(h, w, paths.points.data_ptr(), paths.speeds2.data_ptr(), paths.offsets.data_ptr(),
+                                     paths.ends.data_ptr(), paths.ends.numel(), counts.data_ptr(), bits.data_ptr(),
+                                     ws.data_ptr(), ws.numel(), _stream(dev)), "avl_bench_atomics")
+    return counts, bits
+
+
+def bench_stream(src: torch.Tensor, dst: torch.Tensor) -> None:
+    """Device copy of src into dst (same byte size, a multiple of 16): the HBM stream microbenchmark."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("src and dst must have the same size")
+    with torch.cuda.device(src.device):
+        _check(lib.avl_bench_stream(src.data_ptr(), dst.data_ptr(), nbytes, _stream(src.device)), "avl_bench_stream")
 
 
 def snow_cover(nrm: torch.Tensor, dem: torch.Tensor, snow_line: float, alt_blend: float, max_slope_deg: float,

@@ -11,7 +11,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = ["csrc/api.hip", "csrc/terrain.hip", "csrc/trajectories.hip", "csrc/smooth.hip"]
+SOURCES = ["csrc/api.hip", "csrc/terrain.hip", "csrc/trajectories.hip", "csrc/smooth.hip", "csrc/membench.hip"]
 LIB = os.path.join(HERE, "libavl.so")
 ARCH = os.environ.get("AVL_OFFLOAD_ARCH", "gfx950")
 

@@ -148,19 +148,25 @@ bool g_profile = false;
 bool g_profile_valid = false;
 hipEvent_t g_prof_ev[2] = {nullptr, nullptr};
 
-// Launches the trajectory kernel, bracketed by the timing events when profiling is on and the stream
-// is not being captured.
-hipError_t timed_launch(const avl::TrajArgs& a, bool batched, const avl::LaunchShape& sh, hipStream_t s) {
+// Enqueues `launch` (one kernel), bracketed by the timing events when profiling is on and the stream is
+// not being captured.
+template <class Launch>
+hipError_t timed(hipStream_t s, Launch launch) {
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-    const bool timed = g_profile && hipStreamIsCapturing(s, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone;
+    const bool on = g_profile && hipStreamIsCapturing(s, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone;
     hipError_t e;
-    if (timed && (e = hipEventRecord(g_prof_ev[0], s)) != hipSuccess) return e;
-    if ((e = avl::launch_trajectories(a, batched, sh, s)) != hipSuccess) return e;
-    if (timed) {
+    if (on && (e = hipEventRecord(g_prof_ev[0], s)) != hipSuccess) return e;
+    if ((e = launch()) != hipSuccess) return e;
+    if (on) {
         if ((e = hipEventRecord(g_prof_ev[1], s)) != hipSuccess) return e;
         g_profile_valid = true;
     }
     return hipSuccess;
+}
+
+// The trajectory kernel, timed as above.
+hipError_t timed_launch(const avl::TrajArgs& a, bool batched, const avl::LaunchShape& sh, hipStream_t s) {
+    return timed(s, [&] { return avl::launch_trajectories(a, batched, sh, s); });
 }
 
 __attribute__((format(printf, 2, 3))) int fail(int code, const char* fmt, ...) {
@@ -481,13 +487,23 @@ hipError_t scratch_address(void** out) {
     return hipSuccess;
 }
 
+// Path recording of a pass (avl_trajectories_record).
+struct Record {
+    uint64_t first;
+    uint32_t n, stride;
+    const uint64_t* offsets;
+    float* points;
+    float* speeds2;
+    uint32_t* ends;
+};
+
 // One trajectory pass from a release texture with mult x mult texels per DEM cell (mask: mult*H x mult*W).
 // noalloc: ignore workspace / workspace_bytes and run in the current device's `scratch` (no allocation,
-// no event creation, no tuning).
+// no event creation, no tuning). rec: run the recording instantiation instead of the tuned variants.
 int single_pass(const char* where, const float* dem, const uint8_t* mask, int32_t H, int32_t W, int32_t mult,
                 float cell_size, const avl_params* params, uint32_t particles_per_cell, uint32_t step_limit,
                 uint64_t seed, uint32_t run_id, uint32_t* counts, float* vmax, uint64_t* stats, void* workspace,
-                size_t workspace_bytes, void* stream, bool noalloc = false) {
+                size_t workspace_bytes, void* stream, bool noalloc = false, const Record* rec = nullptr) {
     if (!dem || !mask || !counts || !vmax || (!noalloc && !workspace))
         return fail(AVL_EINVAL, "%s: null pointer", where);
     if (!grid_ok(H, W, 1) || avl::padded_cells(H, W) >= (int64_t(1) << 30))
@@ -558,6 +574,22 @@ int single_pass(const char* where, const float* dem, const uint8_t* mask, int32_
     if ((e = avl::launch_setup_runs(nullptr, nullptr, 0, spec, *params, ws.n_cells, 1, 1, 1, H, W, cell_size,
                                     particles_per_cell, false, ws.runs, ws.run_off, nullptr, s)) != hipSuccess)
         return hip_fail(e, (std::string(where) + ": run setup").c_str());
+    if (rec) {
+        a.rec_first = rec->first;
+        a.rec_n = rec->n;
+        a.rec_stride = rec->stride;
+        a.rec_off = reinterpret_cast<const unsigned long long*>(rec->offsets);
+        a.rec_xy = reinterpret_cast<float2*>(rec->points);
+        a.rec_v2 = rec->speeds2;
+        a.rec_end = rec->ends;
+        if ((e = zero()) != hipSuccess || (e = avl::launch_fill_u32(rec->ends, ~0u, rec->n, s)) != hipSuccess)
+            return hip_fail(e, (std::string(where) + ": zero").c_str());
+        if ((e = timed(s, [&] { return avl::launch_trajectories_record(a, s); })) != hipSuccess)
+            return hip_fail(e, (std::string(where) + ": launch").c_str());
+        if ((e = avl::launch_finalize_vmax(a.vmax2, n, s)) != hipSuccess)
+            return hip_fail(e, (std::string(where) + ": finalize").c_str());
+        return AVL_OK;
+    }
     int variant = 0;
     if ((e = choose_variant(a, false, tune_key(false, nf, 1, particles_per_cell, step_limit), s, zero, &variant,
                             !noalloc)) != hipSuccess)
@@ -592,6 +624,83 @@ int avl_trajectories_noalloc(const float* dem, const uint8_t* mask, int32_t H, i
 }
 
 size_t avl_noalloc_scratch_bytes(void) { return kScratchBytes; }
+
+int avl_trajectories_record(const float* dem, const uint8_t* mask, int32_t H, int32_t W, float cell_size,
+                            const avl_params* params, uint32_t particles_per_cell, uint32_t step_limit, uint64_t seed,
+                            uint32_t run_id, uint64_t first, uint32_t n_rec, const uint64_t* offsets, uint32_t stride,
+                            float* points, float* speeds2, uint32_t* ends, uint32_t* counts, float* vmax,
+                            uint64_t* stats, void* workspace, size_t workspace_bytes, void* stream) {
+    g_last_error.clear();
+    if (n_rec == 0 || !ends) return fail(AVL_EINVAL, "avl_trajectories_record: need n_rec >= 1 and ends");
+    if (first > ~0ull - n_rec) return fail(AVL_EINVAL, "avl_trajectories_record: first + n_rec overflows");
+    if (speeds2 && !points) return fail(AVL_EINVAL, "avl_trajectories_record: speeds2 needs points");
+    if (points && !offsets && stride == 0)
+        return fail(AVL_EINVAL, "avl_trajectories_record: points need offsets or a stride >= 1");
+    if (points && !offsets && (uint64_t)n_rec * stride >= (uint64_t(1) << 40))
+        return fail(AVL_EINVAL, "avl_trajectories_record: n_rec * stride must be < 2^40");
+    const Record rec{first, n_rec, stride, offsets, points, speeds2, ends};
+    return single_pass("avl_trajectories_record", dem, mask, H, W, 1, cell_size, params, particles_per_cell,
+                       step_limit, seed, run_id, counts, vmax, stats, workspace, workspace_bytes, stream, false, &rec);
+}
+
+int avl_bench_gather(const float* dem, int32_t H, int32_t W, const float* points, const uint64_t* offsets,
+                     const uint32_t* ends, uint64_t n_particles, uint32_t* checksum, void* workspace,
+                     size_t workspace_bytes, void* stream) {
+    g_last_error.clear();
+    if (!dem || !points || !offsets || !ends || !checksum || !workspace)
+        return fail(AVL_EINVAL, "avl_bench_gather: null pointer");
+    if (!grid_ok(H, W, 1) || avl::padded_cells(H, W) >= (int64_t(1) << 30) || H >= (1 << 23) || W >= (1 << 23))
+        return fail(AVL_EINVAL, "avl_bench_gather: need H, W >= 1, H, W < 2^23 and (H + 2)(W + 2) < 2^30");
+    if (workspace_bytes < avl::workspace_bytes(H, W)) return fail(AVL_ENOMEM, "avl_bench_gather: workspace too small");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    avl::Workspace ws = avl::carve(workspace, H, W);
+    hipError_t e;
+    if ((e = avl::launch_pad_dem(dem, H, W, ws.dem_pad, s)) != hipSuccess ||
+        (e = avl::launch_fill_u64(ws.queues, 0ull, avl::kXcds, s)) != hipSuccess ||
+        (e = avl::launch_fill_u32(checksum, 0u, 1, s)) != hipSuccess)
+        return hip_fail(e, "avl_bench_gather: set-up");
+    const uint32_t pad_bytes = (uint32_t)(avl::padded_cells(H, W) * sizeof(float));
+    e = timed(s, [&] {
+        return avl::launch_replay_gather(reinterpret_cast<const float2*>(points),
+                                         reinterpret_cast<const unsigned long long*>(offsets), ends, n_particles,
+                                         ws.dem_pad, pad_bytes, W, ws.queues, checksum, s);
+    });
+    return e == hipSuccess ? AVL_OK : hip_fail(e, "avl_bench_gather: launch");
+}
+
+int avl_bench_atomics(int32_t H, int32_t W, const float* points, const float* speeds2, const uint64_t* offsets,
+                      const uint32_t* ends, uint64_t n_particles, uint32_t* counts, uint32_t* vmax2_bits,
+                      void* workspace, size_t workspace_bytes, void* stream) {
+    g_last_error.clear();
+    if (!points || !speeds2 || !offsets || !ends || !counts || !vmax2_bits || !workspace)
+        return fail(AVL_EINVAL, "avl_bench_atomics: null pointer");
+    if (!grid_ok(H, W, 1)) return fail(AVL_EINVAL, "avl_bench_atomics: need H, W >= 1 and H*W < 2^31");
+    if (workspace_bytes < avl::kControl) return fail(AVL_ENOMEM, "avl_bench_atomics: workspace too small");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    auto* queues = reinterpret_cast<unsigned long long*>(static_cast<char*>(workspace) + 128);
+    const int64_t n = (int64_t)H * W;
+    hipError_t e;
+    if ((e = avl::launch_fill_u32(counts, 0u, n, s)) != hipSuccess ||
+        (e = avl::launch_fill_u32(vmax2_bits, 0u, n, s)) != hipSuccess ||
+        (e = avl::launch_fill_u64(queues, 0ull, avl::kXcds, s)) != hipSuccess)
+        return hip_fail(e, "avl_bench_atomics: set-up");
+    e = timed(s, [&] {
+        return avl::launch_replay_atomics(reinterpret_cast<const float2*>(points), speeds2,
+                                          reinterpret_cast<const unsigned long long*>(offsets), ends, n_particles, W,
+                                          queues, counts, vmax2_bits, s);
+    });
+    return e == hipSuccess ? AVL_OK : hip_fail(e, "avl_bench_atomics: launch");
+}
+
+int avl_bench_stream(const void* src, void* dst, size_t bytes, void* stream) {
+    g_last_error.clear();
+    if (!src || !dst) return fail(AVL_EINVAL, "avl_bench_stream: null pointer");
+    if (bytes % 16 || (reinterpret_cast<uintptr_t>(src) & 15) || (reinterpret_cast<uintptr_t>(dst) & 15))
+        return fail(AVL_EINVAL, "avl_bench_stream: bytes and both pointers must be multiples of 16");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = timed(s, [&] { return avl::launch_stream_copy(src, dst, bytes / 16, s); });
+    return e == hipSuccess ? AVL_OK : hip_fail(e, "avl_bench_stream");
+}
 
 int avl_snow_cover(const float* normals4, const float* dem, int32_t H, int32_t W, float snow_line, float alt_blend,
                    float max_slope_deg, float slope_blend_deg, float* alpha, void* stream) {

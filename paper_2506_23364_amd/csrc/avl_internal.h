@@ -119,6 +119,17 @@ struct TrajArgs {
     uint32_t runout_angle;                       // single run: 1 if it uses the runout-angle stop (selects the
                                                  // kernel instantiation; a batch always has the stop compiled in)
     DivU32 wdiv;                                 // division by W (a batch's release cell -> row, column)
+    // path recording (single run, the recording instantiation only): particles [rec_first, rec_first +
+    // rec_n) of the run write their end record and, with rec_xy, their points (the release point, the
+    // position after every accepted step, and an energy or runout-angle stop's rejected target)
+    unsigned long long rec_first;
+    uint32_t rec_n;
+    uint32_t rec_stride;                         // points per particle without rec_off
+    const unsigned long long* __restrict__ rec_off;  // nullable: first point of each recorded particle
+    float2* __restrict__ rec_xy;                 // nullable: the points
+    float* __restrict__ rec_v2;                  // nullable: v^2 at each point (0 at the release point and
+                                                 // at a rejected target)
+    uint32_t* __restrict__ rec_end;              // (accepted steps << 2) | end (0 limit, 1 exit, 2 stop)
 };
 
 struct LaunchShape {
@@ -174,6 +185,17 @@ hipError_t launch_batch_records(const RunSpec* specs, const int32_t* rec_run, co
                                 uint32_t n_scen, const int32_t* cells, const float* dem_pad, int32_t H, int32_t W,
                                 StartRec* starts, hipStream_t s);
 hipError_t launch_trajectories(const TrajArgs& a, bool batched, const LaunchShape& shape, hipStream_t s);
+// The recording instantiation (single run, variant 0's shape, runout-angle stop compiled in).
+hipError_t launch_trajectories_record(const TrajArgs& a, hipStream_t s);
+
+// Memory microbenchmarks (membench.hip): replays of a recorded pass's gathers and raster atomics, and a copy.
+hipError_t launch_replay_gather(const float2* pts, const unsigned long long* off, const uint32_t* ends, uint64_t n,
+                                const float* dem_pad, uint32_t pad_bytes, int W, unsigned long long* queues,
+                                uint32_t* checksum, hipStream_t s);
+hipError_t launch_replay_atomics(const float2* pts, const float* v2s, const unsigned long long* off,
+                                 const uint32_t* ends, uint64_t n, int W, unsigned long long* queues, uint32_t* counts,
+                                 uint32_t* vmax2, hipStream_t s);
+hipError_t launch_stream_copy(const void* src, void* dst, uint64_t n16, hipStream_t s);
 
 // Smooth forward and adjoint (smooth.hip)
 struct SmoothArgs {

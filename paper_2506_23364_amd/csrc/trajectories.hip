@@ -81,9 +81,13 @@ struct Control {
 // release cell when a run uses the stop, so its kernel carries no registers for them.
 // kKeep: table retention, 0 off; else a slot whose cell was entered at least kKeep times in the epoch
 // that ended stays in the table (its count and maximum reach the rasters at a later boundary).
-template <bool kBatch, bool kAlpha, int kBlock, int kFlush, int kTbl, int kProbes, int kWindow, int kKeep>
+// kRec: the recording instantiation (single run): the particles of the recorded range also write their
+// points and end records (a diagnostic; the other instantiations compile none of it).
+template <bool kBatch, bool kAlpha, int kBlock, int kFlush, int kTbl, int kProbes, int kWindow, int kKeep,
+          bool kRec = false>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8)))
 void k_trajectories(TrajArgs a) {
+    static_assert(!(kRec && kBatch), "recording is for single runs");
     static_assert(kFlush % 2 == 0, "epochs keep the iteration parity");
     // a lane enters a given cell at most once per iteration, so a slot gains at most kBlock * kFlush
     // entries per epoch; a retained count stays below kKeepCap, so the low half never carries
@@ -230,6 +234,26 @@ void k_trajectories(TrajArgs a) {
     float x = 0, y = 0, z = 0, gx = 0, gy = 0, dx = 0, dy = 0, v2 = 0, x0 = 0, y0 = 0, zr = 0, cmax2 = 0;
     uint32_t n = 0, rep = 0, cell_id = 0, spare_x = 0, spare_y = 0, cur = 0;
     int my_slot = -1;  // table slot of the current cell in this epoch, -1 if none
+    uint32_t rk = ~0u;  // recording: index of the lane's particle in the recorded range, ~0 if outside it
+    auto rec_point = [&](uint32_t m, float px, float py, float pv2) {
+        if constexpr (kRec) {
+            if (rk == ~0u || !a.rec_xy) return;
+            unsigned long long at;
+            if (a.rec_off) {
+                at = a.rec_off[rk] + m;
+            } else {
+                if (m >= a.rec_stride) return;
+                at = (unsigned long long)rk * a.rec_stride + m;
+            }
+            a.rec_xy[at] = make_float2(px, py);
+            if (a.rec_v2) a.rec_v2[at] = pv2;
+        }
+    };
+    auto rec_end = [&](uint32_t why) {
+        if constexpr (kRec) {
+            if (rk != ~0u) a.rec_end[rk] = (n << 2) | why;
+        }
+    };
 
     auto count_entry = [&](bool e) {
         if (!e) return;
@@ -379,6 +403,11 @@ void k_trajectories(TrajArgs a) {
                     cur = rc.raster_off +
                           (kBatch ? cell_id : (uint32_t)(int)floorf(y) * (uint32_t)W + (uint32_t)(int)floorf(x));
                     alive = true;
+                    if constexpr (kRec) {
+                        const uint64_t k = (uint64_t)i * rc.P + rep;  // the particle's index in the run
+                        rk = (k >= a.rec_first && k - a.rec_first < a.rec_n) ? (uint32_t)(k - a.rec_first) : ~0u;
+                        rec_point(0u, x, y, 0.0f);
+                    }
                 }
             }
             count_entry(fresh);  // entry into the release cell
@@ -394,6 +423,7 @@ void k_trajectories(TrajArgs a) {
                 if (n >= a.S) {
                     ++st_limit;
                     ended = true;
+                    rec_end(0u);
                 } else {
                     ++st_steps;
                     uint32_t ux, uy;
@@ -430,6 +460,7 @@ void k_trajectories(TrajArgs a) {
                     if (!(fc1 >= 0.0f && fc1 < fW && fr1 >= 0.0f && fr1 < fH)) {
                         ++st_exit;
                         ended = true;
+                        rec_end(1u);
                     } else {
                         const Sample s1 = bilinear_pad(dem_rs, Wp, row_bytes, x1, y1);
                         const float dz = z - s1.z;
@@ -454,6 +485,8 @@ void k_trajectories(TrajArgs a) {
                         if (stop) {
                             ++st_stop;
                             ended = true;
+                            rec_point(n + 1u, x1, y1, 0.0f);
+                            rec_end(2u);
                         } else {
                             x = x1;
                             y = y1;
@@ -462,6 +495,7 @@ void k_trajectories(TrajArgs a) {
                             gy = s1.gy;
                             v2 = v2n;
                             ++n;
+                            rec_point(n, x, y, v2);
                             const uint32_t nc =
                                 R.raster_off + (uint32_t)(int)fr1 * (uint32_t)W + (uint32_t)(int)fc1;
                             if (nc != cur) {
@@ -758,6 +792,22 @@ LaunchShape trajectory_shape(bool batched, int variant) {
         per_cu = 1;
     sh.grid = cus * per_cu;
     return sh;
+}
+
+hipError_t launch_trajectories_record(const TrajArgs& a, hipStream_t s) {
+    auto* k = &k_trajectories<false, true, 1024, 16, 6144, 4, 4, 1, true>;
+    int dev = 0, cus = 256, per_cu = 1;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0 &&
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k), 1024, 0) ==
+            hipSuccess &&
+        per_cu > 0) {
+    } else {
+        cus = 256;
+        per_cu = 1;
+    }
+    hipLaunchKernelGGL(k, dim3(cus * per_cu), dim3(1024), 0, s, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_trajectories(const TrajArgs& a, bool batched, const LaunchShape& shape, hipStream_t s) {

@@ -284,6 +284,7 @@ def test_grid_just_below_the_width_limit_passes_the_size_checks(L):
     assert rc == L.AVL_ENOMEM
 
 
+
 def _noalloc(L, **kw):
     a = dict(dem=FAKE, mask=FAKE, H=16, W=16, cs=10.0, params=L.Params.make(), P=4, S=10, seed=1, run=0,
              counts=FAKE, vmax=FAKE, stats=None, stream=None)
@@ -309,4 +310,25 @@ def test_noalloc_rejects_bad_arguments_before_touching_the_gpu(L, kw):
     if kw.get("params") == "bad_mu":
         kw["params"] = L.Params.make(mu=-1.0)
     assert _noalloc(L, **kw) == L.AVL_EINVAL
+    assert L.lib.avl_last_error()
+
+
+def _record(L, **kw):
+    a = dict(dem=FAKE, mask=FAKE, H=16, W=16, cs=10.0, params=L.Params.make(), P=4, S=10, seed=1, run=0, first=0,
+             n=8, offsets=None, stride=0, points=None, speeds=None, ends=FAKE, counts=FAKE, vmax=FAKE, stats=None,
+             ws=FAKE, wsb=L.workspace_bytes(16, 16), stream=None)
+    a.update(kw)
+    p = a["params"]
+    return L.lib.avl_trajectories_record(a["dem"], a["mask"], a["H"], a["W"], a["cs"], ctypes.byref(p) if p else None,
+                                         a["P"], a["S"], a["seed"], a["run"], a["first"], a["n"], a["offsets"],
+                                         a["stride"], a["points"], a["speeds"], a["ends"], a["counts"], a["vmax"],
+                                         a["stats"], a["ws"], a["wsb"], a["stream"])
+
+
+@pytest.mark.parametrize("kw", [
+    dict(n=0), dict(ends=None), dict(points=FAKE), dict(speeds=FAKE), dict(first=2**64 - 4, n=8),
+    dict(points=FAKE, stride=1 << 20, n=1 << 21), dict(dem=None), dict(P=0), dict(wsb=16), dict(H=3, W=1 << 24),
+])
+def test_record_rejects_bad_arguments(L, kw):
+    assert _record(L, **kw) in (L.AVL_EINVAL, L.AVL_ENOMEM)
     assert L.lib.avl_last_error()
