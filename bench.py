@@ -1,20 +1,26 @@
 #!/usr/bin/env python3
 """Benchmark of the avalanche-overlay hot path on one MI355X.
 
-One step = one pass of the whole path over the alpine tile (2048^2 ridged fBm DEM at 10 m, ~1e5
-release cells, 256 particles per cell, step limit 4000): normals -> release map -> release-cell list
--> particle trajectories -> raster finalize, with the DEM already resident in HBM. The metric is
-particle-steps per second (every step a particle enters counts once).
+One step = one pass of the whole path over the headline workload with its DEM already resident in HBM:
+normals -> release map -> release-cell list -> particle trajectories -> raster finalize. The headline is
+the large region (8192^2 ridged fBm DEM at 5 m, ~1.4e6 release cells x 64 particles, step limit 8000),
+the largest single-GPU workload; the tiny (256^2) and alpine (2048^2) workloads are timed as legs. The
+metric is particle-steps per second (every step a particle enters counts once).
 
-Prints one JSON line. Extra fields: the roofline of the dominant kernel (the trajectory kernel), the
-CPU oracle timed on a bounded sample of the same workload, and per-stage timings.
+Prints one JSON line. Besides the contract fields: the roofline of the dominant kernel (the trajectory
+kernel) against ceilings measured on this GPU by replaying the pass's own memory operations (its 2x2
+gathers; its raster atomics without aggregation; an HBM copy), legs for the other workloads, the overlay
+mipmap, snow cover, the fine release texture, batched ensembles against plain calls, gradients against
+the plain forward and the calibration loop; and, on the host, the CPU oracle: a bounded single-threaded
+sample, the full passes on all host threads (bit-exact check of the GPU rasters) and the FP32-vs-FP64
+error of every result.
 """
 from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
+import subprocess
 import sys
 import time
 
@@ -23,23 +29,20 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic work of one particle-step of the model, counted from its definition (one op per
-# add/sub/mul/div/sqrt/floor/compare/convert and per 32-bit integer mul/mulhi/xor/add/shift/clamp):
-# half a Philox4x32-10 block (50), the two uniforms (10), the direction blend (24), the move and grid
-# test (10), the bilinear sample with index clamps (25), the energy step (11), the cell bookkeeping (3).
-OPS_PER_STEP = 133
-# Vector ALU peak without packed FP32: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (one wave64 VALU
-# instruction per SIMD every 4 cycles) = 39.3e12 lane-ops/s; the 157.3 TFLOP/s fp32 figure counts an
-# FMA as 2 and packed issue as 2.
-ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
-# DEM gather (2x2 texels, 16 B) and the two 4-byte atomics per step; HBM3E peak 8 TB/s
+# 2x2 binary32 texels read per gather (one per accepted step or stop; the release point's patch comes from
+# the per-cell start records)
+GATHER_BYTES = 16
+# DEM gather and the two 4-byte raster updates of the model's accumulation, per particle-step
 BYTES_PER_STEP = 24
 HBM_PEAK_GBS = 8000.0
-# HBM traffic of the trajectory kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE runs, recorded with the
-# hash of the kernel sources it was measured on; reported only while the sources are unchanged.
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_trajectories_alpine_traffic.md")
+# Vector issue: 256 CUs x 4 SIMDs, one wave64 VALU instruction per SIMD every 4 cycles at 2.4 GHz
+# (= 39.3e12 lane-operations/s; the 157.3 TFLOP/s fp32 figure counts an FMA as 2 and packed issue as 2)
+VALU_WAVE_INSTS_PER_S = 256 * 4 * 2.4e9 / 4
+# rocprofv3 figures of the trajectory kernel (recorded with the hash of the kernel sources they were taken
+# on; used only while the sources are unchanged)
 KERNEL_SOURCES = ["paper_2506_23364_amd/csrc/trajectories.hip", "paper_2506_23364_amd/csrc/particle.h",
                   "paper_2506_23364_amd/csrc/avl_internal.h"]
+METRIC = "particle-steps/s forward + s per (mu,xi) gradient, batched vs plain, 1 MI355X"
 
 
 def kernel_source_hash() -> str:
@@ -51,22 +54,22 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def recorded_traffic(variant: int):
-    """Memory-side bytes per launch of kernel variant `variant` from the committed counter summary, or
-    None when the summary has no figure for it or was taken on other kernel sources."""
+def recorded(workload: str, key: str, variant: int):
+    """`key[variant]` from profiles/k_trajectories_<workload>_counters.md, or None when the summary has no
+    such figure or was taken on other kernel sources."""
     try:
-        text = open(TRAFFIC_FILE).read()
+        text = open(os.path.join(ROOT, "profiles", f"k_trajectories_{workload}_counters.md")).read()
     except OSError:
         return None
     vals = {}
     for line in text.splitlines():
-        if line.startswith("traffic_bytes_per_launch[") or line.startswith("source_sha256:"):
+        if ":" in line and (line.startswith(key + "[") or line.startswith("source_sha256:")):
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
-    key = f"traffic_bytes_per_launch[{variant}]"
-    if key not in vals or vals.get("source_sha256") != kernel_source_hash():
+    name = f"{key}[{variant}]"
+    if name not in vals or vals.get("source_sha256") != kernel_source_hash():
         return None
-    return float(vals[key])
+    return float(vals[name])
 
 
 def parse():
@@ -74,78 +77,196 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="alpine", choices=["tiny", "alpine", "large"])
+    ap.add_argument("--workload", default="large", choices=["tiny", "alpine", "large"])
     ap.add_argument("--variant", type=int, default=-1,
                     help="trajectory kernel variant (default -1: the library's autotuner chooses)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-procs", type=int, default=min(16, os.cpu_count() or 1),
-                    help="processes of the full-pass oracle run (0 to skip it)")
-    ap.add_argument("--cpu-stride", type=int, default=0, help="oracle sample: every n-th release cell (0 = auto)")
-    ap.add_argument("--no-batched", action="store_true", help="skip the ensemble (batched vs plain) leg")
-    ap.add_argument("--no-gradient", action="store_true", help="skip the calibration-gradient and calibration legs")
-    ap.add_argument("--main-only", action="store_true",
-                    help="only the timed passes: no mipmap, snow, fine-release, ensemble, gradient or CPU legs")
+    ap.add_argument("--cpu-threads", type=int, default=min(16, os.cpu_count() or 1),
+                    help="host threads of the full-pass oracle runs (0 to skip them)")
+    ap.add_argument("--main-only", action="store_true", help="only the timed passes of the headline workload")
+    ap.add_argument("--leg", default="", choices=["", "roofline", "workloads", "batched", "gradient", "calibration"],
+                    help="only this leg (after the headline passes); for counter runs")
     ap.add_argument("--copy-probe", action="store_true",
                     help="copy 256 MiB once first: a plain copy of known size that calibrates HBM byte counters")
     return ap.parse_args()
 
 
-def cpu_baseline(w, mask: np.ndarray, stride: int) -> dict:
-    """The FP32 oracle, single-threaded, on every `stride`-th release cell of the workload."""
-    import oracle
-    cells = np.flatnonzero(mask)
-    if stride <= 0:
-        stride = 2
-    sample = np.zeros(mask.size, np.uint8)
-    sample[cells[::stride]] = 1
-    sample = sample.reshape(mask.shape)
-    p = oracle.make_params(**w.params)
+# ------------------------------------------------------------------------------------------ GPU legs
+
+def make_inputs(torch, name):
+    import synth
+    w = synth.make_workload(name)
+    return w, torch.from_numpy(w.dem).cuda()
+
+
+def timed_passes(avl, torch, w, dem, steps: int, warmup: int) -> dict:
+    """`warmup` untimed passes, then `steps` passes with per-stage events and the kernel's own events, then
+    `steps` back-to-back passes for the throughput."""
+    params = avl.Params.make(**w.params)
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    state = {"res": None, "mask": None}
+
+    def step(timed: bool):
+        if timed:
+            ev[0].record(stream)
+        nrm = avl.normals(dem, w.cell_size)
+        mask = avl.release_mask(nrm, dem, w.slope_min_deg, w.slope_max_deg, w.z_min, w.z_max)
+        if timed:
+            ev[1].record(stream)
+        state["res"] = avl.trajectories(dem, mask, w.cell_size, params, w.particles_per_cell, w.step_limit, w.seed, 0,
+                                        state["res"])
+        if timed:
+            ev[2].record(stream)
+        state["mask"] = mask
+
+    for _ in range(max(warmup, 1)):
+        step(False)
+    torch.cuda.synchronize()
+    res = state["res"]
+    stats = res.stats.cpu().numpy().astype(np.int64)
+    steps_per_pass = int(stats[0])
+    t_terrain = t_traj = 0.0
+    kernel_ms = []
+    avl.set_profiling(True)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    res = oracle.trajectories(w.dem, sample, w.cell_size, p, w.particles_per_cell, w.step_limit, w.seed)
-    dt = time.perf_counter() - t0
-    model = ""
-    try:
-        with open("/proc/cpuinfo") as f:
-            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
-    except OSError:
-        pass
-    return {"value": res.steps / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle", "cpu": model,
-            "sample": f"1 in {stride} release cells ({int(sample.sum())} cells x {w.particles_per_cell} "
-                      f"particles, {res.steps} particle-steps, {dt:.1f} s, single-threaded FP32 C oracle)"}
+    for _ in range(steps):
+        step(True)
+        ev[2].synchronize()
+        t_terrain += ev[0].elapsed_time(ev[1])
+        t_traj += ev[1].elapsed_time(ev[2])
+        kernel_ms.append(avl.last_kernel_ms())
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    avl.set_profiling(False)
+    variant = avl.last_variant()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step(False)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    res = state["res"]
+    assert int(res.stats.cpu().numpy()[0]) == steps_per_pass, "particle-step count changed between passes"
+    n_release = int(state["mask"].sum().item())
+    h, wd = w.dem.shape
+    return {
+        "res": res, "mask": state["mask"], "steps_per_pass": steps_per_pass, "variant": variant,
+        "value": steps_per_pass * steps / elapsed, "ms_per_step": elapsed / steps * 1e3,
+        "kernel_ms": float(np.mean(kernel_ms)),
+        "config": {
+            "workload": f"{w.name}: {h}x{wd} ridged diamond-square fBm DEM at {w.cell_size:g} m, release "
+                        f"{w.slope_min_deg:g}-{w.slope_max_deg:g} deg above z={w.z_min:.1f} m "
+                        f"({n_release} cells), {w.particles_per_cell} particles/cell, step limit {w.step_limit}, "
+                        f"mu {w.params['mu']:g}, xi {w.params['xi']:g}, h {w.params['flow_height']:g}, "
+                        f"persistence {w.params['persistence']:g}, randomness {w.params['randomness']:g}"
+            if w.name != "tiny" else
+            f"tiny: {h}x{wd} DEM at {w.cell_size:g} m, 35-degree incline with a fillet into a flat runout plus 5 m "
+            f"fBm, release {w.slope_min_deg:g}-{w.slope_max_deg:g} deg above z={w.z_min:.1f} m ({n_release} cells), "
+            f"{w.particles_per_cell} particles/cell, step limit {w.step_limit}, mu {w.params['mu']:g}, "
+            f"xi {w.params['xi']:g}, h {w.params['flow_height']:g}",
+            "release_cells": n_release,
+            "particles": n_release * w.particles_per_cell,
+            "particle_steps_per_pass": steps_per_pass,
+            "mean_steps_per_particle": steps_per_pass / max(1, n_release * w.particles_per_cell),
+            "ends_exit_stop_limit": [int(v) for v in stats[1:]],
+        },
+        "timing": {
+            "ms_terrain_normals_mask": t_terrain / steps,
+            "ms_trajectories_call": t_traj / steps,
+            "ms_trajectory_kernel": float(np.mean(kernel_ms)),
+            "ms_trajectory_kernel_median": float(np.median(kernel_ms)),
+            "ms_per_step_synced": wall / steps * 1e3,
+        },
+    }
 
 
-def _oracle_part(args):
-    """One worker of the parallel oracle pass: the particles of a contiguous range of release cells."""
-    dem, mask_part, cell_size, params, P, S, seed = args
-    import oracle
-    r = oracle.trajectories(dem, mask_part, cell_size, oracle.make_params(**params), P, S, seed)
-    return r.counts, r.vmax, (r.steps, r.n_exit, r.n_stop, r.n_limit)
+def kernel_time_ms(avl, torch, fn, reps: int) -> float:
+    """Median over `reps` calls of the library's own events around the one kernel the call times."""
+    ms = []
+    avl.set_profiling(True)
+    for _ in range(reps):
+        fn()
+        ms.append(avl.last_kernel_ms())
+    avl.set_profiling(False)
+    torch.cuda.synchronize()
+    return float(np.median(ms))
 
 
-def cpu_parallel(w, mask: np.ndarray, procs: int, gpu_counts: np.ndarray, gpu_vmax: np.ndarray) -> dict:
-    """The whole pass on the oracle, run as `procs` processes over disjoint ranges of release cells and
-    merged exactly (counts add, speeds take the maximum): a full-size CPU time and a full-size check of the
-    GPU rasters."""
-    import multiprocessing as mp
-    cells = np.flatnonzero(mask)
-    parts = []
-    for chunk in np.array_split(cells, procs):
-        m = np.zeros(mask.size, np.uint8)
-        m[chunk] = 1
-        parts.append((w.dem, m.reshape(mask.shape), w.cell_size, w.params, w.particles_per_cell, w.step_limit,
-                      w.seed))
-    ctx = mp.get_context("spawn")  # fresh interpreters: the children never touch the GPU
-    with ctx.Pool(procs) as pool:
-        pool.map(_oracle_part, parts[:1])  # start-up and library load, untimed
-        t0 = time.perf_counter()
-        out = pool.map(_oracle_part, parts)
-        dt = time.perf_counter() - t0
-    counts = np.sum([o[0] for o in out], axis=0, dtype=np.uint64).astype(np.uint32)
-    vmax = np.max([o[1] for o in out], axis=0)
-    steps = sum(o[2][0] for o in out)
-    same = bool(np.array_equal(counts, gpu_counts) and np.array_equal(vmax, gpu_vmax))
-    return {"value": steps / dt, "unit": "particle-steps/s", "processes": procs, "seconds": dt,
-            "particle_steps": int(steps), "gpu_rasters_equal_oracle": same}
+def roofline_leg(avl, torch, w, dem, mask, run: dict, reps: int = 3) -> dict:
+    """Ceilings of the trajectory kernel measured on this GPU: the pass is recorded (every particle's points
+    and v^2), its 2x2 gathers and cell visits are laid out in wave order (64 neighbouring particles, step by
+    step) and replayed without the model's arithmetic or dependences, and an HBM copy is timed. Each ceiling
+    is the pass's work divided by the replay kernel's time."""
+    params = avl.Params.make(**w.params)
+    paths = avl.trajectory_paths(dem, mask, w.cell_size, params, w.particles_per_cell, w.step_limit, w.seed)
+    torch.cuda.synchronize()
+    same = bool(torch.equal(paths.run.counts.view(torch.int32), run["res"].counts.view(torch.int32))
+                and torch.equal(paths.run.vmax, run["res"].vmax))
+    ends = paths.ends.view(torch.int32).to(torch.int64) & 0xFFFFFFFF
+    valid = ends != 0xFFFFFFFF
+    stops = int(((ends & 3) == 2)[valid].sum().item())
+    accepted = int((ends[valid] >> 2).sum().item())
+    gathers = accepted + stops
+    sched = avl.bench_schedule(tuple(dem.shape), paths)
+    del paths
+    torch.cuda.empty_cache()
+    t_gather = kernel_time_ms(avl, torch, lambda: avl.bench_gather(dem, sched), reps)
+    out = (torch.empty_like(run["res"].counts), torch.empty_like(run["res"].counts))
+    t_atomic = kernel_time_ms(avl, torch, lambda: avl.bench_atomics(tuple(dem.shape), sched, out), reps)
+    counts_equal = bool(torch.equal(out[0].view(torch.int32), run["res"].counts.view(torch.int32)))
+    visits = int(sched.visits.shape[0])
+    assert gathers == int(sched.gathers.numel())
+    del sched, out
+    torch.cuda.empty_cache()
+    n_copy = 1 << 30
+    src = torch.empty(n_copy, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    t_copy = kernel_time_ms(avl, torch, lambda: avl.bench_stream(src, dst), reps)
+    del src, dst
+    torch.cuda.empty_cache()
+    steps = run["steps_per_pass"]
+    t_kernel = run["kernel_ms"]
+    variant = run["variant"]
+    gather_ceiling = steps / (t_gather * 1e-3)
+    atomic_ceiling = steps / (t_atomic * 1e-3)
+    achieved = steps / (t_kernel * 1e-3)
+    valu = recorded(w.name, "valu_wave_insts_per_launch", variant)
+    tcc_atomic = recorded(w.name, "tcc_atomic_per_launch", variant)
+    ceilings = {
+        "l2_gather": {"particle_steps_per_s": gather_ceiling, "replay_ms": t_gather, "gathers": gathers,
+                      "GBs": GATHER_BYTES * gathers / (t_gather * 1e-3) / 1e9},
+        "atomics_unaggregated": {"particle_steps_per_s": atomic_ceiling, "replay_ms": t_atomic,
+                                 "cell_visits": visits, "replay_counts_equal_pass": counts_equal,
+                                 "atomics_per_s_upper": 2 * visits / (t_atomic * 1e-3)},
+        "hbm_copy": {"GBs": 2 * n_copy / (t_copy * 1e-3) / 1e9, "bytes_read_and_written": 2 * n_copy,
+                     "ms": t_copy, "peak_GBs": HBM_PEAK_GBS},
+        "valu": None if valu is None else {
+            "particle_steps_per_s": VALU_WAVE_INSTS_PER_S * steps / valu,
+            "wave_insts_per_particle_step": valu / steps, "source": "rocprofv3 SQ_INSTS_VALU (profiles)"},
+    }
+    if tcc_atomic is not None:
+        # the kernel's own memory-side atomics at the replay's memory-side atomic rate (the replay issues one
+        # add and at most one max per visit: an upper estimate of its rate)
+        rate = 2.0 * visits / (t_atomic * 1e-3)
+        ceilings["atomics_as_issued"] = {"particle_steps_per_s": rate * steps / tcc_atomic,
+                                         "memory_side_atomics_per_launch": tcc_atomic,
+                                         "source": "rocprofv3 TCC_ATOMIC (profiles)"}
+    return {
+        "bound": "l2_gather", "kernel": "k_trajectories", "variant": variant,
+        "achieved": GATHER_BYTES * gathers / (t_kernel * 1e-3) / 1e9,
+        "peak": GATHER_BYTES * gathers / (t_gather * 1e-3) / 1e9,
+        "unit": "GB/s",
+        "frac": achieved / gather_ceiling,
+        "traffic": recorded(w.name, "traffic_bytes_per_launch", variant),
+        "achieved_particle_steps_per_s": achieved,
+        "kernel_ms": t_kernel,
+        "ceilings": ceilings,
+        "recorded_pass_equals_timed_pass": same,
+        "hbm_view": {"bytes_per_particle_step": BYTES_PER_STEP, "achieved_GBs": BYTES_PER_STEP * steps / t_kernel / 1e6,
+                     "peak_GBs": HBM_PEAK_GBS},
+    }
 
 
 def mipmap_leg(avl, torch, res, reps: int) -> dict:
@@ -186,10 +307,11 @@ def mipmap_leg(avl, torch, res, reps: int) -> dict:
             "peak_GBs": HBM_PEAK_GBS, "replay_equals_eager": bool(torch.equal(eager, vp))}
 
 
-def fine_leg(avl, torch, w, dem, reps: int, mult: int = 2, per_texel: int = 64) -> dict:
-    """The same tile and release rule evaluated on a release texture with mult x mult texels per DEM cell,
+def fine_leg(avl, torch, reps: int, mult: int = 2, per_texel: int = 64) -> dict:
+    """The alpine tile's release rule evaluated on a release texture with mult x mult texels per DEM cell,
     with per_texel particles per release texel (mult^2 * per_texel = the plain pass's particles per cell):
     the fine release map and the trajectory pass from it."""
+    w, dem = make_inputs(torch, "alpine")
     params = avl.Params.make(**w.params)
     nrm = avl.normals(dem, w.cell_size)
     stream = torch.cuda.current_stream()
@@ -214,16 +336,17 @@ def fine_leg(avl, torch, w, dem, reps: int, mult: int = 2, per_texel: int = 64) 
     fine_cells = h * wd * mult * mult
     map_bytes = 20 * h * wd + fine_cells  # normals and heights once, one byte per release texel
     kms = float(np.mean(kern_ms))
-    return {"mult": mult, "particles_per_texel": per_texel, "release_texels": texels,
+    return {"workload": "alpine tile, release texture of 2 x 2 texels per DEM cell", "mult": mult,
+            "particles_per_texel": per_texel, "release_texels": texels,
             "particles": texels * per_texel, "particle_steps_per_pass": steps,
             "ms_release_map": float(np.mean(map_ms)), "release_map_GBs": map_bytes / float(np.mean(map_ms)) / 1e6,
             "ms_trajectory_kernel": kms, "particle_steps_per_s": steps / (kms * 1e-3)}
 
 
 def snow_leg(avl, torch, w, dem, reps: int) -> dict:
-    """Snow-cover alpha of the tile (section 5.1) from its normals: an HBM stream of 24 bytes per texel."""
+    """Snow-cover alpha of the DEM (section 5.1) from its normals: an HBM stream of 24 bytes per texel."""
     nrm = avl.normals(dem, w.cell_size)
-    line = float(torch.quantile(dem.flatten()[::16], 0.6).item())
+    line = float(torch.quantile(dem.flatten()[::64], 0.6).item())
     stream = torch.cuda.current_stream()
     out = avl.snow_cover(nrm, dem, line, 200.0, 40.0, 8.0)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -292,7 +415,6 @@ def batched_leg(avl, torch, reps: int) -> dict:
         t_batch = (time.perf_counter() - t0) / reps
     steps = int(out.stats.cpu().numpy()[:, 0].sum())
     variant = avl.last_variant()
-    # the same runs as plain calls, each into its own slice of the output rasters
     plain = avl.BatchResult(torch.empty_like(out.counts), torch.empty_like(out.vmax), torch.empty_like(out.stats),
                             out.status)
     params = [avl.Params.make(**p) for p in e.params]
@@ -321,52 +443,233 @@ def batched_leg(avl, torch, reps: int) -> dict:
             "variant": variant, "batched_equals_plain": same}
 
 
-def gradient_leg(avl, torch, reps: int) -> dict:
-    """Calibration gradient: 1024^2 ridged fBm at 10 m, 5000 release cells x 128 particles, 3000 steps,
-    checkpoints every 64 steps; L = MSE(deposit(mu0, xi0), deposit(mu*, xi*)). Timed: smooth forward +
-    adjoint (s per gradient) against the plain forward of the same release on the same DEM."""
-    import synth
-    c = synth.make_calibration()
-    dem = torch.from_numpy(c.dem).cuda()
-    mask = torch.from_numpy(c.mask).cuda()
-    mass = torch.from_numpy(c.mass).cuda()
-    P, S, seed = c.particles_per_cell, c.step_limit, c.seed
-    n_cells = int(c.mask.sum())
-    p_star = avl.Params.make(mu=c.mu_star, xi=c.xi_star, flow_height=c.flow_height)
-    p0 = avl.Params.make(mu=c.mu0, xi=c.xi0, flow_height=c.flow_height)
-    target = avl.trajectories_smooth(dem, mask, c.cell_size, p_star, P, S, seed, mass=mass,
+def gradient_case(avl, torch, dem_np, mask_np, mass_np, cs, target_params, p0, P, S, seed, reps):
+    """s per (mu, xi) gradient (smooth forward + MSE gradient + adjoint) against the plain forward of the same
+    release; returns the timings, the GPU gradient and the raster gradient gD for the host checks."""
+    dem = torch.from_numpy(dem_np).cuda()
+    mask = torch.from_numpy(mask_np).cuda()
+    mass = torch.from_numpy(mass_np).cuda()
+    n_cells = int(mask_np.sum())
+    target = avl.trajectories_smooth(dem, mask, cs, avl.Params.make(**target_params), P, S, seed, mass=mass,
                                      max_release_cells=n_cells).deposit
+    pp = avl.Params.make(**p0)
 
     def grad_once():
-        run = avl.trajectories_smooth(dem, mask, c.cell_size, p0, P, S, seed, mass=mass, max_release_cells=n_cells)
+        run = avl.trajectories_smooth(dem, mask, cs, pp, P, S, seed, mass=mass, max_release_cells=n_cells)
         gD = (2.0 / run.deposit.numel()) * (run.deposit - target)
-        dparams, dmass, _ = avl.trajectories_backward(run, dem, mask, c.cell_size, p0, P, S, seed, gD, mass=mass)
-        return run, dparams, dmass
+        dparams, dmass, _ = avl.trajectories_backward(run, dem, mask, cs, pp, P, S, seed, gD, mass=mass)
+        return run, dparams, gD
 
-    run, dparams, _ = grad_once()
+    run, dparams, gD = grad_once()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(reps):
-        run, dparams, _ = grad_once()
+        run, dparams, gD = grad_once()
     torch.cuda.synchronize()
     t_grad = (time.perf_counter() - t0) / reps
     res = None
     for _ in range(2):
-        res = avl.trajectories(dem, mask, c.cell_size, p0, P, S, seed, 0, res)
+        res = avl.trajectories(dem, mask, cs, pp, P, S, seed, 0, res)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(reps):
-        res = avl.trajectories(dem, mask, c.cell_size, p0, P, S, seed, 0, res)
+        res = avl.trajectories(dem, mask, cs, pp, P, S, seed, 0, res)
     torch.cuda.synchronize()
     t_plain = (time.perf_counter() - t0) / reps
     g = dparams.cpu().numpy()
     steps = int(run.stats.cpu().numpy()[0])
-    return {"workload": "calibration: 1024^2 at 10 m, 5000 release cells x 128 particles, 3000 steps, "
-                        "checkpoints every 64 steps, MSE of the deposit against (mu*, xi*) = (0.22, 1800)",
-            "at": {"mu": c.mu0, "xi": c.xi0}, "dL_dmu": float(g[0]), "dL_dxi": float(g[1]), "dL_dh": float(g[2]),
-            "particle_steps": steps, "s_per_gradient": t_grad, "ms_plain_forward": t_plain * 1e3,
-            "gradient_over_plain_forward": t_grad / t_plain}
+    n_part = n_cells * P
+    return ({"dL_dmu": float(g[0]), "dL_dxi": float(g[1]), "dL_dh": float(g[2]), "particle_steps": steps,
+             "mean_steps_per_particle": steps / max(1, n_part), "checkpoint_segments_max": -(-S // 64),
+             "s_per_gradient": t_grad, "ms_plain_forward": t_plain * 1e3, "gradient_over_plain_forward": t_grad / t_plain},
+            g, gD.float().cpu().numpy())
 
+
+def gradient_leg(avl, torch, reps: int) -> tuple[dict, dict]:
+    """Calibration gradient (1024^2 at 10 m, 5000 release cells x 128 particles, 3000 steps, checkpoints every 64
+    steps; L = MSE(deposit(mu0, xi0), deposit(mu*, xi*))), and the same on the tiny workload's release, whose paths
+    run ~130 steps (several checkpoint segments): s per gradient against the plain forward."""
+    import oracle
+    import synth
+    c = synth.make_calibration()
+    base = dict(flow_height=c.flow_height)
+    out, g, gD = gradient_case(avl, torch, c.dem, c.mask, c.mass, c.cell_size, dict(base, mu=c.mu_star, xi=c.xi_star),
+                               dict(base, mu=c.mu0, xi=c.xi0), c.particles_per_cell, c.step_limit, c.seed, reps)
+    out["workload"] = ("calibration: 1024^2 at 10 m, 5000 release cells x 128 particles, 3000 steps, checkpoints every "
+                       "64 steps, MSE of the deposit against (mu*, xi*) = (0.22, 1800)")
+    out["at"] = {"mu": c.mu0, "xi": c.xi0}
+    w = synth.make_workload("tiny")
+    mask = oracle.release_mask(oracle.normals(w.dem, w.cell_size), w.dem, w.slope_min_deg, w.slope_max_deg, w.z_min,
+                               w.z_max)
+    tp = dict(w.params)
+    long_out, g_long, gD_long = gradient_case(
+        avl, torch, w.dem, mask, mask.astype(np.float32), w.cell_size, dict(tp, mu=0.22, xi=1800.0),
+        dict(tp, mu=w.params["mu"], xi=w.params["xi"]), w.particles_per_cell, w.step_limit, w.seed, reps)
+    long_out["workload"] = (f"long paths: the tiny workload's release ({int(mask.sum())} cells x {w.particles_per_cell} "
+                            f"particles, step limit {w.step_limit}), mass 1 per cell, MSE against the deposit at "
+                            f"(0.22, 1800), gradient at (mu, xi) = ({w.params['mu']:g}, {w.params['xi']:g})")
+    out["long_paths"] = long_out
+    host = {"calibration": (c, g, gD), "long": (w, mask, g_long, gD_long)}
+    return out, host
+
+
+# ------------------------------------------------------------------------------------------ host (oracle) legs
+
+def cpu_model() -> str:
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    try:
+        with open("/proc/cpuinfo") as f:
+            return next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        return ""
+
+
+def oracle_sample(w, mask: np.ndarray, steps_per_pass: int, seconds: float = 10.0) -> dict:
+    """The FP32 oracle, single-threaded, on every `stride`-th release cell (stride chosen for ~`seconds` of work
+    at ~26 M particle-steps/s)."""
+    import oracle
+    stride = max(1, int(round(steps_per_pass / (26e6 * seconds))))
+    cells = np.flatnonzero(mask)
+    sample = np.zeros(mask.size, np.uint8)
+    sample[cells[::stride]] = 1
+    sample = sample.reshape(mask.shape)
+    p = oracle.make_params(**w.params)
+    t0 = time.perf_counter()
+    res = oracle.trajectories(w.dem, sample, w.cell_size, p, w.particles_per_cell, w.step_limit, w.seed)
+    dt = time.perf_counter() - t0
+    return {"value": res.steps / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{w.name}: 1 in {stride} release cells ({int(sample.sum())} cells x {w.particles_per_cell} "
+                      f"particles, {res.steps} particle-steps, {dt:.1f} s, single-threaded FP32 C oracle)"}
+
+
+def oracle_full_pass(w, mask: np.ndarray, prec: str, threads: int):
+    """The whole pass on the oracle in `threads` host threads (the C calls release the GIL), each taking chunks
+    of consecutive release cells into rasters of its own; the rasters are merged exactly at the end (counts
+    add, speeds take the maximum)."""
+    import queue
+    import threading
+    import oracle
+    oracle._lib(prec)  # load the library once, before the threads
+    cells = np.flatnonzero(mask)
+    todo = queue.Queue()
+    for c in np.array_split(cells, max(1, 4 * threads)):
+        if c.size:
+            todo.put(c)
+    p = oracle.make_params(**w.params)
+    real = np.float32 if prec == "f32" else np.float64
+    acc = []
+
+    def worker():
+        counts = np.zeros(mask.shape, np.uint64)
+        vmax = np.zeros(mask.shape, real)
+        steps = 0
+        m = np.zeros(mask.size, np.uint8)
+        while True:
+            try:
+                chunk = todo.get_nowait()
+            except queue.Empty:
+                break
+            m[:] = 0
+            m[chunk] = 1
+            r = oracle.trajectories(w.dem, m.reshape(mask.shape), w.cell_size, p, w.particles_per_cell,
+                                    w.step_limit, w.seed, prec=prec)
+            counts += r.counts
+            np.maximum(vmax, r.vmax, out=vmax)
+            steps += r.steps
+        acc.append((counts, vmax, steps))
+
+    t0 = time.perf_counter()
+    ts = [threading.Thread(target=worker) for _ in range(threads)]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    dt = time.perf_counter() - t0
+    counts = np.zeros(mask.shape, np.uint64)
+    vmax = np.zeros(mask.shape, real)
+    steps = 0
+    for c, v, s in acc:
+        counts += c
+        np.maximum(vmax, v, out=vmax)
+        steps += s
+    return counts, vmax, steps, dt
+
+
+def fp64_error(c32, v32, s32, c64, v64, s64) -> dict:
+    """FP32 against FP64 oracle results of the same pass (paths diverge where a rounding moves a step across a
+    texel edge, so the rasters differ by more than the rounding of v)."""
+    vis32, vis64 = c32 > 0, c64 > 0
+    v32d = v32.astype(np.float64)
+    pos = vis32 & vis64 & (v32d > 0) & (v64 > 0)
+    rel = np.abs(v32d - v64)[pos] / v64[pos]
+    return {"count_cells_differing": int((c32 != c64).sum()), "cells_visited_fp32": int(vis32.sum()),
+            "visited_set_symmetric_difference": int((vis32 ^ vis64).sum()),
+            "entries_fp32": int(c32.sum()), "entries_fp64": int(c64.sum()),
+            "max_abs_count_difference": int(np.abs(c32.astype(np.int64) - c64.astype(np.int64)).max()),
+            "vmax_max_rel_difference": float(rel.max()) if rel.size else 0.0,
+            "vmax_median_rel_difference": float(np.median(rel)) if rel.size else 0.0,
+            "vmax_cells_rel_difference_above_1e-5": int((rel > 1e-5).sum()),
+            "vmax_cells_zero_in_one_precision_only": int(((vis32 & vis64) & ((v32d > 0) != (v64 > 0))).sum()),
+            "particle_steps_fp32": int(s32), "particle_steps_fp64": int(s64)}
+
+
+def oracle_workload_checks(w, mask, gpu_counts, gpu_vmax, threads: int) -> dict:
+    c32, v32, s32, t32 = oracle_full_pass(w, mask, "f32", threads)
+    c64, v64, s64, t64 = oracle_full_pass(w, mask, "f64", threads)
+    return {"full_pass_fp32": {"value": s32 / t32, "unit": "particle-steps/s", "threads": threads, "seconds": t32,
+                               "particle_steps": int(s32),
+                               "gpu_rasters_equal_oracle": bool(np.array_equal(c32.astype(np.uint32), gpu_counts)
+                                                                and np.array_equal(v32, gpu_vmax))},
+            "fp64_seconds": t64,
+            "fp32_vs_fp64": fp64_error(c32, v32, s32, c64, v64, s64)}
+
+
+def gradient_fp64_checks(host: dict) -> dict:
+    """GPU gradients against the FP64 oracle's on the same raster gradient gD; the share of particles whose
+    binary32 path differs from binary64; and the whole loss's central difference (steps of 1e-3 of the parameter,
+    jumps of particles whose end changes included) against the pathwise FP64 gradient."""
+    import oracle
+    out = {}
+    c, g, gD = host["calibration"]
+    w, mask, g_long, gD_long = host["long"]
+    cases = {
+        "calibration": (c.dem, c.mask, c.mass, c.cell_size, dict(mu=c.mu0, xi=c.xi0, flow_height=c.flow_height),
+                        c.particles_per_cell, c.step_limit, c.seed, g, gD, True),
+        "long_paths": (w.dem, mask, mask.astype(np.float32), w.cell_size, dict(w.params), w.particles_per_cell,
+                       w.step_limit, w.seed, g_long, gD_long, False),
+    }
+    for name, (dem, m, mass, cs, p0, P, S, seed, g_gpu, gD_np, jump) in cases.items():
+        op = oracle.make_params(**p0)
+        g64 = oracle.smooth_backward(dem, m, cs, op, P, S, seed, gD_np, mass=mass, prec="f64")
+        _, r32, s32 = oracle.smooth_particles(dem, m, cs, op, P, S, seed, gD_np, mass=mass, prec="f32")
+        _, r64, s64 = oracle.smooth_particles(dem, m, cs, op, P, S, seed, gD_np, mass=mass, prec="f64")
+        same = (r32 == r64) & (s32 == s64)
+        ref = (g64.dmu, g64.dxi, g64.dh)
+        d = {"fp32_paths_differing_fraction": float(1.0 - same.mean()),
+             "dL_dmu_fp64": ref[0], "dL_dxi_fp64": ref[1], "dL_dh_fp64": ref[2]}
+        for i, nm in enumerate(("mu", "xi", "h")):
+            d[f"rel_err_dL_d{nm}"] = abs(float(g_gpu[i]) - ref[i]) / abs(ref[i]) if ref[i] else None
+        if jump:
+            gl = gD_np.astype(np.float64)
+            for nm in ("mu", "xi"):
+                h = 1e-3 * p0[nm]
+                L = [float((gl * oracle.smooth_forward(dem, m, cs, oracle.make_params(**dict(p0, **{nm: p0[nm] + s * h})),
+                                                       P, S, seed, mass=mass, prec="f64").dep).sum()) for s in (1, -1)]
+                fd = (L[0] - L[1]) / (2 * h)
+                k = ("mu", "xi").index(nm)
+                d[f"whole_loss_central_difference_dL_d{nm}"] = fd
+                d[f"jump_part_dL_d{nm}"] = (fd - ref[k]) / fd
+        out[name] = d
+    return out
+
+
+# ------------------------------------------------------------------------------------------ main
 
 def main() -> int:
     args = parse()
@@ -376,7 +679,6 @@ def main() -> int:
                                     "all-reduce the integer rasters (see the design notes)"}))
         return 2
     import torch
-    import synth
     import paper_2506_23364_amd as avl
 
     if not torch.cuda.is_available():
@@ -391,130 +693,76 @@ def main() -> int:
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    w = synth.make_workload(args.workload)
-    h, wd = w.dem.shape
-    dem = torch.from_numpy(w.dem).cuda()
-    params = avl.Params.make(**w.params)
-    stream = torch.cuda.current_stream()
-
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
-    res = None
-
-    def step(timed: bool):
-        nonlocal res
-        if timed:
-            ev[0].record(stream)
-        nrm = avl.normals(dem, w.cell_size)
-        mask = avl.release_mask(nrm, dem, w.slope_min_deg, w.slope_max_deg, w.z_min, w.z_max)
-        if timed:
-            ev[1].record(stream)
-        res = avl.trajectories(dem, mask, w.cell_size, params, w.particles_per_cell, w.step_limit, w.seed, 0, res)
-        if timed:
-            ev[2].record(stream)
-        return mask
-
-    for _ in range(max(args.warmup, 1)):
-        mask = step(False)
-    torch.cuda.synchronize()
-    stats = res.stats.cpu().numpy().astype(np.int64)
-    steps_per_pass = int(stats[0])
-    n_release = int(mask.sum().item())
-    mask_np = mask.cpu().numpy()
-
-    # per-step timing: the terrain passes and the trajectory call with torch events on the stream, the
-    # trajectory kernel alone with the library's events around its launch on the same stream
-    t_terrain = t_traj = t_kernel = 0.0
-    kernel_ms = []
-    avl.set_profiling(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step(True)
-        ev[2].synchronize()
-        t_terrain += ev[0].elapsed_time(ev[1])
-        t_traj += ev[1].elapsed_time(ev[2])
-        kernel_ms.append(avl.last_kernel_ms())
-        t_kernel += kernel_ms[-1]
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    avl.set_profiling(False)
-    variant = avl.last_variant()
-    # a second loop without per-step syncs gives the throughput figure
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step(False)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    assert int(res.stats.cpu().numpy()[0]) == steps_per_pass, "particle-step count changed between passes"
-
-    value = steps_per_pass * args.steps / elapsed
-    kern_s = t_kernel / 1e3 / args.steps
-    achieved_tops = OPS_PER_STEP * steps_per_pass / kern_s / 1e12
+    w, dem = make_inputs(torch, args.workload)
+    run = timed_passes(avl, torch, w, dem, args.steps, args.warmup)
+    steps_per_pass = run["steps_per_pass"]
+    kern_s = run["kernel_ms"] * 1e-3
     out = {
-        "metric": "particle-steps/s forward + s per (mu,xi) gradient, batched vs plain, 1 MI355X",
-        "value": value,
+        "metric": METRIC,
+        "value": run["value"],
         "unit": "particle-steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": elapsed / args.steps * 1e3,
+        "ms_per_step": run["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {
-            "workload": f"{w.name}: {h}x{wd} ridged diamond-square fBm DEM at {w.cell_size:g} m, release "
-                        f"{w.slope_min_deg:g}-{w.slope_max_deg:g} deg above z={w.z_min:.1f} m "
-                        f"({n_release} cells), {w.particles_per_cell} particles/cell, step limit {w.step_limit}, "
-                        f"mu {w.params['mu']:g}, xi {w.params['xi']:g}, h {w.params['flow_height']:g}, "
-                        f"persistence {w.params['persistence']:g}, randomness {w.params['randomness']:g}",
-            "release_cells": n_release,
-            "particles": n_release * w.particles_per_cell,
-            "particle_steps_per_pass": steps_per_pass,
-            "mean_steps_per_particle": steps_per_pass / max(1, n_release * w.particles_per_cell),
-            "ends_exit_stop_limit": [int(v) for v in stats[1:]],
-        },
-        "timing": {
-            "ms_terrain_normals_mask": t_terrain / args.steps,
-            "ms_trajectories_call": t_traj / args.steps,
-            "ms_trajectory_kernel": t_kernel / args.steps,
-            "ms_trajectory_kernel_median": float(np.median(kernel_ms)),
-            "ms_per_step_synced": wall / args.steps * 1e3,
-        },
-        "roofline": {
-            "bound": "alu",
-            "kernel": "k_trajectories",
-            "variant": variant,
-            "achieved": achieved_tops,
-            "peak": ALU_PEAK_TOPS,
-            "unit": "TFLOP/s",
-            "frac": achieved_tops / ALU_PEAK_TOPS,
-            "traffic": recorded_traffic(variant) if args.workload == "alpine" else None,
-            "ops_per_particle_step": OPS_PER_STEP,
-            "hbm_view": {"bytes_per_particle_step": BYTES_PER_STEP,
-                         "achieved_GBs": BYTES_PER_STEP * steps_per_pass / kern_s / 1e9,
-                         "peak_GBs": HBM_PEAK_GBS},
-        },
+        "config": run["config"],
+        "timing": run["timing"],
+        "roofline": {"bound": "l2_gather", "kernel": "k_trajectories", "variant": run["variant"],
+                     "achieved_particle_steps_per_s": steps_per_pass / kern_s,
+                     "hbm_view": {"bytes_per_particle_step": BYTES_PER_STEP,
+                                  "achieved_GBs": BYTES_PER_STEP * steps_per_pass / kern_s / 1e9,
+                                  "peak_GBs": HBM_PEAK_GBS}},
     }
     if args.main_only:
         print(json.dumps(out), flush=True)
         return 0
-    out["mipmap"] = mipmap_leg(avl, torch, res, 20)
-    out["snow_cover"] = snow_leg(avl, torch, w, dem, 20)
-    if args.workload == "alpine":
-        out["fine_release"] = fine_leg(avl, torch, w, dem, 5)
-    if not args.no_batched:
+    only = args.leg
+    if only in ("", "roofline"):
+        out["roofline"] = roofline_leg(avl, torch, w, dem, run["mask"], run)
+    if only == "":
+        out["mipmap"] = mipmap_leg(avl, torch, run["res"], 20)
+        out["snow_cover"] = snow_leg(avl, torch, w, dem, 20)
+    host_runs = {args.workload: (w, run)}
+    if only in ("", "workloads"):
+        out["workloads"] = {}
+        for name in ("tiny", "alpine", "large"):
+            if name == args.workload:
+                continue
+            w2, dem2 = make_inputs(torch, name)
+            r2 = timed_passes(avl, torch, w2, dem2, args.steps, args.warmup)
+            leg = {k: r2[k] for k in ("value", "ms_per_step", "config", "timing", "variant")}
+            leg["unit"] = "particle-steps/s"
+            leg["roofline"] = roofline_leg(avl, torch, w2, dem2, r2["mask"], r2)
+            out["workloads"][name] = leg
+            host_runs[name] = (w2, r2)
+            del dem2
+    if only == "":
+        out["fine_release"] = fine_leg(avl, torch, 5)
+    if only in ("", "batched"):
         out["batched"] = batched_leg(avl, torch, 3)
-    if not args.no_gradient:
-        out["gradient"] = gradient_leg(avl, torch, 5)
+    grad_host = None
+    if only in ("", "gradient"):
+        out["gradient"], grad_host = gradient_leg(avl, torch, 5)
+    if only in ("", "calibration"):
         out["calibration"] = calibration_leg(avl, torch)
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, mask_np, args.cpu_stride)
-        if args.cpu_procs > 0:
-            out["cpu_baseline"]["parallel_full_pass"] = cpu_parallel(
-                w, mask_np, args.cpu_procs, res.counts.cpu().numpy(), res.vmax.cpu().numpy())
+    if not args.no_cpu_baseline and only == "":
+        mask_np = run["mask"].cpu().numpy()
+        base = oracle_sample(w, mask_np, steps_per_pass)
+        base.update({"cpu": cpu_model(), "os_cpu_count": os.cpu_count(), "threads_full_pass": args.cpu_threads})
+        if args.cpu_threads > 0:
+            base["workloads"] = {}
+            for name, (w2, r2) in host_runs.items():
+                base["workloads"][name] = oracle_workload_checks(
+                    w2, r2["mask"].cpu().numpy(), r2["res"].counts.cpu().numpy(), r2["res"].vmax.cpu().numpy(),
+                    args.cpu_threads)
+        if grad_host is not None:
+            base["gradient_fp32_vs_fp64"] = gradient_fp64_checks(grad_host)
+        out["cpu_baseline"] = base
     print(json.dumps(out), flush=True)
     return 0
 

@@ -158,25 +158,32 @@ AVL_API int avl_trajectories_record(const float* dem, const uint8_t* mask, int32
                                     size_t workspace_bytes, void* stream);
 
 /* ---- Memory microbenchmarks (measurement: the ceilings of the trajectory node's memory traffic on this
- * chip, for a pass's own access stream). They replay the output of avl_trajectories_record's two calls
- * (ends, then points with the offsets sized from them; speeds2 for the atomics), of the run on the same grid,
- * over particles 0 .. n_particles - 1; the offsets must be those the points were written with. Nothing of the
- * model is computed. With avl_set_profiling on, avl_last_kernel_ms gives the replay kernel's duration.
+ * chip, for a pass's own addresses). They take the output of avl_trajectories_record's two calls (ends, then
+ * points and speeds2 at the offsets sized from the ends) over particles 0 .. n_particles - 1 of a run on an
+ * H x W grid; the offsets must be those the points were written with. Nothing of the model is computed. With
+ * avl_set_profiling on, avl_last_kernel_ms gives the replay kernel's duration.
  *
- * avl_bench_gather: every 2 x 2 patch read of the pass (each accepted step's position and a stopped
- *   particle's rejected target), as two 8-byte loads from a padded copy of dem (H*W floats), lanes taking
- *   particles in slot order, 64 consecutive per wave; *checksum (device u32) gets the XOR of the bits of
- *   every texel read. workspace: avl_workspace_bytes(H, W).
- * avl_bench_atomics: the raster accumulation without aggregation: a device-scope u32 add per cell entry and
- *   a u32 max of the v^2 bits per cell left; counts and vmax2_bits (H*W u32 each, overwritten) end equal to
- *   the pass's counts and the bits of its v^2 maxima. workspace: at least 512 bytes.
+ * avl_bench_schedule lays the pass's memory operations out in the order a wave meets them: chunks of 64
+ *   consecutive particles, and within a chunk the t-th operation of every particle that has one, in particle
+ *   order. mode 0 writes per chunk c (of ceil(n_particles / 64)) totals[2c] = its gathers (each accepted step's
+ *   position and a stopped particle's rejected target) and totals[2c + 1] = its cell visits (the release cell
+ *   and every cell entered). mode 1 writes, at gather_base[c] and visit_base[c] (the exclusive sums of those
+ *   totals), the gathers (u32 byte offset of the 2 x 2 patch in a copy of the DEM padded by one texel) and the
+ *   visits (u32 pairs: the cell, the bits of the largest v^2 of the steps that ended in it). All device arrays.
+ * avl_bench_gather: two 8-byte loads from the padded copy of dem (H*W floats) per gather, every gather
+ *   independent; *checksum (device u32) gets the XOR of the bits of every texel read. workspace:
+ *   avl_workspace_bytes(H, W).
+ * avl_bench_atomics: per visit a device-scope u32 add to counts and a u32 max of the v^2 bits into vmax2_bits
+ *   (H*W u32 each, overwritten): the accumulation without aggregation, whose rasters equal the pass's.
  * avl_bench_stream: copies `bytes` (a multiple of 16; 16-byte aligned pointers) from src to dst. */
-AVL_API int avl_bench_gather(const float* dem, int32_t H, int32_t W, const float* points, const uint64_t* offsets,
-                             const uint32_t* ends, uint64_t n_particles, uint32_t* checksum, void* workspace,
-                             size_t workspace_bytes, void* stream);
-AVL_API int avl_bench_atomics(int32_t H, int32_t W, const float* points, const float* speeds2, const uint64_t* offsets,
-                              const uint32_t* ends, uint64_t n_particles, uint32_t* counts, uint32_t* vmax2_bits,
-                              void* workspace, size_t workspace_bytes, void* stream);
+AVL_API int avl_bench_schedule(int32_t mode, int32_t H, int32_t W, const float* points, const float* speeds2,
+                               const uint64_t* offsets, const uint32_t* ends, uint64_t n_particles, uint64_t* totals,
+                               const uint64_t* gather_base, const uint64_t* visit_base, uint32_t* gathers,
+                               uint32_t* visits, void* stream);
+AVL_API int avl_bench_gather(const float* dem, int32_t H, int32_t W, const uint32_t* gathers, uint64_t n_gathers,
+                             uint32_t* checksum, void* workspace, size_t workspace_bytes, void* stream);
+AVL_API int avl_bench_atomics(int32_t H, int32_t W, const uint32_t* visits, uint64_t n_visits, uint32_t* counts,
+                              uint32_t* vmax2_bits, void* stream);
 AVL_API int avl_bench_stream(const void* src, void* dst, size_t bytes, void* stream);
 
 /* Release texture at a finer resolution than the DEM (section 5.2: the user picks the texture resolution

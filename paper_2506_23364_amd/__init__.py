@@ -81,9 +81,11 @@ def _load() -> ctypes.CDLL:
     L.avl_trajectories_record.argtypes = [vp, vp, i32, i32, f32, ctypes.POINTER(Params), u32, u32, u64, u32, u64, u32,
                                           vp, u32, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     L.avl_trajectories_record.restype = ctypes.c_int
-    L.avl_bench_gather.argtypes = [vp, i32, i32, vp, vp, vp, u64, vp, vp, sz, vp]
+    L.avl_bench_schedule.argtypes = [i32, i32, i32, vp, vp, vp, vp, u64, vp, vp, vp, vp, vp, vp]
+    L.avl_bench_schedule.restype = ctypes.c_int
+    L.avl_bench_gather.argtypes = [vp, i32, i32, vp, u64, vp, vp, sz, vp]
     L.avl_bench_gather.restype = ctypes.c_int
-    L.avl_bench_atomics.argtypes = [i32, i32, vp, vp, vp, vp, u64, vp, vp, vp, sz, vp]
+    L.avl_bench_atomics.argtypes = [i32, i32, vp, u64, vp, vp, vp]
     L.avl_bench_atomics.restype = ctypes.c_int
     L.avl_bench_stream.argtypes = [vp, vp, sz, vp]
     L.avl_bench_stream.restype = ctypes.c_int
@@ -381,30 +383,57 @@ def trajectory_paths(dem: torch.Tensor, mask: torch.Tensor, cell_size: float, pa
     return Paths(ends, pts[:total], sp[:total] if sp is not None else None, offsets, out)
 
 
-def bench_gather(dem: torch.Tensor, paths: Paths) -> torch.Tensor:
-    """Replay of the gathers of a recorded pass (memory microbenchmark); returns the device checksum."""
+@dataclass
+class ReplaySchedule:
+    gathers: torch.Tensor  # (n_gathers,) uint32 byte offsets of the 2 x 2 patches in the padded DEM, wave order
+    visits: torch.Tensor   # (n_visits, 2) uint32 (cell, v^2 bits), wave order
+
+
+def bench_schedule(shape, paths: Paths) -> ReplaySchedule:
+    """The wave-order schedule of a recorded pass's gathers and cell visits (memory microbenchmarks)."""
+    h, w = shape
+    dev = paths.points.device
+    n = paths.ends.numel()
+    n_chunks = (n + 63) // 64
+    totals = torch.zeros(2 * n_chunks, dtype=torch.int64, device=dev)
+    args = (h, w, paths.points.data_ptr(), paths.speeds2.data_ptr(), paths.offsets.data_ptr(), paths.ends.data_ptr(), n)
+    with torch.cuda.device(dev):
+        _check(lib.avl_bench_schedule(0, *args, totals.data_ptr(), None, None, None, None, _stream(dev)),
+               "avl_bench_schedule")
+        t = totals.view(n_chunks, 2)
+        base = torch.zeros((n_chunks + 1, 2), dtype=torch.int64, device=dev)
+        base[1:] = torch.cumsum(t, 0)
+        ng, nv = (int(v) for v in base[-1].tolist())
+        gb = base[:-1, 0].contiguous()
+        vb = base[:-1, 1].contiguous()
+        gathers = torch.empty(max(ng, 1), dtype=torch.uint32, device=dev)
+        visits = torch.empty((max(nv, 1), 2), dtype=torch.uint32, device=dev)
+        _check(lib.avl_bench_schedule(1, *args, None, gb.data_ptr(), vb.data_ptr(), gathers.data_ptr(),
+                                      visits.data_ptr(), _stream(dev)), "avl_bench_schedule")
+    return ReplaySchedule(gathers[:ng], visits[:nv])
+
+
+def bench_gather(dem: torch.Tensor, sched: ReplaySchedule) -> torch.Tensor:
+    """Replay of the gathers of a schedule (memory microbenchmark); returns the device checksum."""
     _need(dem, "dem", torch.float32, 2)
     h, w = dem.shape
     chk = torch.empty(1, dtype=torch.uint32, device=dem.device)
     with torch.cuda.device(dem.device):
         ws = _workspace(dem.device, workspace_bytes(h, w))
-        _check(lib.avl_bench_gather(dem.data_ptr(), h, w, paths.points.data_ptr(), paths.offsets.data_ptr(),
-                                    paths.ends.data_ptr(), paths.ends.numel(), chk.data_ptr(), ws.data_ptr(),
-                                    ws.numel(), _stream(dem.device)), "avl_bench_gather")
+        _check(lib.avl_bench_gather(dem.data_ptr(), h, w, sched.gathers.data_ptr(), sched.gathers.numel(),
+                                    chk.data_ptr(), ws.data_ptr(), ws.numel(), _stream(dem.device)), "avl_bench_gather")
     return chk
 
 
-def bench_atomics(shape, paths: Paths, out: tuple | None = None) -> tuple[torch.Tensor, torch.Tensor]:
-    """Replay of the raster atomics of a recorded pass without aggregation: (counts, v^2 max bits)."""
+def bench_atomics(shape, sched: ReplaySchedule, out: tuple | None = None) -> tuple[torch.Tensor, torch.Tensor]:
+    """Replay of the cell visits of a schedule as unaggregated raster atomics: (counts, v^2 max bits)."""
     h, w = shape
-    dev = paths.points.device
+    dev = sched.visits.device
     counts, bits = out if out is not None else (torch.empty((h, w), dtype=torch.uint32, device=dev),
                                                 torch.empty((h, w), dtype=torch.uint32, device=dev))
     with torch.cuda.device(dev):
-        ws = _workspace(dev, 512)
-        _check(lib.avl_bench_atomics(h, w, paths.points.data_ptr(), paths.speeds2.data_ptr(), paths.offsets.data_ptr(),
-                                     paths.ends.data_ptr(), paths.ends.numel(), counts.data_ptr(), bits.data_ptr(),
-                                     ws.data_ptr(), ws.numel(), _stream(dev)), "avl_bench_atomics")
+        _check(lib.avl_bench_atomics(h, w, sched.visits.data_ptr(), sched.visits.shape[0], counts.data_ptr(),
+                                     bits.data_ptr(), _stream(dev)), "avl_bench_atomics")
     return counts, bits
 
 

@@ -643,12 +643,31 @@ int avl_trajectories_record(const float* dem, const uint8_t* mask, int32_t H, in
                        step_limit, seed, run_id, counts, vmax, stats, workspace, workspace_bytes, stream, false, &rec);
 }
 
-int avl_bench_gather(const float* dem, int32_t H, int32_t W, const float* points, const uint64_t* offsets,
-                     const uint32_t* ends, uint64_t n_particles, uint32_t* checksum, void* workspace,
-                     size_t workspace_bytes, void* stream) {
+int avl_bench_schedule(int32_t mode, int32_t H, int32_t W, const float* points, const float* speeds2,
+                       const uint64_t* offsets, const uint32_t* ends, uint64_t n_particles, uint64_t* totals,
+                       const uint64_t* gather_base, const uint64_t* visit_base, uint32_t* gathers, uint32_t* visits,
+                       void* stream) {
     g_last_error.clear();
-    if (!dem || !points || !offsets || !ends || !checksum || !workspace)
-        return fail(AVL_EINVAL, "avl_bench_gather: null pointer");
+    if (mode != 0 && mode != 1) return fail(AVL_EINVAL, "avl_bench_schedule: mode must be 0 or 1");
+    if (!points || !speeds2 || !offsets || !ends) return fail(AVL_EINVAL, "avl_bench_schedule: null pointer");
+    if (mode == 0 && !totals) return fail(AVL_EINVAL, "avl_bench_schedule: totals is NULL");
+    if (mode == 1 && (!gather_base || !visit_base || !gathers || !visits))
+        return fail(AVL_EINVAL, "avl_bench_schedule: null pointer");
+    if (!grid_ok(H, W, 1) || H >= (1 << 23) || W >= (1 << 23) || avl::padded_cells(H, W) >= (int64_t(1) << 30))
+        return fail(AVL_EINVAL, "avl_bench_schedule: need H, W >= 1, H, W < 2^23 and (H + 2)(W + 2) < 2^30");
+    if (n_particles == 0) return AVL_OK;
+    hipError_t e = avl::launch_replay_schedule(
+        mode, reinterpret_cast<const float2*>(points), speeds2, reinterpret_cast<const unsigned long long*>(offsets),
+        ends, n_particles, W, reinterpret_cast<unsigned long long*>(totals),
+        reinterpret_cast<const unsigned long long*>(gather_base), reinterpret_cast<const unsigned long long*>(visit_base),
+        gathers, reinterpret_cast<uint2*>(visits), static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? AVL_OK : hip_fail(e, "avl_bench_schedule");
+}
+
+int avl_bench_gather(const float* dem, int32_t H, int32_t W, const uint32_t* gathers, uint64_t n_gathers,
+                     uint32_t* checksum, void* workspace, size_t workspace_bytes, void* stream) {
+    g_last_error.clear();
+    if (!dem || !gathers || !checksum || !workspace) return fail(AVL_EINVAL, "avl_bench_gather: null pointer");
     if (!grid_ok(H, W, 1) || avl::padded_cells(H, W) >= (int64_t(1) << 30) || H >= (1 << 23) || W >= (1 << 23))
         return fail(AVL_EINVAL, "avl_bench_gather: need H, W >= 1, H, W < 2^23 and (H + 2)(W + 2) < 2^30");
     if (workspace_bytes < avl::workspace_bytes(H, W)) return fail(AVL_ENOMEM, "avl_bench_gather: workspace too small");
@@ -656,38 +675,31 @@ int avl_bench_gather(const float* dem, int32_t H, int32_t W, const float* points
     avl::Workspace ws = avl::carve(workspace, H, W);
     hipError_t e;
     if ((e = avl::launch_pad_dem(dem, H, W, ws.dem_pad, s)) != hipSuccess ||
-        (e = avl::launch_fill_u64(ws.queues, 0ull, avl::kXcds, s)) != hipSuccess ||
         (e = avl::launch_fill_u32(checksum, 0u, 1, s)) != hipSuccess)
         return hip_fail(e, "avl_bench_gather: set-up");
+    if (n_gathers == 0) return AVL_OK;
     const uint32_t pad_bytes = (uint32_t)(avl::padded_cells(H, W) * sizeof(float));
     e = timed(s, [&] {
-        return avl::launch_replay_gather(reinterpret_cast<const float2*>(points),
-                                         reinterpret_cast<const unsigned long long*>(offsets), ends, n_particles,
-                                         ws.dem_pad, pad_bytes, W, ws.queues, checksum, s);
+        return avl::launch_replay_gather(gathers, n_gathers, ws.dem_pad, pad_bytes, 4u * ((uint32_t)W + 2u), checksum,
+                                         s);
     });
     return e == hipSuccess ? AVL_OK : hip_fail(e, "avl_bench_gather: launch");
 }
 
-int avl_bench_atomics(int32_t H, int32_t W, const float* points, const float* speeds2, const uint64_t* offsets,
-                      const uint32_t* ends, uint64_t n_particles, uint32_t* counts, uint32_t* vmax2_bits,
-                      void* workspace, size_t workspace_bytes, void* stream) {
+int avl_bench_atomics(int32_t H, int32_t W, const uint32_t* visits, uint64_t n_visits, uint32_t* counts,
+                      uint32_t* vmax2_bits, void* stream) {
     g_last_error.clear();
-    if (!points || !speeds2 || !offsets || !ends || !counts || !vmax2_bits || !workspace)
-        return fail(AVL_EINVAL, "avl_bench_atomics: null pointer");
+    if (!visits || !counts || !vmax2_bits) return fail(AVL_EINVAL, "avl_bench_atomics: null pointer");
     if (!grid_ok(H, W, 1)) return fail(AVL_EINVAL, "avl_bench_atomics: need H, W >= 1 and H*W < 2^31");
-    if (workspace_bytes < avl::kControl) return fail(AVL_ENOMEM, "avl_bench_atomics: workspace too small");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    auto* queues = reinterpret_cast<unsigned long long*>(static_cast<char*>(workspace) + 128);
     const int64_t n = (int64_t)H * W;
     hipError_t e;
     if ((e = avl::launch_fill_u32(counts, 0u, n, s)) != hipSuccess ||
-        (e = avl::launch_fill_u32(vmax2_bits, 0u, n, s)) != hipSuccess ||
-        (e = avl::launch_fill_u64(queues, 0ull, avl::kXcds, s)) != hipSuccess)
+        (e = avl::launch_fill_u32(vmax2_bits, 0u, n, s)) != hipSuccess)
         return hip_fail(e, "avl_bench_atomics: set-up");
+    if (n_visits == 0) return AVL_OK;
     e = timed(s, [&] {
-        return avl::launch_replay_atomics(reinterpret_cast<const float2*>(points), speeds2,
-                                          reinterpret_cast<const unsigned long long*>(offsets), ends, n_particles, W,
-                                          queues, counts, vmax2_bits, s);
+        return avl::launch_replay_atomics(reinterpret_cast<const uint2*>(visits), n_visits, counts, vmax2_bits, s);
     });
     return e == hipSuccess ? AVL_OK : hip_fail(e, "avl_bench_atomics: launch");
 }

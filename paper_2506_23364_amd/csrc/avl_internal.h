@@ -188,13 +188,15 @@ hipError_t launch_trajectories(const TrajArgs& a, bool batched, const LaunchShap
 // The recording instantiation (single run, variant 0's shape, runout-angle stop compiled in).
 hipError_t launch_trajectories_record(const TrajArgs& a, hipStream_t s);
 
-// Memory microbenchmarks (membench.hip): replays of a recorded pass's gathers and raster atomics, and a copy.
-hipError_t launch_replay_gather(const float2* pts, const unsigned long long* off, const uint32_t* ends, uint64_t n,
-                                const float* dem_pad, uint32_t pad_bytes, int W, unsigned long long* queues,
-                                uint32_t* checksum, hipStream_t s);
-hipError_t launch_replay_atomics(const float2* pts, const float* v2s, const unsigned long long* off,
-                                 const uint32_t* ends, uint64_t n, int W, unsigned long long* queues, uint32_t* counts,
-                                 uint32_t* vmax2, hipStream_t s);
+// Memory microbenchmarks (membench.hip): the wave-order schedule of a recorded pass's gathers and cell visits,
+// the replays of both, and a copy.
+hipError_t launch_replay_schedule(int mode, const float2* pts, const float* v2s, const unsigned long long* off,
+                                  const uint32_t* ends, uint64_t n, int W, unsigned long long* totals,
+                                  const unsigned long long* gbase, const unsigned long long* vbase, uint32_t* gathers,
+                                  uint2* visits, hipStream_t s);
+hipError_t launch_replay_gather(const uint32_t* sched, uint64_t n, const float* dem_pad, uint32_t pad_bytes,
+                                uint32_t row_bytes, uint32_t* checksum, hipStream_t s);
+hipError_t launch_replay_atomics(const uint2* sched, uint64_t n, uint32_t* counts, uint32_t* vmax2, hipStream_t s);
 hipError_t launch_stream_copy(const void* src, void* dst, uint64_t n16, hipStream_t s);
 
 // Smooth forward and adjoint (smooth.hip)
