@@ -86,6 +86,8 @@ def parse():
     ap.add_argument("--main-only", action="store_true", help="only the timed passes of the headline workload")
     ap.add_argument("--leg", default="", choices=["", "roofline", "workloads", "batched", "gradient", "calibration"],
                     help="only this leg (after the headline passes); for counter runs")
+    ap.add_argument("--no-graphs", action="store_true",
+                    help="launch batched calls eagerly instead of replaying captured HIP graphs (counter runs)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="copy 256 MiB once first: a plain copy of known size that calibrates HBM byte counters")
     return ap.parse_args()
@@ -246,21 +248,29 @@ def roofline_leg(avl, torch, w, dem, mask, run: dict, reps: int = 3) -> dict:
             "particle_steps_per_s": VALU_WAVE_INSTS_PER_S * steps / valu,
             "wave_insts_per_particle_step": valu / steps, "source": "rocprofv3 SQ_INSTS_VALU (profiles)"},
     }
+    bound, peak_steps = "l2_gather", gather_ceiling
+    achieved_bw, peak_bw = (GATHER_BYTES * gathers / (t_kernel * 1e-3) / 1e9, GATHER_BYTES * gathers / (t_gather * 1e-3) / 1e9)
     if tcc_atomic is not None:
         # the kernel's own memory-side atomics at the replay's memory-side atomic rate (the replay issues one
-        # add and at most one max per visit: an upper estimate of its rate)
+        # add and at most one max per visit: an upper estimate of its rate, so a ceiling on the high side);
+        # each memory-side atomic moves one 32-byte request
         rate = 2.0 * visits / (t_atomic * 1e-3)
-        ceilings["atomics_as_issued"] = {"particle_steps_per_s": rate * steps / tcc_atomic,
+        atomic_steps = rate * steps / tcc_atomic
+        ceilings["atomics_as_issued"] = {"particle_steps_per_s": atomic_steps,
                                          "memory_side_atomics_per_launch": tcc_atomic,
+                                         "memory_side_atomics_per_particle_step": tcc_atomic / steps,
+                                         "replay_atomics_per_s_upper": rate,
                                          "source": "rocprofv3 TCC_ATOMIC (profiles)"}
+        if atomic_steps < peak_steps:
+            bound, peak_steps = "atomics_as_issued", atomic_steps
+            achieved_bw, peak_bw = 32 * tcc_atomic / (t_kernel * 1e-3) / 1e9, 32 * rate / 1e9
     return {
-        "bound": "l2_gather", "kernel": "k_trajectories", "variant": variant,
-        "achieved": GATHER_BYTES * gathers / (t_kernel * 1e-3) / 1e9,
-        "peak": GATHER_BYTES * gathers / (t_gather * 1e-3) / 1e9,
-        "unit": "GB/s",
-        "frac": achieved / gather_ceiling,
+        "bound": bound, "kernel": "k_trajectories", "variant": variant,
+        "achieved": achieved_bw, "peak": peak_bw, "unit": "GB/s",
+        "frac": achieved / peak_steps,
         "traffic": recorded(w.name, "traffic_bytes_per_launch", variant),
         "achieved_particle_steps_per_s": achieved,
+        "ceiling_particle_steps_per_s": peak_steps,
         "kernel_ms": t_kernel,
         "ceilings": ceilings,
         "recorded_pass_equals_timed_pass": same,
@@ -685,8 +695,8 @@ def main() -> int:
         print(json.dumps({"error": "no GPU visible"}))
         return 1
     torch.cuda.set_device(0)
-    if args.variant >= 0:
-        avl.set_tuning(args.variant, True)
+    if args.variant >= 0 or args.no_graphs:
+        avl.set_tuning(args.variant, not args.no_graphs)
     if args.copy_probe:
         src = torch.ones(256 << 20, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)
@@ -712,7 +722,8 @@ def main() -> int:
         "data": "synthetic",
         "config": run["config"],
         "timing": run["timing"],
-        "roofline": {"bound": "l2_gather", "kernel": "k_trajectories", "variant": run["variant"],
+        "roofline": {"bound": None, "note": "ceilings are measured by the roofline leg (not run with --main-only)",
+                     "kernel": "k_trajectories", "variant": run["variant"],
                      "achieved_particle_steps_per_s": steps_per_pass / kern_s,
                      "hbm_view": {"bytes_per_particle_step": BYTES_PER_STEP,
                                   "achieved_GBs": BYTES_PER_STEP * steps_per_pass / kern_s / 1e9,
