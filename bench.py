@@ -265,7 +265,7 @@ def roofline_leg(avl, torch, w, dem, mask, run: dict, reps: int = 3) -> dict:
             bound, peak_steps = "atomics_as_issued", atomic_steps
             achieved_bw, peak_bw = 32 * tcc_atomic / (t_kernel * 1e-3) / 1e9, 32 * rate / 1e9
     return {
-        "bound": bound, "kernel": "k_trajectories", "variant": variant,
+        "bound": bound, "kernel": "k_trajectories", "variant": variant, "variant_shape": avl.variant_info(variant),
         "achieved": achieved_bw, "peak": peak_bw, "unit": "GB/s",
         "frac": achieved / peak_steps,
         "traffic": recorded(w.name, "traffic_bytes_per_launch", variant),
@@ -440,6 +440,7 @@ def batched_leg(avl, torch, reps: int) -> dict:
         plain_loop()
     torch.cuda.synchronize()
     t_plain = (time.perf_counter() - t0) / reps
+    plain_variant = avl.last_variant()
     same = bool(torch.equal(plain.counts.view(torch.int32), out.counts.view(torch.int32))
                 and torch.equal(plain.vmax, out.vmax)
                 and torch.equal(plain.stats.view(torch.int64), out.stats.view(torch.int64)))
@@ -450,7 +451,8 @@ def batched_leg(avl, torch, reps: int) -> dict:
             "particle_steps": steps, "ms_batched": t_batch * 1e3, "ms_plain_calls": t_plain * 1e3,
             "speedup_batched_vs_plain": t_plain / t_batch,
             "particle_steps_per_s_batched": steps / t_batch, "particle_steps_per_s_plain": steps / t_plain,
-            "variant": variant, "batched_equals_plain": same}
+            "variant": variant, "variant_shape": avl.variant_info(variant), "plain_calls_variant": plain_variant,
+            "batched_equals_plain": same}
 
 
 def gradient_case(avl, torch, dem_np, mask_np, mass_np, cs, target_params, p0, P, S, seed, reps):

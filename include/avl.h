@@ -343,6 +343,11 @@ AVL_API int avl_overlay_mipmap(const uint32_t* counts, const float* vmax, int32_
  * (default), 0 = launch eagerly. Returns AVL_EINVAL for an out-of-range variant. */
 AVL_API int avl_set_tuning(int32_t variant, int32_t graphs);
 AVL_API int32_t avl_tuning_variants(void);
+/* Shape of a kernel variant: info (8 host int32) = threads per block, iterations per epoch between table
+ * flushes, LDS table slots per block, probes per key, window top-up in blocks of slots, retention threshold
+ * (0 = none), waves per SIMD the register budget is sized for, particle slots per lane that size the grid of a
+ * small problem. AVL_EINVAL for a NULL info or an index out of range. */
+AVL_API int avl_tuning_variant_info(int32_t variant, int32_t* info);
 /* The variant the last trajectory call on this thread used. */
 AVL_API int32_t avl_last_variant(void);
 

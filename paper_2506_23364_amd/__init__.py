@@ -126,6 +126,8 @@ def _load() -> ctypes.CDLL:
     L.avl_set_tuning.restype = ctypes.c_int
     L.avl_tuning_variants.argtypes = []
     L.avl_tuning_variants.restype = i32
+    L.avl_tuning_variant_info.argtypes = [i32, vp]
+    L.avl_tuning_variant_info.restype = ctypes.c_int
     L.avl_last_variant.argtypes = []
     L.avl_last_variant.restype = i32
     L.avl_strerror.argtypes = [ctypes.c_int]
@@ -191,6 +193,15 @@ def set_tuning(variant: int = -1, graphs: bool = True) -> None:
 
 def tuning_variants() -> int:
     return int(lib.avl_tuning_variants())
+
+
+def variant_info(variant: int) -> dict:
+    """Shape of a trajectory kernel variant."""
+    info = (ctypes.c_int32 * 8)()
+    _check(lib.avl_tuning_variant_info(variant, ctypes.cast(info, ctypes.c_void_p)), "avl_tuning_variant_info")
+    keys = ("block", "iterations_per_epoch", "table_slots", "probes", "window", "retention", "waves_per_simd",
+            "slots_per_lane")
+    return dict(zip(keys, (int(v) for v in info)))
 
 
 def last_variant() -> int:

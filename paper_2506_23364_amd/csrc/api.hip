@@ -332,6 +332,14 @@ int avl_set_tuning(int32_t variant, int32_t graphs) {
 
 int32_t avl_tuning_variants(void) { return avl::trajectory_variants(); }
 
+int avl_tuning_variant_info(int32_t variant, int32_t* info) {
+    g_last_error.clear();
+    if (!info) return fail(AVL_EINVAL, "avl_tuning_variant_info: info is NULL");
+    if (!avl::trajectory_variant_info(variant, info))
+        return fail(AVL_EINVAL, "avl_tuning_variant_info: variant out of range");
+    return AVL_OK;
+}
+
 int32_t avl_mipmap_levels(int32_t H, int32_t W) {
     if (H < 1 || W < 1) return 0;
     int32_t n = 1;

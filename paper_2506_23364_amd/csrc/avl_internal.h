@@ -130,6 +130,7 @@ struct TrajArgs {
     float* __restrict__ rec_v2;                  // nullable: v^2 at each point (0 at the release point and
                                                  // at a rejected target)
     uint32_t* __restrict__ rec_end;              // (accepted steps << 2) | end (0 limit, 1 exit, 2 stop)
+    uint32_t slots_per_lane;                     // sizes a small problem's grid (set from the kernel variant)
 };
 
 struct LaunchShape {
@@ -240,5 +241,8 @@ hipError_t launch_finalize_vmax(uint32_t* vmax_bits, int64_t n, hipStream_t s);
 // Persistent-grid shape of kernel variant `variant` on the current device; number of variants.
 LaunchShape trajectory_shape(bool batched, int variant);
 int trajectory_variants();
+// info[0..7]: threads per block, iterations per epoch, table slots, probes, window top-up (x block), retention
+// threshold, waves per SIMD of the register budget, slots per lane; false for an index out of range.
+bool trajectory_variant_info(int variant, int32_t* info);
 
 }  // namespace avl

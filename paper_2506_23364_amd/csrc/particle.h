@@ -254,12 +254,12 @@ __device__ __forceinline__ uint64_t part_begin(uint64_t total, uint32_t p) {
     return (total / kChunk * p / kXcds) * kChunk;
 }
 
-// Blocks of a persistent grid that take part for `total` slots: enough for about kSlotsPerLane slots
-// per lane, at least one per XCD (measured: a 640,000-particle pass runs 2.3x faster on 8 slots per lane
+// Blocks of a persistent grid that take part for `total` slots: enough for about `spl` (default
+// kSlotsPerLane) slots per lane, at least one per XCD (measured: a 640,000-particle pass runs 2.3x faster on 8 slots per lane
 // than on the full grid's ~1).
 constexpr uint64_t kSlotsPerLane = 8;
-__device__ __forceinline__ uint64_t active_blocks(uint64_t total, int block_threads) {
-    const uint64_t per_block = (uint64_t)block_threads * kSlotsPerLane;
+__device__ __forceinline__ uint64_t active_blocks(uint64_t total, int block_threads, uint32_t spl = kSlotsPerLane) {
+    const uint64_t per_block = (uint64_t)block_threads * (spl ? spl : 1u);
     const uint64_t want = (total + per_block - 1) / per_block;
     return want > (uint64_t)kXcds ? want : (uint64_t)kXcds;
 }

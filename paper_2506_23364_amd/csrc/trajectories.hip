@@ -81,11 +81,12 @@ struct Control {
 // release cell when a run uses the stop, so its kernel carries no registers for them.
 // kKeep: table retention, 0 off; else a slot whose cell was entered at least kKeep times in the epoch
 // that ended stays in the table (its count and maximum reach the rasters at a later boundary).
+// kWpe: waves per SIMD the register budget is sized for (8: 64 VGPRs; 6: 80).
 // kRec: the recording instantiation (single run): the particles of the recorded range also write their
 // points and end records (a diagnostic; the other instantiations compile none of it).
-template <bool kBatch, bool kAlpha, int kBlock, int kFlush, int kTbl, int kProbes, int kWindow, int kKeep,
+template <bool kBatch, bool kAlpha, int kBlock, int kFlush, int kTbl, int kProbes, int kWindow, int kKeep, int kWpe = 8,
           bool kRec = false>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8)))
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWpe)))
 void k_trajectories(TrajArgs a) {
     static_assert(!(kRec && kBatch), "recording is for single runs");
     static_assert(kFlush % 2 == 0, "epochs keep the iteration parity");
@@ -103,8 +104,8 @@ void k_trajectories(TrajArgs a) {
     const uint64_t total = wave_bcast64(a.run_off[a.n_runs]);
     // A small problem runs on fewer blocks: with ~1 particle per lane every wave would issue the whole
     // iteration for a few live lanes, and the waves of a SIMD would share its issue slots until the
-    // longest path ends. Blocks past what gives each lane about kSlotsPerLane slots leave at once.
-    if ((uint64_t)blockIdx.x >= active_blocks(total, kBlock)) return;
+    // longest path ends. Blocks past what gives each lane about the variant's slots per lane leave at once.
+    if ((uint64_t)blockIdx.x >= active_blocks(total, kBlock, a.slots_per_lane)) return;
     const int W = a.W, H = a.H;
     const float fW = (float)W, fH = (float)H;
     const uint32_t xcd = xcd_id();
@@ -747,36 +748,52 @@ struct Variant {
     const void* single;
     const void* batch;
     int block;
+    uint32_t spl;  // particle slots per lane that size the grid of a small problem
+    int shape[7];  // block, iterations per epoch, table slots, probes, window, retention, waves per SIMD
     void (*launch_single)(dim3, dim3, hipStream_t, const TrajArgs&);        // runout-angle stop compiled in
     void (*launch_single_plain)(dim3, dim3, hipStream_t, const TrajArgs&);  // without it
     void (*launch_batch)(dim3, dim3, hipStream_t, const TrajArgs&);
 };
 
-template <bool B, bool A, int Blk, int F, int T, int Q, int M, int K>
+template <bool B, bool A, int Blk, int F, int T, int Q, int M, int K, int Wpe>
 void launch_t(dim3 g, dim3 t, hipStream_t s, const TrajArgs& a) {
-    hipLaunchKernelGGL((k_trajectories<B, A, Blk, F, T, Q, M, K>), g, t, 0, s, a);
+    hipLaunchKernelGGL((k_trajectories<B, A, Blk, F, T, Q, M, K, Wpe>), g, t, 0, s, a);
 }
 
-template <int Blk, int F, int T, int Q, int M, int K>
-constexpr Variant make_variant() {
-    return Variant{reinterpret_cast<const void*>(&k_trajectories<false, true, Blk, F, T, Q, M, K>),
-                   reinterpret_cast<const void*>(&k_trajectories<true, true, Blk, F, T, Q, M, K>), Blk,
-                   &launch_t<false, true, Blk, F, T, Q, M, K>, &launch_t<false, false, Blk, F, T, Q, M, K>,
-                   &launch_t<true, true, Blk, F, T, Q, M, K>};
+template <int Blk, int F, int T, int Q, int M, int K, int Wpe = 8>
+constexpr Variant make_variant(uint32_t spl = (uint32_t)kSlotsPerLane) {
+    return Variant{reinterpret_cast<const void*>(&k_trajectories<false, true, Blk, F, T, Q, M, K, Wpe>),
+                   reinterpret_cast<const void*>(&k_trajectories<true, true, Blk, F, T, Q, M, K, Wpe>), Blk, spl,
+                   {Blk, F, T, Q, M, K, Wpe},
+                   &launch_t<false, true, Blk, F, T, Q, M, K, Wpe>, &launch_t<false, false, Blk, F, T, Q, M, K, Wpe>,
+                   &launch_t<true, true, Blk, F, T, Q, M, K, Wpe>};
 }
 
 // candidates of the autotuner: (threads per block, iterations per epoch, table slots per block, probes,
-// window top-up in blocks of slots, retention threshold). Two blocks share a CU: 6144 slots of 12 bytes
-// are 72 KiB of LDS per block. The fifth keeps no slot across epochs.
+// window top-up in blocks of slots, retention threshold[, waves per SIMD of the register budget]) and the
+// slots per lane that size a small problem's grid. 1024-thread blocks run two per CU at eight waves per SIMD
+// (64 VGPRs; 6144 slots of 12 bytes are 72 KiB of LDS per block); the 768- and 512-thread shapes run at six
+// (80 VGPRs), two and three blocks per CU. The fifth keeps no slot across epochs.
 const Variant kVariants[] = {
-    make_variant<1024, 16, 6144, 4, 4, 1>(), make_variant<1024, 32, 6144, 4, 4, 2>(),
-    make_variant<1024, 16, 6144, 4, 4, 2>(), make_variant<1024, 32, 6144, 6, 4, 2>(),
-    make_variant<1024, 32, 4096, 4, 4, 0>(), make_variant<1024, 16, 6144, 8, 4, 2>(),
+    make_variant<1024, 16, 6144, 4, 4, 1>(),    make_variant<1024, 32, 6144, 4, 4, 2>(),
+    make_variant<1024, 16, 6144, 4, 4, 2>(),    make_variant<1024, 32, 6144, 6, 4, 2>(),
+    make_variant<1024, 32, 4096, 4, 4, 0>(),    make_variant<1024, 16, 6144, 8, 4, 2>(),
+    make_variant<768, 16, 6144, 8, 4, 2, 6>(),  make_variant<512, 16, 4096, 8, 4, 2, 6>(),
+    make_variant<1024, 16, 6144, 4, 4, 1>(2u),  make_variant<1024, 16, 6144, 4, 4, 1>(4u),
+    make_variant<1024, 16, 6144, 4, 4, 1>(16u),
 };
 
 }  // namespace
 
 int trajectory_variants() { return (int)(sizeof(kVariants) / sizeof(kVariants[0])); }
+
+bool trajectory_variant_info(int variant, int32_t* info) {
+    if (variant < 0 || variant >= trajectory_variants()) return false;
+    const Variant& v = kVariants[variant];
+    for (int i = 0; i < 7; ++i) info[i] = v.shape[i];
+    info[7] = (int32_t)v.spl;
+    return true;
+}
 
 LaunchShape trajectory_shape(bool batched, int variant) {
     if (variant < 0 || variant >= trajectory_variants()) variant = 0;
@@ -795,7 +812,7 @@ LaunchShape trajectory_shape(bool batched, int variant) {
 }
 
 hipError_t launch_trajectories_record(const TrajArgs& a, hipStream_t s) {
-    auto* k = &k_trajectories<false, true, 1024, 16, 6144, 4, 4, 1, true>;
+    auto* k = &k_trajectories<false, true, 1024, 16, 6144, 4, 4, 1, 8, true>;
     int dev = 0, cus = 256, per_cu = 1;
     if (hipGetDevice(&dev) == hipSuccess &&
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0 &&
@@ -806,19 +823,23 @@ hipError_t launch_trajectories_record(const TrajArgs& a, hipStream_t s) {
         cus = 256;
         per_cu = 1;
     }
-    hipLaunchKernelGGL(k, dim3(cus * per_cu), dim3(1024), 0, s, a);
+    TrajArgs b = a;
+    b.slots_per_lane = (uint32_t)kSlotsPerLane;
+    hipLaunchKernelGGL(k, dim3(cus * per_cu), dim3(1024), 0, s, b);
     return hipGetLastError();
 }
 
 hipError_t launch_trajectories(const TrajArgs& a, bool batched, const LaunchShape& shape, hipStream_t s) {
     const int vi = (shape.variant >= 0 && shape.variant < trajectory_variants()) ? shape.variant : 0;
     const Variant& v = kVariants[vi];
+    TrajArgs b = a;
+    b.slots_per_lane = v.spl;
     if (batched)
-        v.launch_batch(dim3(shape.grid), dim3(v.block), s, a);
+        v.launch_batch(dim3(shape.grid), dim3(v.block), s, b);
     else if (a.runout_angle)
-        v.launch_single(dim3(shape.grid), dim3(v.block), s, a);
+        v.launch_single(dim3(shape.grid), dim3(v.block), s, b);
     else
-        v.launch_single_plain(dim3(shape.grid), dim3(v.block), s, a);
+        v.launch_single_plain(dim3(shape.grid), dim3(v.block), s, b);
     return hipGetLastError();
 }
 

@@ -332,3 +332,20 @@ def _record(L, **kw):
 def test_record_rejects_bad_arguments(L, kw):
     assert _record(L, **kw) in (L.AVL_EINVAL, L.AVL_ENOMEM)
     assert L.lib.avl_last_error()
+
+
+def test_variant_info(L):
+    n = L.tuning_variants()
+    assert n >= 8
+    shapes = set()
+    for v in range(n):
+        info = L.variant_info(v)
+        assert info["block"] % 64 == 0 and info["table_slots"] % info["block"] == 0
+        assert info["slots_per_lane"] >= 1 and info["waves_per_simd"] in (6, 8)
+        shapes.add(tuple(info.values()))
+    assert len(shapes) == n  # every candidate differs
+    assert {L.variant_info(v)["block"] for v in range(n)} >= {512, 768, 1024}
+    assert len({L.variant_info(v)["slots_per_lane"] for v in range(n)}) >= 3
+    info = (ctypes.c_int32 * 8)()
+    assert L.lib.avl_tuning_variant_info(n, ctypes.cast(info, ctypes.c_void_p)) == L.AVL_EINVAL
+    assert L.lib.avl_tuning_variant_info(0, None) == L.AVL_EINVAL

@@ -216,10 +216,12 @@ def test_graph_replay_with_new_parameters(avl):
         avl.set_tuning(-1, True)
 
 
-def test_ensemble_full_size_sampled(avl):
-    """The full 16-tile x 64-parameter ensemble (1024 runs, 1024^2 tiles, 32 particles per cell, 2000 steps)
-    in the launch shape the benchmark times; the oracle checks the runs of the two smallest scenarios
-    under four parameter sets each, and the per-run statistics of all runs must add up to the batch's."""
+def test_ensemble_full_size(avl):
+    """The full 16-tile x 64-parameter ensemble (1024 runs, 1024^2 tiles, 32 particles per cell, 2000 steps) in
+    the launch shape the benchmark times: every run against the oracle's plain run of its (tile, scenario,
+    parameter set, seed, run id), run on all host threads, counts and statistics bit for bit and speeds within
+    1e-5 (so the largest scenarios, up to 26,397 release cells, are checked as well as the smallest)."""
+    from support import oracle_threads
     e = synth.make_ensemble()
     d = torch.from_numpy(e.dems).cuda()
     m = torch.from_numpy(e.masks).cuda()
@@ -227,18 +229,24 @@ def test_ensemble_full_size_sampled(avl):
                                    avl.runs_tensor(e.runs, "cuda"), e.particles_per_cell, e.step_limit)
     stats = host(res.stats)
     assert (host(res.status) == 0).all()
+    counts = host(res.counts)
+    vmax = host(res.vmax)
     sizes = e.masks.sum(axis=(1, 2))
-    small = np.argsort(sizes)[:2]
-    for t in small:
-        for p in (0, 21, 42, 63):
-            k = int(t) * 64 + p
-            run = e.runs[k]
-            ref = oracle.trajectories(e.dems[run[0]], e.masks[run[1]], e.cell_size, oracle.make_params(**e.params[p]),
-                                      e.particles_per_cell, e.step_limit, run[4], run[3])
-            assert np.array_equal(host(res.counts[k]), ref.counts), k
-            np.testing.assert_allclose(host(res.vmax[k]), ref.vmax, rtol=1e-5, atol=0)
-            assert list(stats[k]) == [ref.steps, ref.n_exit, ref.n_stop, ref.n_limit]
-    # each run released exactly its scenario's particles
+    print(f"ensemble: {len(e.runs)} runs, scenarios {sizes.min()}-{sizes.max()} cells, oracle on "
+          f"{oracle_threads.host_threads()} threads", flush=True)
+
+    def check(k):
+        t, sc, p, run_id, seed = e.runs[k]
+        ref = oracle.trajectories(e.dems[t], e.masks[sc], e.cell_size, oracle.make_params(**e.params[p]),
+                                  e.particles_per_cell, e.step_limit, seed, run_id)
+        ok_c = np.array_equal(counts[k], ref.counts)
+        ok_v = np.allclose(vmax[k], ref.vmax, rtol=1e-5, atol=0)
+        ok_s = list(stats[k]) == [ref.steps, ref.n_exit, ref.n_stop, ref.n_limit]
+        return ok_c and ok_v and ok_s
+
+    ok = oracle_threads.run_all(range(len(e.runs)), check)
+    bad = [k for k, v in enumerate(ok) if not v]
+    assert not bad, f"runs differing from the oracle: {bad[:20]}"
     ends = stats[:, 1:].sum(axis=1)
     expect = np.array([sizes[r[1]] * e.particles_per_cell for r in e.runs])
     assert np.array_equal(ends, expect)

@@ -215,9 +215,11 @@ def test_particles_per_cell_sweep(avl, P):
     both(avl, dem, mask, 10.0, dict(mu=0.2, xi=2000.0, randomness=0.3), P, 300, 77, 5, f"P={P}")
 
 
-def test_alpine_full_size_sampled(avl):
-    """Full 2048^2 alpine tile at 256 particles per cell, in the launch shape the benchmark times: the
-    oracle runs every 97th release cell; the GPU runs that sample, its complement and the whole mask."""
+def test_alpine_full_size(avl):
+    """Full 2048^2 alpine tile at 256 particles per cell, in the launch shape the benchmark times: the whole
+    pass against the oracle's whole pass (all host threads); then the GPU runs every 97th release cell, its
+    complement and the whole mask, whose rasters must superpose."""
+    from support import oracle_threads
     w = synth.make_workload("alpine")
     nrm = oracle.normals(w.dem, w.cell_size)
     mask = oracle.release_mask(nrm, w.dem, w.slope_min_deg, w.slope_max_deg, w.z_min, w.z_max)
@@ -231,31 +233,42 @@ def test_alpine_full_size_sampled(avl):
                       "alpine sample")
     got_r = gpu_run(avl, w.dem, rest, w.cell_size, w.params, w.particles_per_cell, w.step_limit, w.seed)
     got_f = gpu_run(avl, w.dem, mask, w.cell_size, w.params, w.particles_per_cell, w.step_limit, w.seed)
+    counts, vmax, stats = oracle_threads.full_pass(w.dem, mask, w.cell_size, w.params, w.particles_per_cell,
+                                                   w.step_limit, w.seed)
+    assert np.array_equal(got_f[0], counts)
+    np.testing.assert_allclose(got_f[1], vmax, rtol=1e-5, atol=0)
+    assert list(got_f[2]) == stats
     assert np.array_equal(got_f[0], got_s[0] + got_r[0])
     assert np.array_equal(got_f[1], np.maximum(got_s[1], got_r[1]))
     assert np.array_equal(got_f[2], got_s[2] + got_r[2])
 
 
-def test_large_region_full_size_sampled(avl):
-    """Full 8192^2 region at 5 m (256 MB DEM, ~1.4e6 release cells, 64 particles per cell, step limit
-    8000) in the benchmark's launch shape: the oracle runs every 1009th release cell; the GPU runs that
-    sample, its complement and the whole mask, whose rasters must be the sum (counts, statistics) and the
-    maximum (speeds) of the two parts."""
+def test_large_region_full_size(avl):
+    """Full 8192^2 region at 5 m (256 MB DEM, ~1.4e6 release cells, 64 particles per cell, step limit 8000) in
+    the benchmark's launch shape: the whole pass against the oracle's whole pass (run on all host threads),
+    counts and statistics bit for bit, speeds within 1e-5; and the superposition of a 1-in-64 sample of the
+    release cells and its complement equal to the whole pass."""
+    from support import oracle_threads
     w = synth.make_workload("large")
     nrm = oracle.normals(w.dem, w.cell_size)
     mask = oracle.release_mask(nrm, w.dem, w.slope_min_deg, w.slope_max_deg, w.z_min, w.z_max)
     del nrm
     cells = np.flatnonzero(mask)
     assert 5e5 < len(cells) < 3e6
+    got_f = gpu_run(avl, w.dem, mask, w.cell_size, w.params, w.particles_per_cell, w.step_limit, w.seed)
+    print(f"large region: {len(cells)} release cells, oracle on {oracle_threads.host_threads()} threads", flush=True)
+    counts, vmax, stats = oracle_threads.full_pass(w.dem, mask, w.cell_size, w.params, w.particles_per_cell,
+                                                   w.step_limit, w.seed)
+    assert np.array_equal(got_f[0], counts)
+    np.testing.assert_allclose(got_f[1], vmax, rtol=1e-5, atol=0)
+    assert list(got_f[2]) == stats
+    del counts, vmax
     sample = np.zeros(mask.size, np.uint8)
-    sample[cells[::1009]] = 1
+    sample[cells[::64]] = 1
     sample = sample.reshape(mask.shape)
     rest = (mask & (1 - sample)).astype(np.uint8)
-    got_s, ref = both(avl, w.dem, sample, w.cell_size, w.params, w.particles_per_cell, w.step_limit, w.seed, 0,
-                      "large sample")
-    del ref
+    got_s = gpu_run(avl, w.dem, sample, w.cell_size, w.params, w.particles_per_cell, w.step_limit, w.seed)
     got_r = gpu_run(avl, w.dem, rest, w.cell_size, w.params, w.particles_per_cell, w.step_limit, w.seed)
-    got_f = gpu_run(avl, w.dem, mask, w.cell_size, w.params, w.particles_per_cell, w.step_limit, w.seed)
     assert np.array_equal(got_f[0], got_s[0] + got_r[0])
     assert np.array_equal(got_f[1], np.maximum(got_s[1], got_r[1]))
     assert np.array_equal(got_f[2], got_s[2] + got_r[2])
