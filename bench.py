@@ -196,6 +196,36 @@ def kernel_time_ms(avl, torch, fn, reps: int) -> float:
     return float(np.median(ms))
 
 
+def tail_probe(avl, torch, w, dem, mask, variant: int) -> dict:
+    """One more pass with the library's tail probe: per block its start, the moment it finds no particle slot
+    left anywhere, and its end (GPU real-time clock, 100 MHz). The tail is the time from the first block
+    running out of slots to the kernel's end, during which paths started earlier finish on fewer lanes."""
+    grid = avl.trajectory_grid(variant)
+    buf = torch.zeros(3 * max(grid, 1), dtype=torch.uint64, device="cuda")
+    avl.set_probe(buf)
+    try:
+        avl.trajectories(dem, mask, w.cell_size, avl.Params.make(**w.params), w.particles_per_cell, w.step_limit,
+                         w.seed)
+        torch.cuda.synchronize()
+    finally:
+        avl.set_probe(None)
+    t = buf.view(torch.int64).cpu().numpy().reshape(-1, 3).astype(np.int64)
+    t = t[t[:, 2] > 0]
+    if t.size == 0:
+        return {"blocks": 0}
+    t0 = t[:, 0].min()
+    ms = (t - t0) * 1e-5  # 100 MHz ticks -> ms
+    dry = ms[t[:, 1] > 0, 1]
+    end = ms[:, 2]
+    first_dry = float(dry.min()) if dry.size else None
+    return {"blocks": int(t.shape[0]), "ms_kernel_span": float(end.max()),
+            "ms_first_block_out_of_slots": first_dry,
+            "ms_median_block_out_of_slots": float(np.median(dry)) if dry.size else None,
+            "ms_tail_after_first_out_of_slots": float(end.max() - first_dry) if dry.size else None,
+            "ms_block_end_p10_p50_p90": [float(np.percentile(end, q)) for q in (10, 50, 90)],
+            "tail_fraction": float((end.max() - first_dry) / end.max()) if dry.size else None}
+
+
 def roofline_leg(avl, torch, w, dem, mask, run: dict, reps: int = 3) -> dict:
     """Ceilings of the trajectory kernel measured on this GPU: the pass is recorded (every particle's points
     and v^2), its 2x2 gathers and cell visits are laid out in wave order (64 neighbouring particles, step by
@@ -231,6 +261,7 @@ def roofline_leg(avl, torch, w, dem, mask, run: dict, reps: int = 3) -> dict:
     steps = run["steps_per_pass"]
     t_kernel = run["kernel_ms"]
     variant = run["variant"]
+    tail = tail_probe(avl, torch, w, dem, mask, variant)
     gather_ceiling = steps / (t_gather * 1e-3)
     atomic_ceiling = steps / (t_atomic * 1e-3)
     achieved = steps / (t_kernel * 1e-3)
@@ -274,6 +305,7 @@ def roofline_leg(avl, torch, w, dem, mask, run: dict, reps: int = 3) -> dict:
         "kernel_ms": t_kernel,
         "ceilings": ceilings,
         "recorded_pass_equals_timed_pass": same,
+        "tail": tail,
         "hbm_view": {"bytes_per_particle_step": BYTES_PER_STEP, "achieved_GBs": BYTES_PER_STEP * steps / t_kernel / 1e6,
                      "peak_GBs": HBM_PEAK_GBS},
     }

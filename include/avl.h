@@ -359,6 +359,15 @@ AVL_API int32_t avl_last_variant(void);
 AVL_API int avl_set_profiling(int32_t enable);
 AVL_API int avl_last_kernel_ms(float* ms);
 
+/* Tail probe (diagnostics; not for concurrent callers). With blocks3 set (a device buffer of 3 * n_blocks
+ * uint64), every later uncaptured single-run trajectory call whose persistent grid has at most n_blocks blocks
+ * writes, per block b, the GPU's 100 MHz real-time clock at the block's start (blocks3[3b]), when the block
+ * first finds no particle slot left in its window or in any queue (3b + 1; 0 if it never does, i.e. if it left
+ * at once) and at its end (3b + 2); the caller zeroes the buffer beforehand. blocks3 = NULL stops it.
+ * avl_trajectory_grid gives the grid (blocks) of a kernel variant on the current device, -1 if out of range. */
+AVL_API int avl_set_probe(uint64_t* blocks3, uint64_t n_blocks);
+AVL_API int32_t avl_trajectory_grid(int32_t variant);
+
 /* Name of an error code. Never NULL. */
 AVL_API const char* avl_strerror(int code);
 

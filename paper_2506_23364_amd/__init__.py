@@ -128,6 +128,10 @@ def _load() -> ctypes.CDLL:
     L.avl_tuning_variants.restype = i32
     L.avl_tuning_variant_info.argtypes = [i32, vp]
     L.avl_tuning_variant_info.restype = ctypes.c_int
+    L.avl_set_probe.argtypes = [vp, u64]
+    L.avl_set_probe.restype = ctypes.c_int
+    L.avl_trajectory_grid.argtypes = [i32]
+    L.avl_trajectory_grid.restype = i32
     L.avl_last_variant.argtypes = []
     L.avl_last_variant.restype = i32
     L.avl_strerror.argtypes = [ctypes.c_int]
@@ -202,6 +206,20 @@ def variant_info(variant: int) -> dict:
     keys = ("block", "iterations_per_epoch", "table_slots", "probes", "window", "retention", "waves_per_simd",
             "slots_per_lane")
     return dict(zip(keys, (int(v) for v in info)))
+
+
+def set_probe(buf: "torch.Tensor | None") -> None:
+    """Tail probe of later single-run trajectory calls: buf (uint64, 3 per block of the grid, zeroed by the
+    caller) gets each block's start, slots-exhausted and end times on the GPU's 100 MHz clock; None stops it."""
+    if buf is None:
+        _check(lib.avl_set_probe(None, 0), "avl_set_probe")
+        return
+    _need(buf, "probe", torch.uint64, 1)
+    _check(lib.avl_set_probe(buf.data_ptr(), buf.numel() // 3), "avl_set_probe")
+
+
+def trajectory_grid(variant: int) -> int:
+    return int(lib.avl_trajectory_grid(variant))
 
 
 def last_variant() -> int:

@@ -145,8 +145,13 @@ thread_local int32_t g_last_variant = -1;
 
 // kernel timing (avl_set_profiling): events around the last uncaptured trajectory launch
 bool g_profile = false;
+// tail probe (avl_set_probe): device buffer of 3 u64 per block of the trajectory grid, or null
+unsigned long long* g_probe = nullptr;
+uint64_t g_probe_blocks = 0;
 bool g_profile_valid = false;
 hipEvent_t g_prof_ev[2] = {nullptr, nullptr};
+
+bool capturing(hipStream_t s);
 
 // Enqueues `launch` (one kernel), bracketed by the timing events when profiling is on and the stream is
 // not being captured.
@@ -164,9 +169,12 @@ hipError_t timed(hipStream_t s, Launch launch) {
     return hipSuccess;
 }
 
-// The trajectory kernel, timed as above.
+// The trajectory kernel, timed as above; an uncaptured single run also writes the tail probe when one is set
+// and holds the grid.
 hipError_t timed_launch(const avl::TrajArgs& a, bool batched, const avl::LaunchShape& sh, hipStream_t s) {
-    return timed(s, [&] { return avl::launch_trajectories(a, batched, sh, s); });
+    avl::TrajArgs b = a;
+    if (!batched && g_probe && (uint64_t)sh.grid <= g_probe_blocks && !capturing(s)) b.probe = g_probe;
+    return timed(s, [&] { return avl::launch_trajectories(b, batched, sh, s); });
 }
 
 __attribute__((format(printf, 2, 3))) int fail(int code, const char* fmt, ...) {
@@ -409,6 +417,18 @@ int avl_set_profiling(int32_t enable) {
     g_profile = enable != 0;
     g_profile_valid = false;
     return AVL_OK;
+}
+
+int avl_set_probe(uint64_t* blocks3, uint64_t n_blocks) {
+    g_last_error.clear();
+    g_probe = reinterpret_cast<unsigned long long*>(blocks3);
+    g_probe_blocks = blocks3 ? n_blocks : 0;
+    return AVL_OK;
+}
+
+int32_t avl_trajectory_grid(int32_t variant) {
+    if (variant < 0 || variant >= avl::trajectory_variants()) return -1;
+    return avl::trajectory_shape(false, variant).grid;
 }
 
 int avl_last_kernel_ms(float* ms) {

@@ -131,6 +131,8 @@ struct TrajArgs {
                                                  // at a rejected target)
     uint32_t* __restrict__ rec_end;              // (accepted steps << 2) | end (0 limit, 1 exit, 2 stop)
     uint32_t slots_per_lane;                     // sizes a small problem's grid (set from the kernel variant)
+    unsigned long long* __restrict__ probe;      // nullable: 3 per block, the real-time clock at the block's
+                                                 // start, when it runs out of slots, and at its end
 };
 
 struct LaunchShape {

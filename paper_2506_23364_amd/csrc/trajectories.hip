@@ -73,6 +73,7 @@ struct Control {
     uint32_t take;                // window slots handed out this epoch (grows by 64 per take)
     uint32_t busy[2];             // waves with work left, per epoch parity
     uint32_t part, tried, empty;  // the window's own walk over the XCD partitions
+    uint32_t dry;                 // the tail probe has seen the block run out of slots
     unsigned long long left;      // slots left in the partition after the window's last top-up
 };
 
@@ -172,6 +173,7 @@ void k_trajectories(TrajArgs a) {
             ctl.tried = 0;
             ctl.empty = total == 0 ? 1u : 0u;
             ctl.left = ~0ull;
+            ctl.dry = 0u;
         }
         const uint32_t l0 = ctl.len[0], l1 = ctl.len[1];
         const uint32_t t = min(ctl.take, l0 + l1);
@@ -197,7 +199,13 @@ void k_trajectories(TrajArgs a) {
             ctl.left = left;
         }
     };
-    if (threadIdx.x == 0) refill_window(true);
+    // tail probe (diagnostics): per block the real-time clock at its start, when it first finds no slot left
+    // in its window nor in any queue, and at its end
+    unsigned long long* const probe = a.probe ? a.probe + 3 * (size_t)blockIdx.x : nullptr;
+    if (threadIdx.x == 0) {
+        if (probe) probe[0] = __builtin_amdgcn_s_memrealtime();
+        refill_window(true);
+    }
     __syncthreads();
 
     // The wave's run: its constants in scalar registers and its padded DEM tile through a buffer
@@ -539,6 +547,10 @@ void k_trajectories(TrajArgs a) {
         if (threadIdx.x == 0) {
             ctl.busy[(epoch + 1) & 1u] = 0u;
             refill_window(false);
+            if (probe && !ctl.dry && ctl.empty && ctl.len[0] == 0u) {
+                ctl.dry = 1u;
+                probe[1] = __builtin_amdgcn_s_memrealtime();
+            }
         }
         // flush this thread's kPer slots: all raster reads of the max check are issued before any is
         // used, so the flush costs one memory round trip rather than one per slot. The last boundary
@@ -583,6 +595,7 @@ void k_trajectories(TrajArgs a) {
         if (ctl.busy[epoch & 1u] == 0u) break;
     }
     flush_stats();
+    if (probe && threadIdx.x == 0) probe[2] = __builtin_amdgcn_s_memrealtime();
 }
 
 // ------------------------------------------------------------------------------------------ start records
@@ -773,14 +786,17 @@ constexpr Variant make_variant(uint32_t spl = (uint32_t)kSlotsPerLane) {
 // window top-up in blocks of slots, retention threshold[, waves per SIMD of the register budget]) and the
 // slots per lane that size a small problem's grid. 1024-thread blocks run two per CU at eight waves per SIMD
 // (64 VGPRs; 6144 slots of 12 bytes are 72 KiB of LDS per block); the 768- and 512-thread shapes run at six
-// (80 VGPRs), two and three blocks per CU. The fifth keeps no slot across epochs.
+// (80 VGPRs), two and three blocks per CU, and the 384-thread shape at six with four blocks per CU. The fifth
+// keeps no slot across epochs.
 const Variant kVariants[] = {
     make_variant<1024, 16, 6144, 4, 4, 1>(),    make_variant<1024, 32, 6144, 4, 4, 2>(),
     make_variant<1024, 16, 6144, 4, 4, 2>(),    make_variant<1024, 32, 6144, 6, 4, 2>(),
     make_variant<1024, 32, 4096, 4, 4, 0>(),    make_variant<1024, 16, 6144, 8, 4, 2>(),
     make_variant<768, 16, 6144, 8, 4, 2, 6>(),  make_variant<512, 16, 4096, 8, 4, 2, 6>(),
     make_variant<1024, 16, 6144, 4, 4, 1>(2u),  make_variant<1024, 16, 6144, 4, 4, 1>(4u),
-    make_variant<1024, 16, 6144, 4, 4, 1>(16u),
+    make_variant<1024, 16, 6144, 4, 4, 1>(16u), make_variant<512, 32, 4096, 8, 4, 2, 6>(),
+    make_variant<512, 16, 4096, 8, 4, 1, 6>(),  make_variant<768, 16, 6144, 4, 4, 1, 6>(),
+    make_variant<384, 16, 3072, 8, 4, 2, 6>(),
 };
 
 }  // namespace

@@ -349,3 +349,9 @@ def test_variant_info(L):
     info = (ctypes.c_int32 * 8)()
     assert L.lib.avl_tuning_variant_info(n, ctypes.cast(info, ctypes.c_void_p)) == L.AVL_EINVAL
     assert L.lib.avl_tuning_variant_info(0, None) == L.AVL_EINVAL
+
+
+def test_probe_switch_and_grid_query(L):
+    assert L.lib.avl_set_probe(None, 0) == L.AVL_OK
+    assert L.lib.avl_trajectory_grid(-1) == -1
+    assert L.lib.avl_trajectory_grid(L.tuning_variants()) == -1

@@ -272,3 +272,25 @@ def test_large_region_full_size(avl):
     assert np.array_equal(got_f[0], got_s[0] + got_r[0])
     assert np.array_equal(got_f[1], np.maximum(got_s[1], got_r[1]))
     assert np.array_equal(got_f[2], got_s[2] + got_r[2])
+
+
+def test_tail_probe_times_every_block_and_leaves_the_pass_unchanged(avl):
+    w = synth.make_workload("tiny")
+    mask = oracle.release_mask(oracle.normals(w.dem, w.cell_size), w.dem, w.slope_min_deg, w.slope_max_deg, w.z_min,
+                               w.z_max)
+    plain = gpu_run(avl, w.dem, mask, w.cell_size, w.params, 8, 600, w.seed)
+    grid = max(avl.trajectory_grid(v) for v in range(avl.tuning_variants()))
+    buf = torch.zeros(3 * grid, dtype=torch.uint64, device="cuda")
+    avl.set_probe(buf)
+    try:
+        got = gpu_run(avl, w.dem, mask, w.cell_size, w.params, 8, 600, w.seed)
+    finally:
+        avl.set_probe(None)
+    for a, b in zip(got, plain):
+        assert np.array_equal(a, b)
+    t = host(buf).view(np.int64).reshape(-1, 3)
+    t = t[t[:, 0] > 0]
+    assert t.shape[0] > 0
+    assert (t[:, 2] >= t[:, 0]).all()
+    dry = t[t[:, 1] > 0]
+    assert dry.shape[0] > 0 and (dry[:, 1] >= dry[:, 0]).all() and (dry[:, 2] >= dry[:, 1]).all()
