@@ -305,6 +305,64 @@ hipError_t choose_variant(const avl::TrajArgs& a, bool batched, const std::vecto
     return hipSuccess;
 }
 
+// The same for the smooth kernels' grid variants: `launch(v)` enqueues variant v after `zero()` re-zeroes what
+// it accumulates into; the fastest of kTuneRounds interleaved timings is kept per key (kind 2: forward, 3:
+// adjoint). Under capture, or with may_tune false, an uncached key takes variant 0.
+template <class Zero, class Launch>
+hipError_t choose_smooth(const std::vector<int64_t>& key, int nv, hipStream_t s, Zero zero, Launch launch, int* variant,
+                         bool may_tune = true) {
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto it = g_best.find(key);
+        if (it != g_best.end()) {
+            *variant = it->second;
+            return hipSuccess;
+        }
+    }
+    if (!may_tune || capturing(s) || nv <= 1) {
+        *variant = 0;
+        return hipSuccess;
+    }
+    hipEvent_t e0, e1;
+    hipError_t e;
+    if ((e = hipEventCreate(&e0)) != hipSuccess) return e;
+    if ((e = hipEventCreate(&e1)) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return e;
+    }
+    constexpr int kTuneRounds = 3;
+    std::vector<float> vmin(nv, 1e30f);
+    for (int round = 0; round < kTuneRounds && e == hipSuccess; ++round) {
+        for (int v = 0; v < nv; ++v) {
+            if ((e = zero()) != hipSuccess) break;
+            if ((e = hipEventRecord(e0, s)) != hipSuccess) break;
+            if ((e = launch(v)) != hipSuccess) break;
+            if ((e = hipEventRecord(e1, s)) != hipSuccess) break;
+            if ((e = hipEventSynchronize(e1)) != hipSuccess) break;
+            float ms = 0.0f;
+            if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
+            if (ms < vmin[v]) vmin[v] = ms;
+        }
+    }
+    constexpr float kTuneMargin = 0.98f;
+    int best = 0;
+    for (int v = 1; v < nv; ++v)
+        if (vmin[v] < vmin[best] * kTuneMargin) best = v;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_best[key] = best;
+    *variant = best;
+    return hipSuccess;
+}
+
+std::vector<int64_t> smooth_key(int kind, int64_t n, int64_t cap, uint32_t P, uint32_t S) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    return {dev, kind, ilog2((uint64_t)n), ilog2((uint64_t)cap + 1), ilog2(P), ilog2((uint64_t)S + 1)};
+}
+
 // ------------------------------------------------------------------ graph cache of batched calls
 struct GraphEntry {
     hipGraphExec_t exec;
@@ -893,14 +951,24 @@ int avl_trajectories_smooth(const float* dem, const uint8_t* mask, const float* 
                                     particles_per_cell, false, sw.w.runs, sw.w.run_off, status, s,
                                     max_release_cells)) != hipSuccess)
         return hip_fail(e, "avl_trajectories_smooth: run setup");
-    if ((e = avl::launch_fill_u32(reinterpret_cast<uint32_t*>(deposit_q), 0u, 2 * n, s)) != hipSuccess ||
-        (vel && (e = avl::launch_fill_u32(reinterpret_cast<uint32_t*>(velocity_q), 0u, 2 * n, s)) != hipSuccess) ||
-        (e = avl::launch_fill_u64(sw.w.queues, 0ull, avl::kXcds, s)) != hipSuccess ||
-        (e = avl::launch_fill_u64(a.stats, 0ull, 4, s)) != hipSuccess)
-        return hip_fail(e, "avl_trajectories_smooth: zero");
+    auto zero = [&]() -> hipError_t {
+        hipError_t z;
+        if ((z = avl::launch_fill_u32(reinterpret_cast<uint32_t*>(deposit_q), 0u, 2 * n, s)) != hipSuccess) return z;
+        if (vel && (z = avl::launch_fill_u32(reinterpret_cast<uint32_t*>(velocity_q), 0u, 2 * n, s)) != hipSuccess)
+            return z;
+        if ((z = avl::launch_fill_u64(sw.w.queues, 0ull, avl::kXcds, s)) != hipSuccess) return z;
+        return avl::launch_fill_u64(a.stats, 0ull, 4, s);
+    };
     if ((e = avl::launch_pad_dem(dem, H, W, sw.dem_pad, s)) != hipSuccess)
         return hip_fail(e, "avl_trajectories_smooth: padded DEM");
-    if ((e = avl::launch_smooth_forward(a, s)) != hipSuccess) return hip_fail(e, "avl_trajectories_smooth: launch");
+    int variant = 0;
+    if ((e = choose_smooth(smooth_key(2, n, max_release_cells, particles_per_cell, step_limit),
+                           avl::smooth_forward_variants(), s, zero,
+                           [&](int v) { return avl::launch_smooth_forward(a, v, s); }, &variant)) != hipSuccess)
+        return hip_fail(e, "avl_trajectories_smooth: autotune");
+    if ((e = zero()) != hipSuccess) return hip_fail(e, "avl_trajectories_smooth: zero");
+    if ((e = avl::launch_smooth_forward(a, variant, s)) != hipSuccess)
+        return hip_fail(e, "avl_trajectories_smooth: launch");
     if (deposit && (e = avl::launch_q_to_float(a.dep_q, n, deposit, s)) != hipSuccess)
         return hip_fail(e, "avl_trajectories_smooth: deposit");
     if (vel && velocity && (e = avl::launch_q_to_float(a.vel_q, n, velocity, s)) != hipSuccess)
@@ -928,11 +996,21 @@ int avl_trajectories_backward(const float* dem, const uint8_t* mask, const float
                                     max_release_cells, sw);
     a.gD = grad_deposit;
     hipError_t e;
-    if ((e = avl::launch_fill_u32(reinterpret_cast<uint32_t*>(dmass), 0u, n, s)) != hipSuccess ||
-        (e = avl::launch_fill_u64(sw.w.queues, 0ull, avl::kXcds, s)) != hipSuccess)
-        return hip_fail(e, "avl_trajectories_backward: zero");
-    if ((e = avl::launch_smooth_backward(a, sw.w.n_cells, dmass, max_release_cells, sw.part, dparams, s)) !=
+    auto zero = [&]() -> hipError_t {
+        hipError_t z;
+        if ((z = avl::launch_fill_u32(reinterpret_cast<uint32_t*>(dmass), 0u, n, s)) != hipSuccess) return z;
+        return avl::launch_fill_u64(sw.w.queues, 0ull, avl::kXcds, s);
+    };
+    int variant = 0;
+    if ((e = choose_smooth(smooth_key(3, n, max_release_cells, particles_per_cell, step_limit),
+                           avl::smooth_backward_variants(), s, zero,
+                           [&](int v) { return avl::launch_smooth_backward_kernel(a, v, s); }, &variant)) !=
         hipSuccess)
+        return hip_fail(e, "avl_trajectories_backward: autotune");
+    if ((e = zero()) != hipSuccess) return hip_fail(e, "avl_trajectories_backward: zero");
+    if ((e = avl::launch_smooth_backward_kernel(a, variant, s)) != hipSuccess ||
+        (e = avl::launch_smooth_reductions(a, sw.w.n_cells, dmass, max_release_cells, sw.part, dparams, s)) !=
+            hipSuccess)
         return hip_fail(e, "avl_trajectories_backward: launch");
     if (per_particle && a.cap &&
         (e = hipMemcpyAsync(per_particle, sw.pp, 4 * (size_t)a.cap * sizeof(float), hipMemcpyDeviceToDevice, s)) !=

@@ -224,15 +224,22 @@ struct SmoothArgs {
     float g2, g2dl, xi, h;                  // 2g, 2g * dl (dl = step_cells * cell_size), xi, h
     const float* dem_pad;                   // the DEM with a replicated border, (H + 2) x (W + 2)
     uint32_t pad_bytes;                     // its bytes, < 2^32
+    uint32_t spl;                           // particle slots per lane of a small problem (set by the launchers)
 };
 
 
 size_t smooth_checkpoints(uint32_t S);
 size_t smooth_scratch_bytes();
 size_t smooth_reduce_blocks(unsigned long long cap);
-hipError_t launch_smooth_forward(const SmoothArgs& a, hipStream_t s);
-hipError_t launch_smooth_backward(const SmoothArgs& a, const int32_t* n_cells, float* dmass, int64_t n_grid,
-                                  double* part, double* dparams, hipStream_t s);
+// Kernel variants of the smooth forward and of the adjoint (grid shapes only: every variant gives the same
+// results); the library's tuner picks one per problem size.
+int smooth_forward_variants();
+int smooth_backward_variants();
+hipError_t launch_smooth_forward(const SmoothArgs& a, int variant, hipStream_t s);
+hipError_t launch_smooth_backward_kernel(const SmoothArgs& a, int variant, hipStream_t s);
+// the adjoint's reductions after its kernel: dL/dparams and dL/dmass
+hipError_t launch_smooth_reductions(const SmoothArgs& a, const int32_t* n_cells, float* dmass, int64_t n_grid,
+                                    double* part, double* dparams, hipStream_t s);
 hipError_t launch_q_to_float(const unsigned long long* q, int64_t n, float* out, hipStream_t s);
 // calibration loss: gD = c (D - T) and L = sum (D - T)^2 / N (binary64, fixed order) into *loss
 hipError_t launch_mse_grad(const float* dep, const float* target, int64_t n, float c, float* gD, double* part,

@@ -211,8 +211,11 @@ __device__ __forceinline__ float mass_per_particle(const float* __restrict__ mas
 }  // namespace
 
 
-__global__ __launch_bounds__(kSmoothBlock) void k_smooth_forward(SmoothArgs a) {
-    if ((uint64_t)blockIdx.x >= active_blocks(a.run_off[1], kSmoothBlock)) return;  // small problems: fewer blocks
+// kBlk threads per block share one deposit table; a.spl particle slots per lane size the grid of a small
+// problem (its variants: 256 threads at 8 slots per lane suit short paths, larger blocks at 2 long ones).
+template <int kBlk>
+__global__ __launch_bounds__(kBlk) void k_smooth_forward(SmoothArgs a) {
+    if ((uint64_t)blockIdx.x >= active_blocks(a.run_off[1], kBlk, a.spl)) return;  // small problems: fewer blocks
     const int lane = threadIdx.x & (kWave - 1);
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
     const RunConst rc = uniform_run(a.runs[0]);
@@ -222,7 +225,7 @@ __global__ __launch_bounds__(kSmoothBlock) void k_smooth_forward(SmoothArgs a) {
     disp.init(wave_bcast64(a.run_off[1]), xcd_id());
     const size_t cplane = (size_t)a.C * a.cap;
     __shared__ DepTable dep;
-    for (int k = threadIdx.x; k < kDepSlots; k += kSmoothBlock) {
+    for (int k = threadIdx.x; k < kDepSlots; k += kBlk) {
         dep.tag[k] = kDepEmpty;
         dep.val[k] = 0ull;
     }
@@ -293,7 +296,7 @@ __global__ __launch_bounds__(kSmoothBlock) void k_smooth_forward(SmoothArgs a) {
     }
     // every wave of the block is done: the table's sums go to the raster
     __syncthreads();
-    for (int k = threadIdx.x; k < kDepSlots; k += kSmoothBlock)
+    for (int k = threadIdx.x; k < kDepSlots; k += kBlk)
         if (dep.tag[k] != kDepEmpty && dep.val[k] != 0ull) atomicAdd(a.dep_q + dep.tag[k], dep.val[k]);
     const uint64_t s0 = wave_sum64(st_steps), s1 = wave_sum64(st_exit), s2 = wave_sum64(st_stop);
     const uint64_t s3 = wave_sum64(st_limit);
@@ -306,7 +309,7 @@ __global__ __launch_bounds__(kSmoothBlock) void k_smooth_forward(SmoothArgs a) {
 }
 
 __global__ __launch_bounds__(kSmoothBlock) void k_smooth_backward(SmoothArgs a) {
-    if ((uint64_t)blockIdx.x >= active_blocks(a.run_off[1], kSmoothBlock)) return;  // small problems: fewer blocks
+    if ((uint64_t)blockIdx.x >= active_blocks(a.run_off[1], kSmoothBlock, a.spl)) return;  // small problems: fewer blocks
     const int lane = threadIdx.x & (kWave - 1);
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
     const RunConst rc = uniform_run(a.runs[0]);
@@ -551,22 +554,56 @@ size_t smooth_checkpoints(uint32_t S) { return S == 0 ? 0 : (S + kCkpt - 1) / kC
 size_t smooth_scratch_bytes() { return (size_t)kCkpt * kBackwardGrid * kSmoothBlock * sizeof(float2); }
 size_t smooth_reduce_blocks(unsigned long long cap) { return (size_t)((cap + kReduceChunk - 1) / kReduceChunk) + 1; }
 
-hipError_t launch_smooth_forward(const SmoothArgs& a, hipStream_t s) {
+namespace {
+
+struct SmoothVariant {
+    int block;
+    uint32_t spl;
+};
+// forward candidates: (threads per block, slots per lane); backward: slots per lane at 256 threads
+constexpr SmoothVariant kFwdVariants[] = {{256, 8}, {1024, 2}, {512, 2}};
+constexpr uint32_t kBwdSpl[] = {8, 2};
+
+template <int kBlk>
+void launch_fwd(const SmoothArgs& a, hipStream_t s) {
     int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
         cus = 256;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k_smooth_forward),
-                                                     kSmoothBlock, 0) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&k_smooth_forward<kBlk>),
+                                                     kBlk, 0) != hipSuccess ||
         per_cu <= 0)
         per_cu = 1;
-    hipLaunchKernelGGL(k_smooth_forward, dim3(cus * per_cu), dim3(kSmoothBlock), 0, s, a);
+    hipLaunchKernelGGL(k_smooth_forward<kBlk>, dim3(cus * per_cu), dim3(kBlk), 0, s, a);
+}
+
+}  // namespace
+
+int smooth_forward_variants() { return (int)(sizeof(kFwdVariants) / sizeof(kFwdVariants[0])); }
+int smooth_backward_variants() { return (int)(sizeof(kBwdSpl) / sizeof(kBwdSpl[0])); }
+
+hipError_t launch_smooth_forward(const SmoothArgs& a, int variant, hipStream_t s) {
+    if (variant < 0 || variant >= smooth_forward_variants()) variant = 0;
+    SmoothArgs b = a;
+    b.spl = kFwdVariants[variant].spl;
+    switch (kFwdVariants[variant].block) {
+        case 1024: launch_fwd<1024>(b, s); break;
+        case 512: launch_fwd<512>(b, s); break;
+        default: launch_fwd<256>(b, s); break;
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_smooth_backward(const SmoothArgs& a, const int32_t* n_cells, float* dmass, int64_t n_grid,
-                                  double* part, double* dparams, hipStream_t s) {
-    hipLaunchKernelGGL(k_smooth_backward, dim3(kBackwardGrid), dim3(kSmoothBlock), 0, s, a);
+hipError_t launch_smooth_backward_kernel(const SmoothArgs& a, int variant, hipStream_t s) {
+    if (variant < 0 || variant >= smooth_backward_variants()) variant = 0;
+    SmoothArgs b = a;
+    b.spl = kBwdSpl[variant];
+    hipLaunchKernelGGL(k_smooth_backward, dim3(kBackwardGrid), dim3(kSmoothBlock), 0, s, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_smooth_reductions(const SmoothArgs& a, const int32_t* n_cells, float* dmass, int64_t n_grid,
+                                    double* part, double* dparams, hipStream_t s) {
     const int nb = (int)smooth_reduce_blocks(a.cap);
     hipLaunchKernelGGL(k_reduce_params, dim3(nb), dim3(256), 0, s, a.pp, a.cap, a.runs, part);
     hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, s, part, nb, dparams);
