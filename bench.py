@@ -86,6 +86,8 @@ def parse():
     ap.add_argument("--main-only", action="store_true", help="only the timed passes of the headline workload")
     ap.add_argument("--leg", default="", choices=["", "roofline", "workloads", "batched", "gradient", "calibration"],
                     help="only this leg (after the headline passes); for counter runs")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="batched leg without the 1024 plain calls it is compared with (counter runs)")
     ap.add_argument("--no-graphs", action="store_true",
                     help="launch batched calls eagerly instead of replaying captured HIP graphs (counter runs)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -433,7 +435,7 @@ def calibration_leg(avl, torch, iters: int = 60) -> dict:
                      "xi": float(hist[best, 2])}}
 
 
-def batched_leg(avl, torch, reps: int) -> dict:
+def batched_leg(avl, torch, reps: int, plain_calls: bool = True) -> dict:
     """Ensemble sweep: 16 ridged-fBm tiles of 1024^2 at 10 m, one release scenario each (103-26,397
     cells), crossed with 64 (mu, xi, h) sets: 1024 runs of 32 particles per cell and 2000 steps. Timed
     as one batched call (captured once into a HIP graph, then replayed) and as 1024 plain calls."""
@@ -457,6 +459,9 @@ def batched_leg(avl, torch, reps: int) -> dict:
         t_batch = (time.perf_counter() - t0) / reps
     steps = int(out.stats.cpu().numpy()[:, 0].sum())
     variant = avl.last_variant()
+    if not plain_calls:
+        return {"runs": len(e.runs), "particle_steps": steps, "ms_batched": t_batch * 1e3,
+                "particle_steps_per_s_batched": steps / t_batch, "variant": variant}
     plain = avl.BatchResult(torch.empty_like(out.counts), torch.empty_like(out.vmax), torch.empty_like(out.stats),
                             out.status)
     params = [avl.Params.make(**p) for p in e.params]
@@ -789,7 +794,7 @@ def main() -> int:
     if only == "":
         out["fine_release"] = fine_leg(avl, torch, 5)
     if only in ("", "batched"):
-        out["batched"] = batched_leg(avl, torch, 3)
+        out["batched"] = batched_leg(avl, torch, 3, not args.no_plain)
     grad_host = None
     if only in ("", "gradient"):
         out["gradient"], grad_host = gradient_leg(avl, torch, 5)
