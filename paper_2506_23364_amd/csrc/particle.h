@@ -17,8 +17,9 @@ __device__ __forceinline__ uint4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_
     for (int round = 0; round < 10; ++round) {
         const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
         const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
-        const uint32_t n0 = hi1 ^ c1 ^ k0;
-        const uint32_t n2 = hi0 ^ c3 ^ k1;
+        // three-way XORs as single gfx950 three-input bit operations (truth table 0x96)
+        const uint32_t n0 = __builtin_amdgcn_bitop3_b32(hi1, c1, k0, 0x96);
+        const uint32_t n2 = __builtin_amdgcn_bitop3_b32(hi0, c3, k1, 0x96);
         c0 = n0;
         c1 = lo1;
         c2 = n2;
@@ -231,6 +232,10 @@ __device__ __forceinline__ RunConst uniform_run(const RunConst& r) {
     u.raster_off = uniform_u(r.raster_off);
     u.P = uniform_u(r.P);
     u.n_slots = ((unsigned long long)uniform_u((uint32_t)(r.n_slots >> 32)) << 32) | uniform_u((uint32_t)r.n_slots);
+    // the DEM tile's offset builds the buffer resource of every gather: a value the compiler cannot prove
+    // uniform there makes each buffer load a loop over the distinct resources of the wave's lanes
+    u.pad_off = uniform_u(r.pad_off);
+    u.use_rec = uniform_u(r.use_rec);
     return u;
 }
 

@@ -14,8 +14,12 @@
 //  - Device-scope atomics on the rasters are performed beyond L2 (at the memory side), so they are the
 //    cost to cut. Entry counts and per-cell max v^2 go first into a table in LDS shared by the whole
 //    workgroup (tag, count, max; linear probing), flushed to the rasters at epoch boundaries (a pair of
-//    barriers every kFlush iterations). A cell whose probes are all held by other cells goes straight to
-//    the raster.
+//    barriers every kFlush iterations per wave on average). A cell whose probes are all held by other
+//    cells goes straight to the raster.
+//  - An epoch is a budget of kFlush x (waves per block) wave-iterations that the block's waves claim one
+//    at a time from an LDS counter, so a wave that runs faster than its neighbours does more of them and
+//    every wave reaches the boundary within about one iteration of the others (a fixed count per wave
+//    left the fast waves waiting at the first barrier for 15-25 % of their time).
 //  - The waves of a workgroup share a window of consecutive slots (two ranges, topped up at epoch
 //    boundaries), so the table sees the paths of neighbouring release cells together. Top-ups are guided:
 //    up to kWindow x kBlock slots, but at most half the partition's remainder over the blocks of an XCD,
@@ -74,6 +78,7 @@ struct Control {
     uint32_t busy[2];             // waves with work left, per epoch parity
     uint32_t part, tried, empty;  // the window's own walk over the XCD partitions
     uint32_t dry;                 // the tail probe has seen the block run out of slots
+    uint32_t iters;               // wave-iterations of the epoch's budget claimed so far
     unsigned long long left;      // slots left in the partition after the window's last top-up
 };
 
@@ -90,9 +95,9 @@ template <bool kBatch, bool kAlpha, int kBlock, int kFlush, int kTbl, int kProbe
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWpe)))
 void k_trajectories(TrajArgs a) {
     static_assert(!(kRec && kBatch), "recording is for single runs");
-    static_assert(kFlush % 2 == 0, "epochs keep the iteration parity");
-    // a lane enters a given cell at most once per iteration, so a slot gains at most kBlock * kFlush
-    // entries per epoch; a retained count stays below kKeepCap, so the low half never carries
+    // a lane enters a given cell at most once per iteration and a block runs at most kFlush x (waves per
+    // block) wave-iterations per epoch, so a slot gains at most kBlock * kFlush entries per epoch; a
+    // retained count stays below kKeepCap, so the low half never carries
     static_assert(kKeep == 0 || kBlock * kFlush <= 32768, "retention needs 16-bit counts per epoch");
     constexpr uint32_t kKeepCap = 65536u - (uint32_t)(kBlock * kFlush);
     constexpr uint32_t kSuper = (uint32_t)kWindow * kBlock;  // slots per window top-up
@@ -174,6 +179,7 @@ void k_trajectories(TrajArgs a) {
             ctl.empty = total == 0 ? 1u : 0u;
             ctl.left = ~0ull;
             ctl.dry = 0u;
+            ctl.iters = 0u;
         }
         const uint32_t l0 = ctl.len[0], l1 = ctl.len[1];
         const uint32_t t = min(ctl.take, l0 + l1);
@@ -273,6 +279,8 @@ void k_trajectories(TrajArgs a) {
             atomicAdd(counts + cur, 1u);
     };
 
+    constexpr uint32_t kBudget = (uint32_t)kFlush * (uint32_t)(kBlock / kWave);  // wave-iterations per epoch
+    uint32_t wit = 0;  // the wave's iterations so far; a live particle's step count has their parity
     for (uint32_t epoch = 0;; ++epoch) {
         // the window of this epoch
         const uint64_t wb0 = wave_bcast64(ctl.base[0]), wb1 = wave_bcast64(ctl.base[1]);
@@ -280,7 +288,11 @@ void k_trajectories(TrajArgs a) {
         bool win_out = wl0 + wl1 == 0u;
         bool finished = false;
 
-        for (int it = 0; it < kFlush; ++it) {
+        // the wave claims each iteration of the epoch's budget one iteration ahead, so the LDS round trip
+        // overlaps the iteration before it
+        uint32_t ticket = 0;
+        if (lane == 0) ticket = atomicAdd(&ctl.iters, 1u);
+        for (;;) {
             const uint64_t idle = __ballot(!alive);
             const int nidle = __popcll(idle);
             const bool drained = win_out && queue_empty && res_next >= res_end;
@@ -288,11 +300,14 @@ void k_trajectories(TrajArgs a) {
                 finished = true;
                 break;
             }
+            if (__builtin_amdgcn_readfirstlane(ticket) >= kBudget) break;
+            const uint32_t it = wit++;
+            if (lane == 0) ticket = atomicAdd(&ctl.iters, 1u);
 
             // ---- hand slots to idle lanes in lane order: the reservoir, refilled with the next 64-slot
-            // chunk of the window (else of the queues) when it runs dry. Only on even iterations: every
-            // particle then starts on an even iteration, so its step parity is the iteration's and the
-            // Philox block (one per two steps) is a uniform branch.
+            // chunk of the window (else of the queues) when it runs dry. Only on the wave's even iterations:
+            // every particle then starts on an even iteration, so its step parity is the iteration's and
+            // the Philox block (one per two steps) is a uniform branch.
             bool fresh = false;
             if ((it & 1) == 0 && nidle > 0 && !drained) {
                 // next 64-slot chunk of the window, else of the queues; empty when neither has any left
@@ -546,6 +561,7 @@ void k_trajectories(TrajArgs a) {
         __syncthreads();
         if (threadIdx.x == 0) {
             ctl.busy[(epoch + 1) & 1u] = 0u;
+            ctl.iters = 0u;
             refill_window(false);
             if (probe && !ctl.dry && ctl.empty && ctl.len[0] == 0u) {
                 ctl.dry = 1u;
