@@ -41,7 +41,7 @@ VALU_WAVE_INSTS_PER_S = 256 * 4 * 2.4e9 / 4
 # rocprofv3 figures of the trajectory kernel (recorded with the hash of the kernel sources they were taken
 # on; used only while the sources are unchanged)
 KERNEL_SOURCES = ["paper_2506_23364_amd/csrc/trajectories.hip", "paper_2506_23364_amd/csrc/particle.h",
-                  "paper_2506_23364_amd/csrc/avl_internal.h"]
+                  "paper_2506_23364_amd/csrc/avl_internal.h", "paper_2506_23364_amd/build.py"]
 METRIC = "particle-steps/s forward + s per (mu,xi) gradient, batched vs plain, 1 MI355X"
 
 

@@ -19,6 +19,9 @@ HIP_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
     "-ffp-contract=off", "-fhip-fp32-correctly-rounded-divide-sqrt", "-fno-gpu-flush-denormals-to-zero",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # the kernels' same-address atomics on hot paths are issued by one lane already (queue and budget
+    # counters, statistics); the compiler's wave-level combining only adds lane counting around them
+    "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
     "-fvisibility=hidden", "-Wall", "-Wno-unused-result",
 ]
 
