@@ -34,7 +34,7 @@ Workspace carve(void* base, int64_t H, int64_t W, int64_t mult) {
     Workspace w{};
     w.n_cells = reinterpret_cast<int32_t*>(p);
     w.stats = reinterpret_cast<unsigned long long*>(p + 64);
-    w.queues = reinterpret_cast<unsigned long long*>(p + 128);
+    w.queues = reinterpret_cast<unsigned long long*>(p + 512);
     w.run_off = reinterpret_cast<unsigned long long*>(p + 192);
     w.runs = reinterpret_cast<RunConst*>(p + 256);
     p += kControl;
@@ -62,7 +62,7 @@ Workspace carve_batched(void* base, int64_t H, int64_t W, int64_t n_masks, int64
     const int64_t n = H * W;
     char* p = static_cast<char*>(base);
     Workspace w{};
-    w.queues = reinterpret_cast<unsigned long long*>(p + 128);
+    w.queues = reinterpret_cast<unsigned long long*>(p + 512);
     p += kControl;
     w.blk = reinterpret_cast<uint32_t*>(p);
     p += round256((size_t)scan_blocks(n) * sizeof(uint32_t));
@@ -85,9 +85,13 @@ Workspace carve_batched(void* base, int64_t H, int64_t W, int64_t n_masks, int64
 }
 
 // Smooth pass workspace: the single-run control block, scan sums and cell list, then the end records,
-// checkpoints, per-particle adjoint results, reduction partials and the adjoint's scratch.
+// checkpoints, per-particle adjoint results, reduction partials and the adjoint's scratch, the padded DEM,
+// and per release cell its start state and the mass of each of its particles (made by the forward, read
+// by the adjoint).
 struct SmoothWs {
     Workspace w;
+    StartRec* starts;
+    float* mpc;
     uint32_t* end_rec;
     float* ck;
     float* pp;
@@ -116,12 +120,16 @@ static size_t smooth_layout(int64_t H, int64_t W, int64_t cap_cells, uint32_t P,
     const size_t o_part = take(3 * smooth_reduce_blocks(cap) * sizeof(double));
     const size_t o_scr = take(smooth_scratch_bytes());
     const size_t o_pad = take((size_t)padded_cells(H, W) * sizeof(float));
+    const size_t o_st = take((size_t)cap_cells * sizeof(StartRec));
+    const size_t o_mpc = take((size_t)cap_cells * sizeof(float));
     if (base && out) {
         char* p = base + o_ctrl;
         out->w = Workspace{};
+        out->starts = reinterpret_cast<StartRec*>(base + o_st);
+        out->mpc = reinterpret_cast<float*>(base + o_mpc);
         out->w.n_cells = reinterpret_cast<int32_t*>(p);
         out->w.stats = reinterpret_cast<unsigned long long*>(p + 64);
-        out->w.queues = reinterpret_cast<unsigned long long*>(p + 128);
+        out->w.queues = reinterpret_cast<unsigned long long*>(p + 512);
         out->w.run_off = reinterpret_cast<unsigned long long*>(p + 192);
         out->w.runs = reinterpret_cast<RunConst*>(p + 256);
         out->w.blk = reinterpret_cast<uint32_t*>(base + o_blk);
@@ -646,7 +654,7 @@ int single_pass(const char* where, const float* dem, const uint8_t* mask, int32_
         hipError_t e;
         if ((e = avl::launch_fill_u32(counts, 0u, n, s)) != hipSuccess) return e;
         if ((e = avl::launch_fill_u32(a.vmax2, 0u, n, s)) != hipSuccess) return e;
-        if ((e = avl::launch_fill_u64(ws.queues, 0ull, avl::kXcds, s)) != hipSuccess) return e;
+        if ((e = avl::launch_fill_u64(ws.queues, 0ull, avl::kXcds * avl::kQueueStride, s)) != hipSuccess) return e;
         return avl::launch_fill_u64(a.stats, 0ull, 4, s);
     };
     hipError_t e;
@@ -916,6 +924,9 @@ avl::SmoothArgs smooth_args(const float* dem, const float* mass, int32_t H, int3
     a.h = params->flow_height;
     a.dem_pad = sw.dem_pad;
     a.pad_bytes = (uint32_t)(avl::padded_cells(H, W) * sizeof(float));
+    a.starts = sw.starts;
+    a.mpc = sw.mpc;
+    a.pdiv = avl::make_divu32(P);
     return a;
 }
 
@@ -956,11 +967,16 @@ int avl_trajectories_smooth(const float* dem, const uint8_t* mask, const float* 
         if ((z = avl::launch_fill_u32(reinterpret_cast<uint32_t*>(deposit_q), 0u, 2 * n, s)) != hipSuccess) return z;
         if (vel && (z = avl::launch_fill_u32(reinterpret_cast<uint32_t*>(velocity_q), 0u, 2 * n, s)) != hipSuccess)
             return z;
-        if ((z = avl::launch_fill_u64(sw.w.queues, 0ull, avl::kXcds, s)) != hipSuccess) return z;
+        if ((z = avl::launch_fill_u64(sw.w.queues, 0ull, avl::kXcds * avl::kQueueStride, s)) != hipSuccess) return z;
         return avl::launch_fill_u64(a.stats, 0ull, 4, s);
     };
     if ((e = avl::launch_pad_dem(dem, H, W, sw.dem_pad, s)) != hipSuccess)
         return hip_fail(e, "avl_trajectories_smooth: padded DEM");
+    if ((e = avl::launch_start_records(dem, H, W, 1, sw.w.cells, sw.w.n_cells, max_release_cells, sw.starts, s)) !=
+            hipSuccess ||
+        (e = avl::launch_particle_mass(mass, sw.w.cells, sw.w.n_cells, max_release_cells, particles_per_cell, sw.mpc,
+                                       s)) != hipSuccess)
+        return hip_fail(e, "avl_trajectories_smooth: start records");
     int variant = 0;
     if ((e = choose_smooth(smooth_key(2, n, max_release_cells, particles_per_cell, step_limit),
                            avl::smooth_forward_variants(), s, zero,
@@ -999,7 +1015,7 @@ int avl_trajectories_backward(const float* dem, const uint8_t* mask, const float
     auto zero = [&]() -> hipError_t {
         hipError_t z;
         if ((z = avl::launch_fill_u32(reinterpret_cast<uint32_t*>(dmass), 0u, n, s)) != hipSuccess) return z;
-        return avl::launch_fill_u64(sw.w.queues, 0ull, avl::kXcds, s);
+        return avl::launch_fill_u64(sw.w.queues, 0ull, avl::kXcds * avl::kQueueStride, s);
     };
     int variant = 0;
     if ((e = choose_smooth(smooth_key(3, n, max_release_cells, particles_per_cell, step_limit),
@@ -1073,7 +1089,7 @@ int avl_trajectories_batched(const float* dems, int32_t n_tiles, const uint8_t* 
         hipError_t e;
         if ((e = avl::launch_fill_u32(counts, 0u, raster, s)) != hipSuccess) return e;
         if ((e = avl::launch_fill_u32(a.vmax2, 0u, raster, s)) != hipSuccess) return e;
-        if ((e = avl::launch_fill_u64(ws.queues, 0ull, avl::kXcds, s)) != hipSuccess) return e;
+        if ((e = avl::launch_fill_u64(ws.queues, 0ull, avl::kXcds * avl::kQueueStride, s)) != hipSuccess) return e;
         return avl::launch_fill_u64(a.stats, 0ull, 4 * (int64_t)n_runs, s);
     };
     // padded copies of the tiles, release-cell lists of every scenario, then the run table

@@ -14,22 +14,27 @@ constexpr int kWave = 64;
 
 // ------------------------------------------------------------------ workspace layout
 // Single run (avl_workspace_bytes):
-//   [0, 512)     control block: n_cells (i32 @0), stats (4 x u64 @64), per-XCD slot queues (kXcds x u64
-//                @128), run offsets (2 x u64 @192), the run's constants (RunConst @256)
+//   [0, kControl) control block: n_cells (i32 @0), stats (4 x u64 @64), run offsets (2 x u64 @192), the
+//                run's constants (RunConst @256), per-XCD slot queues (kXcds u64 @512, kQueueStride words
+//                apart)
 //   then         per-block sums of the compaction scan (u32), the release-texel list (i32, one per texel of
 //                the release texture: mult^2 H W), the start records of the release texels (StartRec, as
 //                many) and the padded DEM (f32, (H + 2) x (W + 2))
 // Batch (avl_batched_workspace_bytes):
-//   [0, 512)     control block: per-XCD slot queues @128
+//   [0, kControl) control block: per-XCD slot queues @512, kQueueStride words apart
 //   then         compaction scan sums; n_masks release-cell lists (i32, H*W each); n_masks cell counts;
 //                n_runs RunConst; n_runs + 1 slot offsets; n_runs x 4 internal statistics; n_tiles padded
 //                DEM tiles (f32, (H + 2) x (W + 2) each)
 // Every region starts on a 256-byte boundary.
 constexpr int kXcds = 8;            // MI355X: 8 XCDs, each with its own L2
+// The slot queues' counters sit 256 bytes apart: device-scope atomics are performed at the memory side
+// and serialise per memory line, and with the eight counters in one line every wave's take from the
+// queues waited for the other XCDs' takes as well (4.5-10 us per take in the smooth kernels).
+constexpr uint32_t kQueueStride = 32;
 constexpr int kScanThreads = 256;
 constexpr int kScanPerThread = 16;
 constexpr int kScanChunk = kScanThreads * kScanPerThread;  // cells per compaction block
-constexpr size_t kControl = 512;
+constexpr size_t kControl = 512 + (size_t)kXcds * kQueueStride * 8;
 
 inline size_t round256(size_t v) { return (v + 255) & ~size_t(255); }
 inline int64_t scan_blocks(int64_t n) { return (n + kScanChunk - 1) / kScanChunk; }
@@ -39,7 +44,7 @@ struct StartRec;
 
 struct Workspace {
     int32_t* n_cells;             // single: 1; batch: n_masks
-    unsigned long long* queues;   // kXcds counters
+    unsigned long long* queues;   // kXcds counters, kQueueStride words apart
     unsigned long long* stats;    // single: 4; batch: 4 x n_runs
     unsigned long long* run_off;  // n_runs + 1
     RunConst* runs;               // n_runs
@@ -103,7 +108,7 @@ struct TrajArgs {
     const int32_t* __restrict__ cells;           // all release-cell lists, H*W each
     const RunConst* __restrict__ runs;           // n_runs
     const unsigned long long* __restrict__ run_off;  // n_runs + 1 slot offsets, each a multiple of 64
-    unsigned long long* __restrict__ queues;     // kXcds slot counters, zero at launch
+    unsigned long long* __restrict__ queues;     // kXcds slot counters kQueueStride words apart, zero at launch
     uint32_t* __restrict__ counts;               // count rasters, zero at launch
     uint32_t* __restrict__ vmax2;                // binary32 bits of the per-cell max of v^2 (v^2 >= 0, so bit
                                                  // order is value order), zero at launch
@@ -164,7 +169,7 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int64_t n, hipStream_t s);
 // (H + 2) x (W + 2) copy of the DEM with the edge texels replicated into a one-texel border.
 hipError_t launch_pad_dem(const float* dem, int H, int W, float* out, hipStream_t s);
-// starts[i] for each of the *n_cells release cells (capacity n).
+// starts[i] for each of the first min(*n_cells, n) release cells (the records array holds n).
 hipError_t launch_start_records(const float* dem, int H, int W, int mult, const int32_t* cells,
                                 const int32_t* n_cells, int64_t n, StartRec* starts, hipStream_t s);
 // Setup of the run table: per run, constants from its parameter set and the slot count from its
@@ -209,7 +214,7 @@ struct SmoothArgs {
     const int32_t* cells;
     const RunConst* runs;      // one run
     const unsigned long long* run_off;
-    unsigned long long* queues;
+    unsigned long long* queues;  // kXcds slot counters kQueueStride words apart, zero at launch
     unsigned long long* dep_q;
     unsigned long long* vel_q;  // nullable
     unsigned long long* stats;
@@ -225,6 +230,9 @@ struct SmoothArgs {
     const float* dem_pad;                   // the DEM with a replicated border, (H + 2) x (W + 2)
     uint32_t pad_bytes;                     // its bytes, < 2^32
     uint32_t spl;                           // particle slots per lane of a small problem (set by the launchers)
+    const StartRec* starts;                 // per release cell: the start state of its particles
+    const float* mpc;                       // per release cell: the mass of each of its particles
+    DivU32 pdiv;                            // slot -> release cell (division by the particles per cell)
 };
 
 
@@ -241,6 +249,9 @@ hipError_t launch_smooth_backward_kernel(const SmoothArgs& a, int variant, hipSt
 hipError_t launch_smooth_reductions(const SmoothArgs& a, const int32_t* n_cells, float* dmass, int64_t n_grid,
                                     double* part, double* dparams, hipStream_t s);
 hipError_t launch_q_to_float(const unsigned long long* q, int64_t n, float* out, hipStream_t s);
+// per release cell i < *n_cells: mpc[i] = (mass ? mass[cells[i]] : 1) / P, the mass each of its particles carries
+hipError_t launch_particle_mass(const float* mass, const int32_t* cells, const int32_t* n_cells, int64_t cap,
+                                uint32_t P, float* mpc, hipStream_t s);
 // calibration loss: gD = c (D - T) and L = sum (D - T)^2 / N (binary64, fixed order) into *loss
 hipError_t launch_mse_grad(const float* dep, const float* target, int64_t n, float c, float* gD, double* part,
                            double* loss, hipStream_t s);

@@ -269,22 +269,38 @@ __device__ __forceinline__ uint64_t active_blocks(uint64_t total, int block_thre
     return want > (uint64_t)kXcds ? want : (uint64_t)kXcds;
 }
 
-// Wave-uniform slot dispenser: a reservoir of up to kChunk slots refilled from per-XCD queues, the
-// wave starting on its own XCD's partition and moving on when it is empty.
+// Wave-uniform slot dispenser of the smooth kernels. The first chunks of 64 slots are dealt out without
+// atomics, round-robin over the grid's waves (kStaticShare of the chunks, a whole number of rounds); the
+// rest come from per-XCD queues, the wave starting on its own XCD's partition of the remainder and moving
+// on when it is empty. Device-scope atomics on one counter are serialised at the memory side: taking
+// every chunk from the queues cost each wave 4.5-10 us per take (up to ~150 waves per counter). The
+// counters sit kQueueStride words apart, each in a memory line of its own.
+constexpr uint32_t kStaticShareNum = 3, kStaticShareDen = 4;
 struct Dispenser {
-    uint64_t total;
+    uint64_t total;      // padded slot count (a multiple of kChunk)
+    uint64_t dyn_begin;  // slots below it are dealt out statically
+    uint64_t st_next;    // the wave's next static chunk (>= dyn_begin: none left)
+    uint64_t st_stride;  // kChunk x the grid's waves
     uint32_t part, tried;
     bool queue_empty;
     uint64_t res_next, res_end;
 
-    __device__ __forceinline__ void init(uint64_t total_slots, uint32_t xcd) {
+    // `wave`: the wave's index among the `waves` waves of the grid that take part
+    __device__ __forceinline__ void init(uint64_t total_slots, uint32_t xcd, uint64_t wave, uint64_t waves) {
         total = total_slots;
+        const uint64_t chunks = total / kChunk;
+        const uint64_t rounds = waves ? chunks * kStaticShareNum / kStaticShareDen / waves : 0;
+        dyn_begin = rounds * waves * kChunk;
+        st_stride = waves * kChunk;
+        st_next = rounds ? wave * kChunk : dyn_begin;
         part = xcd;
         tried = 0;
-        queue_empty = total == 0;
+        queue_empty = dyn_begin >= total;
         res_next = res_end = 0;
     }
-    __device__ __forceinline__ bool drained() const { return queue_empty && res_next >= res_end; }
+    __device__ __forceinline__ bool drained() const {
+        return queue_empty && st_next >= dyn_begin && res_next >= res_end;
+    }
 
     // Hands slots to the idle lanes (ballot `idle`) in lane order; returns this lane's slot or ~0.
     __device__ __forceinline__ uint64_t take(unsigned long long* __restrict__ queues, uint64_t idle, int lane,
@@ -299,19 +315,26 @@ struct Dispenser {
             return slot;
         }
         uint64_t base = 0, cend = 0;
-        const int leader = __ffsll((long long)idle) - 1;
-        while (!queue_empty) {
-            const uint64_t pb = part_begin(total, part), pe = part_begin(total, part + 1);
-            uint64_t got = 0;
-            if (lane == leader) got = atomicAdd(queues + part, (unsigned long long)kChunk);
-            got = wave_bcast64(__shfl(got, leader, kWave));
-            if (pb + got < pe) {
-                base = pb + got;
-                cend = (base + kChunk < pe) ? base + kChunk : pe;
-                break;
+        if (st_next < dyn_begin) {
+            base = st_next;
+            cend = base + kChunk;
+            st_next += st_stride;
+        } else {
+            const int leader = __ffsll((long long)idle) - 1;
+            const uint64_t rem = total - dyn_begin;
+            while (!queue_empty) {
+                const uint64_t pb = dyn_begin + part_begin(rem, part), pe = dyn_begin + part_begin(rem, part + 1);
+                uint64_t got = 0;
+                if (lane == leader) got = atomicAdd(queues + part * kQueueStride, (unsigned long long)kChunk);
+                got = wave_bcast64(__shfl(got, leader, kWave));
+                if (pb + got < pe) {
+                    base = pb + got;
+                    cend = (base + kChunk < pe) ? base + kChunk : pe;
+                    break;
+                }
+                part = (part + 1) % kXcds;
+                if (++tried >= (uint32_t)kXcds) queue_empty = true;
             }
-            part = (part + 1) % kXcds;
-            if (++tried >= (uint32_t)kXcds) queue_empty = true;
         }
         if ((uint64_t)rank < avail)
             slot = res_next + rank;

@@ -63,37 +63,14 @@ __device__ __forceinline__ Sample sample(const PadDem& d, float x, float y) {
     return bilinear_pad(d.rs, d.Wp, d.row_bytes, x, y);
 }
 
-// Release state of particle (cell_id, ...) at the texel centre, heading downslope.
-__device__ __forceinline__ void release(State& s, const PadDem& dem, int W, uint32_t cell_id) {
-    const int r = (int)(cell_id / (uint32_t)W);
-    const int c = (int)(cell_id - (uint32_t)r * (uint32_t)W);
-    s.x = (float)c + 0.5f;
-    s.y = (float)r + 0.5f;
-    const Sample s0 = sample(dem, s.x, s.y);
-    s.z = s0.z;
-    s.gx = s0.gx;
-    s.gy = s0.gy;
-    s.x0 = s.x;
-    s.y0 = s.y;
-    s.zr = s.z;
-    const float gg = s.gx * s.gx + s.gy * s.gy;
-    if (gg > 0.0f) {
-        const float t = 1.0f / sqrtf(gg);
-        s.dx = -(s.gx * t);
-        s.dy = -(s.gy * t);
-    } else {
-        s.dx = 0.0f;
-        s.dy = 0.0f;
-    }
-    s.v2 = 0.0f;
-}
-
-// Step n of the model (the same binary32 operations as the plain pass). Updates s when accepted.
+// Step n of the model (the same binary32 operations as the plain pass). Updates s when accepted. `even`
+// is n's parity (a wave-uniform value where every live particle of the wave has the parity of the wave's
+// iteration, which makes the Philox block a uniform branch).
 __device__ __forceinline__ StepOut step(State& s, uint32_t n, uint32_t rep, uint32_t cell_id, const RunConst& rc,
-                                        const PadDem& dem, int H, int W, float g2) {
+                                        const PadDem& dem, int H, int W, float g2, bool even) {
     StepOut o;
     uint32_t ux, uy;
-    if ((n & 1u) == 0u) {
+    if (even) {
         const uint4 b = philox4x32_10(n >> 1, rep, cell_id, rc.run, rc.key0, rc.key1);
         ux = b.x;
         uy = b.y;
@@ -175,40 +152,85 @@ struct DepTable {
     unsigned long long val[kDepSlots];
 };
 
+__device__ __forceinline__ uint32_t dep_home(uint32_t cell) { return (cell * 2654435761u) >> (32 - kDepLog2); }
+
+// The table's adds name the LDS address space: the compiler would otherwise merge them with the raster's
+// fallback add into one generic (flat) atomic through a selected pointer, which every later LDS wait and
+// every vector-memory wait then has to wait for.
+typedef __attribute__((address_space(3))) unsigned long long lds_u64;
+__device__ __forceinline__ void lds_add_u64(unsigned long long* p, unsigned long long v) {
+    __hip_atomic_fetch_add((lds_u64*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ __forceinline__ uint32_t dep_tag(DepTable& t, uint32_t k) {
+    return __hip_atomic_load(&t.tag[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Adds v to the table slot of `cell` (claimed if a probe finds an empty slot first), else to the raster.
+// `first` is a read of the cell's home slot: slots only ever go from empty to a tag, so a stale read of it
+// is either right or empty, and an empty read is settled by the claim.
 __device__ __forceinline__ void dep_add(DepTable& t, unsigned long long* __restrict__ q, uint32_t cell,
-                                        unsigned long long v) {
+                                        unsigned long long v, uint32_t first) {
     if (v == 0ull) return;
-    const uint32_t h = (cell * 2654435761u) >> (32 - kDepLog2);
+    const uint32_t h = dep_home(cell);
     for (int p = 0; p < kDepProbes; ++p) {
         const uint32_t k = (h + (uint32_t)p) & (uint32_t)(kDepSlots - 1);
-        uint32_t cur = t.tag[k];
+        uint32_t cur = p == 0 ? first : dep_tag(t, k);
         if (cur == kDepEmpty) cur = atomicCAS(&t.tag[k], kDepEmpty, cell);  // the old tag: empty if taken here
         if (cur == kDepEmpty || cur == cell) {
-            atomicAdd(&t.val[k], v);
+            lds_add_u64(&t.val[k], v);
             return;
         }
     }
     atomicAdd(q + cell, v);
 }
 
-// splat_q through the block's table
+// splat_q through the block's table; the home slots of the four corners are read together (one LDS round
+// trip instead of four)
 __device__ __forceinline__ void splat_q_table(DepTable& t, unsigned long long* __restrict__ q, int H, int W, float x,
                                               float y, float val) {
     const Corners k = corners(H, W, x, y);
     const float w00 = (1.0f - k.fx) * (1.0f - k.fy), w01 = k.fx * (1.0f - k.fy);
     const float w10 = (1.0f - k.fx) * k.fy, w11 = k.fx * k.fy;
     const float sc = 16777216.0f;  // 2^24
-    dep_add(t, q, (uint32_t)(k.ra * W + k.ca), (unsigned long long)(long long)rintf((val * w00) * sc));
-    dep_add(t, q, (uint32_t)(k.ra * W + k.cb), (unsigned long long)(long long)rintf((val * w01) * sc));
-    dep_add(t, q, (uint32_t)(k.rb * W + k.ca), (unsigned long long)(long long)rintf((val * w10) * sc));
-    dep_add(t, q, (uint32_t)(k.rb * W + k.cb), (unsigned long long)(long long)rintf((val * w11) * sc));
+    const uint32_t c00 = (uint32_t)(k.ra * W + k.ca), c01 = (uint32_t)(k.ra * W + k.cb);
+    const uint32_t c10 = (uint32_t)(k.rb * W + k.ca), c11 = (uint32_t)(k.rb * W + k.cb);
+    const uint32_t f00 = dep_tag(t, dep_home(c00)), f01 = dep_tag(t, dep_home(c01));
+    const uint32_t f10 = dep_tag(t, dep_home(c10)), f11 = dep_tag(t, dep_home(c11));
+    dep_add(t, q, c00, (unsigned long long)(long long)rintf((val * w00) * sc), f00);
+    dep_add(t, q, c01, (unsigned long long)(long long)rintf((val * w01) * sc), f01);
+    dep_add(t, q, c10, (unsigned long long)(long long)rintf((val * w10) * sc), f10);
+    dep_add(t, q, c11, (unsigned long long)(long long)rintf((val * w11) * sc), f11);
 }
 
 __device__ __forceinline__ float mass_per_particle(const float* __restrict__ mass, uint32_t cell, uint32_t P) {
     return (mass ? mass[cell] : 1.0f) / (float)P;
 }
 
+// release cell of particle slot `slot`, and the particle's replica index within it
+__device__ __forceinline__ uint64_t cell_of_slot(uint64_t slot, const SmoothArgs& a, uint32_t P, uint32_t* rep) {
+    const uint64_t i = (slot >> 32) == 0 ? (uint64_t)udiv((uint32_t)slot, a.pdiv) : slot / P;
+    *rep = (uint32_t)(slot - i * P);
+    return i;
+}
+
 }  // namespace
+
+__global__ __launch_bounds__(256) void k_particle_mass(const float* __restrict__ mass, const int32_t* __restrict__ cells,
+                                                       const int32_t* __restrict__ n_cells, int64_t cap,
+                                                       uint32_t P, float* __restrict__ mpc) {
+    const int64_t n = min((int64_t)*n_cells, cap);
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        mpc[i] = mass_per_particle(mass, (uint32_t)cells[i], P);
+}
+
+hipError_t launch_particle_mass(const float* mass, const int32_t* cells, const int32_t* n_cells, int64_t cap,
+                                uint32_t P, float* mpc, hipStream_t s) {
+    const int64_t blocks = (cap + 255) / 256;
+    hipLaunchKernelGGL(k_particle_mass, dim3((unsigned)(blocks < 4096 ? (blocks > 0 ? blocks : 1) : 4096)), dim3(256),
+                       0, s, mass, cells, n_cells, cap, P > 0 ? P : 1u, mpc);
+    return hipGetLastError();
+}
 
 
 // kBlk threads per block share one deposit table; a.spl particle slots per lane size the grid of a small
@@ -222,7 +244,12 @@ __global__ __launch_bounds__(kBlk) void k_smooth_forward(SmoothArgs a) {
     const int H = a.H, W = a.W;
     const PadDem dd = pad_dem(a);
     Dispenser disp;
-    disp.init(wave_bcast64(a.run_off[1]), xcd_id());
+    {
+        const uint64_t total = wave_bcast64(a.run_off[1]);
+        const uint64_t nb = min((uint64_t)gridDim.x, active_blocks(total, blockDim.x, a.spl));
+        const uint32_t wpb = blockDim.x / kWave;
+        disp.init(total, xcd_id(), (uint64_t)blockIdx.x * wpb + threadIdx.x / kWave, nb * wpb);
+    }
     const size_t cplane = (size_t)a.C * a.cap;
     __shared__ DepTable dep;
     for (int k = threadIdx.x; k < kDepSlots; k += kBlk) {
@@ -238,29 +265,59 @@ __global__ __launch_bounds__(kBlk) void k_smooth_forward(SmoothArgs a) {
     float mp = 0.0f;
     uint64_t st_steps = 0;
     uint32_t st_exit = 0, st_stop = 0, st_limit = 0;
+    // Particles start on the wave's even iterations only: a live particle's step count then has the parity
+    // of the wave's iteration, so the Philox block (one per two steps) is a uniform branch, and the slot
+    // hand-out runs every other iteration. A particle starts from its release cell's start record (one
+    // load, the mass per particle beside it). The waits for vector memory cover stores as well as loads,
+    // so an end record is written in the iteration after the particle ended, after the hand-out's loads.
+    bool end_pending = false;
+    uint64_t end_slot = 0;
+    uint32_t end_val = 0;
+    auto end_particle = [&](uint32_t why) {
+        end_pending = true;
+        end_slot = slot_id;
+        end_val = (n << 2) | why;
+        alive = false;
+    };
 
-    for (;;) {
-        const uint64_t idle = __ballot(!alive);
-        if (__popcll(idle) == kWave && disp.drained()) break;
-        if (idle && !disp.drained()) {
-            const uint64_t slot = disp.take(a.queues, idle, lane, below);
-            if (!alive && slot < rc.n_slots) {
-                const uint64_t i = slot / rc.P;
-                rep = (uint32_t)(slot - i * rc.P);
-                cell_id = (uint32_t)a.cells[i];
-                slot_id = slot;
-                mp = mass_per_particle(a.mass, cell_id, rc.P);
-                release(s, dd, W, cell_id);
-                n = 0;
-                alive = true;
+    for (uint32_t wit = 0;; ++wit) {
+        const bool even = (wit & 1u) == 0u;
+        if (even) {
+            const uint64_t idle = __ballot(!alive);
+            if (__popcll(idle) == kWave && disp.drained() && __ballot(end_pending) == 0ull) break;
+            if (idle && !disp.drained()) {
+                const uint64_t slot = disp.take(a.queues, idle, lane, below);
+                if (!alive && slot < rc.n_slots) {
+                    const uint64_t i = cell_of_slot(slot, a, rc.P, &rep);
+                    const StartRec st = a.starts[i];
+                    mp = a.mpc[i];
+                    s.x = st.x;
+                    s.y = st.y;
+                    s.z = st.z;
+                    s.gx = st.gx;
+                    s.gy = st.gy;
+                    s.dx = st.dx;
+                    s.dy = st.dy;
+                    s.x0 = st.x;
+                    s.y0 = st.y;
+                    s.zr = st.z;
+                    s.v2 = 0.0f;
+                    cell_id = st.cell;
+                    slot_id = slot;
+                    n = 0;
+                    alive = true;
+                }
             }
+        }
+        if (end_pending) {
+            a.end_rec[end_slot] = end_val;
+            end_pending = false;
         }
         if (!alive) continue;
         if (n >= a.S) {
             ++st_limit;
-            a.end_rec[slot_id] = (n << 2) | kEndLimit;
             splat_q_table(dep, a.dep_q, H, W, s.x, s.y, mp);
-            alive = false;
+            end_particle(kEndLimit);
             continue;
         }
         if (n % kCkpt == 0) {
@@ -273,25 +330,24 @@ __global__ __launch_bounds__(kBlk) void k_smooth_forward(SmoothArgs a) {
         }
         ++st_steps;
         const float xp = s.x, yp = s.y, v2p = s.v2;
-        const StepOut o = step(s, n, rep, cell_id, rc, dd, H, W, a.g2);
+        const StepOut o = step(s, n, rep, cell_id, rc, dd, H, W, a.g2, even);
         if (o.outcome == kAccept) {
             ++n;
             if (a.vel_q) splat_q(a.vel_q, H, W, s.x, s.y, mp * sqrtf(s.v2));
             continue;
         }
-        alive = false;
         if (o.outcome == kExit) {
             ++st_exit;
-            a.end_rec[slot_id] = (n << 2) | kEndExit;
+            end_particle(kEndExit);
         } else if (o.outcome == kStop) {
             ++st_stop;
-            a.end_rec[slot_id] = (n << 2) | kEndStop;
             const float t = v2p > 0.0f ? v2p / (v2p - o.num) : 0.0f;
             splat_q_table(dep, a.dep_q, H, W, xp + t * (o.x1 - xp), yp + t * (o.y1 - yp), mp);
+            end_particle(kEndStop);
         } else {
             ++st_stop;
-            a.end_rec[slot_id] = (n << 2) | kEndAngle;
             splat_q_table(dep, a.dep_q, H, W, xp, yp, mp);
+            end_particle(kEndAngle);
         }
     }
     // every wave of the block is done: the table's sums go to the raster
@@ -320,17 +376,23 @@ __global__ __launch_bounds__(kSmoothBlock) void k_smooth_backward(SmoothArgs a) 
     const size_t cplane = (size_t)a.C * a.cap;
     const float g2dl = a.g2dl;
     Dispenser disp;
-    disp.init(wave_bcast64(a.run_off[1]), xcd_id());
+    {
+        const uint64_t total = wave_bcast64(a.run_off[1]);
+        const uint64_t nb = min((uint64_t)gridDim.x, active_blocks(total, blockDim.x, a.spl));
+        const uint32_t wpb = blockDim.x / kWave;
+        disp.init(total, xcd_id(), (uint64_t)blockIdx.x * wpb + threadIdx.x / kWave, nb * wpb);
+    }
 
     for (;;) {
         const uint64_t idle = __ballot(true);
         if (disp.drained()) break;
         const uint64_t slot = disp.take(a.queues, idle, lane, below);
         if (slot >= rc.n_slots) continue;
-        const uint64_t i = slot / rc.P;
-        const uint32_t rep = (uint32_t)(slot - i * rc.P);
-        const uint32_t cell_id = (uint32_t)a.cells[i];
-        const float mp = mass_per_particle(a.mass, cell_id, rc.P);
+        uint32_t rep = 0;
+        const uint64_t i = cell_of_slot(slot, a, rc.P, &rep);
+        const StartRec st = a.starts[i];  // the release state, as the forward started the particle
+        const uint32_t cell_id = st.cell;
+        const float mp = a.mpc[i];
         const uint32_t rec = a.end_rec[slot];
         const uint32_t n_end = rec >> 2, reason = rec & 3u;
         float dmu = 0.0f, dxi = 0.0f, dh = 0.0f, gw = 0.0f;
@@ -341,8 +403,18 @@ __global__ __launch_bounds__(kSmoothBlock) void k_smooth_backward(SmoothArgs a) 
             if (a.C > 0) c_last = (int32_t)min(n_end / kCkpt, a.C - 1);
             uint32_t n0 = 0;
             auto load = [&](int32_t c) {
+                s.x0 = st.x;
+                s.y0 = st.y;
+                s.zr = st.z;
                 if (c < 0) {
-                    release(s, dd, W, cell_id);
+                    s.x = st.x;
+                    s.y = st.y;
+                    s.z = st.z;
+                    s.gx = st.gx;
+                    s.gy = st.gy;
+                    s.dx = st.dx;
+                    s.dy = st.dy;
+                    s.v2 = 0.0f;
                     return;
                 }
                 const size_t at = (size_t)c * a.cap + slot;
@@ -355,25 +427,21 @@ __global__ __launch_bounds__(kSmoothBlock) void k_smooth_backward(SmoothArgs a) 
                 s.z = sm.z;
                 s.gx = sm.gx;
                 s.gy = sm.gy;
-                // release point of the particle (for the runout-angle test)
-                const int r = (int)(cell_id / (uint32_t)W);
-                const int cc = (int)(cell_id - (uint32_t)r * (uint32_t)W);
-                s.x0 = (float)cc + 0.5f;
-                s.y0 = (float)r + 0.5f;
-                s.zr = sample(dd, s.x0, s.y0).z;
             };
             load(c_last);
             n0 = c_last < 0 ? 0u : (uint32_t)c_last * kCkpt;
-            for (uint32_t k = n0; k < n_end; ++k) {
-                const StepOut o = step(s, k, rep, cell_id, rc, dd, H, W, a.g2);
-                a.scratch[(size_t)(k - n0) * T + gtid] = make_float2(o.a, s.v2);
+            // segments start at checkpoints, multiples of kCkpt (even): the step's parity is that of the trip
+            // count, the same for every lane still in the loop
+            for (uint32_t t = 0; n0 + t < n_end; ++t) {
+                const StepOut o = step(s, n0 + t, rep, cell_id, rc, dd, H, W, a.g2, (t & 1u) == 0u);
+                a.scratch[(size_t)t * T + gtid] = make_float2(o.a, s.v2);
             }
             float px = s.x, py = s.y;
             float lam = 0.0f, gt = 0.0f;
             bool stop = false;
             if (reason == kEndStop) {
                 const float xp = s.x, yp = s.y, v2p = s.v2;
-                const StepOut o = step(s, n_end, rep, cell_id, rc, dd, H, W, a.g2);
+                const StepOut o = step(s, n_end, rep, cell_id, rc, dd, H, W, a.g2, (n_end & 1u) == 0u);
                 const float t = v2p > 0.0f ? v2p / (v2p - o.num) : 0.0f;
                 px = xp + t * (o.x1 - xp);
                 py = yp + t * (o.y1 - yp);
@@ -409,9 +477,9 @@ __global__ __launch_bounds__(kSmoothBlock) void k_smooth_backward(SmoothArgs a) 
                     const uint32_t c1 = (c == c_last) ? n_end : c0 + kCkpt;
                     if (c != c_last) {
                         load(c);
-                        for (uint32_t k = c0; k < c1; ++k) {
-                            const StepOut o = step(s, k, rep, cell_id, rc, dd, H, W, a.g2);
-                            a.scratch[(size_t)(k - c0) * T + gtid] = make_float2(o.a, s.v2);
+                        for (uint32_t t = 0; c0 + t < c1; ++t) {
+                            const StepOut o = step(s, c0 + t, rep, cell_id, rc, dd, H, W, a.g2, (t & 1u) == 0u);
+                            a.scratch[(size_t)t * T + gtid] = make_float2(o.a, s.v2);
                         }
                     }
                     for (uint32_t k = c1; k-- > c0;) {

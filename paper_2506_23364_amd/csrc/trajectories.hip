@@ -133,7 +133,7 @@ void k_trajectories(TrajArgs a) {
         base = end = left = 0;
         while (!empty) {
             const uint64_t pb = part_begin(total, part), pe = part_begin(total, part + 1);
-            const uint64_t got = atomicAdd(a.queues + part, (unsigned long long)len);
+            const uint64_t got = atomicAdd(a.queues + part * kQueueStride, (unsigned long long)len);
             if (pb + got < pe) {
                 base = pb + got;
                 end = (base + len < pe) ? base + len : pe;
@@ -618,9 +618,9 @@ void k_trajectories(TrajArgs a) {
 
 __global__ __launch_bounds__(256) void k_start_records(const float* __restrict__ dem, int H, int W, uint32_t mult,
                                                        const int32_t* __restrict__ cells,
-                                                       const int32_t* __restrict__ n_cells,
+                                                       const int32_t* __restrict__ n_cells, int64_t cap,
                                                        StartRec* __restrict__ starts) {
-    const int64_t n = *n_cells;
+    const int64_t n = min((int64_t)*n_cells, cap);  // records of the first `cap` cells at most
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         starts[i] = start_state(dem, H, W, mult, (uint32_t)cells[i]);
 }
@@ -629,7 +629,7 @@ hipError_t launch_start_records(const float* dem, int H, int W, int mult, const 
                                 const int32_t* n_cells, int64_t n, StartRec* starts, hipStream_t s) {
     const int64_t blocks = (n + 255) / 256;
     hipLaunchKernelGGL(k_start_records, dim3((unsigned)(blocks < 4096 ? (blocks > 0 ? blocks : 1) : 4096)), dim3(256),
-                       0, s, dem, H, W, (uint32_t)mult, cells, n_cells, starts);
+                       0, s, dem, H, W, (uint32_t)mult, cells, n_cells, n, starts);
     return hipGetLastError();
 }
 
