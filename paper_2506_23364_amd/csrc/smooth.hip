@@ -350,18 +350,24 @@ __global__ __launch_bounds__(kBlk) void k_smooth_forward(SmoothArgs a) {
             end_particle(kEndAngle);
         }
     }
-    // every wave of the block is done: the table's sums go to the raster
+    // every wave of the block is done: the table's sums go to the raster, and the statistics, summed over
+    // the block in LDS, go to the four counters with one atomic each per block (the counters share a
+    // memory line, where device-scope atomics serialise)
+    __shared__ unsigned long long bst[4];
+    if (threadIdx.x < 4) bst[threadIdx.x] = 0ull;
     __syncthreads();
-    for (int k = threadIdx.x; k < kDepSlots; k += kBlk)
-        if (dep.tag[k] != kDepEmpty && dep.val[k] != 0ull) atomicAdd(a.dep_q + dep.tag[k], dep.val[k]);
     const uint64_t s0 = wave_sum64(st_steps), s1 = wave_sum64(st_exit), s2 = wave_sum64(st_stop);
     const uint64_t s3 = wave_sum64(st_limit);
     if (lane == 0) {
-        if (s0) atomicAdd(a.stats + 0, (unsigned long long)s0);
-        if (s1) atomicAdd(a.stats + 1, (unsigned long long)s1);
-        if (s2) atomicAdd(a.stats + 2, (unsigned long long)s2);
-        if (s3) atomicAdd(a.stats + 3, (unsigned long long)s3);
+        lds_add_u64(&bst[0], s0);
+        lds_add_u64(&bst[1], s1);
+        lds_add_u64(&bst[2], s2);
+        lds_add_u64(&bst[3], s3);
     }
+    for (int k = threadIdx.x; k < kDepSlots; k += kBlk)
+        if (dep.tag[k] != kDepEmpty && dep.val[k] != 0ull) atomicAdd(a.dep_q + dep.tag[k], dep.val[k]);
+    __syncthreads();
+    if (threadIdx.x < 4 && bst[threadIdx.x]) atomicAdd(a.stats + threadIdx.x, bst[threadIdx.x]);
 }
 
 __global__ __launch_bounds__(kSmoothBlock) void k_smooth_backward(SmoothArgs a) {
@@ -629,8 +635,8 @@ struct SmoothVariant {
     uint32_t spl;
 };
 // forward candidates: (threads per block, slots per lane); backward: slots per lane at 256 threads
-constexpr SmoothVariant kFwdVariants[] = {{256, 8}, {1024, 2}, {512, 2}};
-constexpr uint32_t kBwdSpl[] = {8, 2};
+constexpr SmoothVariant kFwdVariants[] = {{256, 8}, {1024, 2}, {512, 2}, {1024, 1}, {256, 2}, {512, 4}};
+constexpr uint32_t kBwdSpl[] = {8, 2, 1, 4};
 
 template <int kBlk>
 void launch_fwd(const SmoothArgs& a, hipStream_t s) {
