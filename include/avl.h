@@ -343,6 +343,14 @@ AVL_API int avl_overlay_mipmap(const uint32_t* counts, const float* vmax, int32_
  * (default), 0 = launch eagerly. Returns AVL_EINVAL for an out-of-range variant. */
 AVL_API int avl_set_tuning(int32_t variant, int32_t graphs);
 AVL_API int32_t avl_tuning_variants(void);
+/* The same for the smooth forward (avl_trajectories_smooth) and its adjoint (avl_trajectories_backward):
+ * -1 lets the library's tuner pick a grid shape per problem size, else a fixed variant index in
+ * [0, n) with n from avl_smooth_tuning_variants (grid shapes only: every variant gives identical
+ * results). Returns AVL_EINVAL for an out-of-range index. */
+AVL_API int avl_set_smooth_tuning(int32_t forward_variant, int32_t backward_variant);
+/* Number of smooth forward and adjoint variants into *n_forward, *n_backward (host pointers); AVL_EINVAL
+ * for a NULL pointer. */
+AVL_API int avl_smooth_tuning_variants(int32_t* n_forward, int32_t* n_backward);
 /* Shape of a kernel variant: info (8 host int32) = threads per block, iterations per epoch between table
  * flushes, LDS table slots per block, probes per key, window top-up in blocks of slots, retention threshold
  * (0 = none), waves per SIMD the register budget is sized for, particle slots per lane that size the grid of a

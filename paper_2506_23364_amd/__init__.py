@@ -126,6 +126,10 @@ def _load() -> ctypes.CDLL:
     L.avl_set_tuning.restype = ctypes.c_int
     L.avl_tuning_variants.argtypes = []
     L.avl_tuning_variants.restype = i32
+    L.avl_set_smooth_tuning.argtypes = [i32, i32]
+    L.avl_set_smooth_tuning.restype = ctypes.c_int
+    L.avl_smooth_tuning_variants.argtypes = [vp, vp]
+    L.avl_smooth_tuning_variants.restype = ctypes.c_int
     L.avl_tuning_variant_info.argtypes = [i32, vp]
     L.avl_tuning_variant_info.restype = ctypes.c_int
     L.avl_set_probe.argtypes = [vp, u64]
@@ -197,6 +201,17 @@ def set_tuning(variant: int = -1, graphs: bool = True) -> None:
 
 def tuning_variants() -> int:
     return int(lib.avl_tuning_variants())
+
+
+def set_smooth_tuning(forward: int = -1, backward: int = -1) -> None:
+    """Grid variants of the smooth forward and adjoint: -1 = the library's tuner, else a fixed index."""
+    _check(lib.avl_set_smooth_tuning(forward, backward), "avl_set_smooth_tuning")
+
+
+def smooth_tuning_variants() -> tuple[int, int]:
+    nf, nb = ctypes.c_int32(0), ctypes.c_int32(0)
+    _check(lib.avl_smooth_tuning_variants(ctypes.byref(nf), ctypes.byref(nb)), "avl_smooth_tuning_variants")
+    return int(nf.value), int(nb.value)
 
 
 def variant_info(variant: int) -> dict:

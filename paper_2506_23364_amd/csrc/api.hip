@@ -225,6 +225,7 @@ const char* check_params(const avl_params* p) {
 // ------------------------------------------------------------------ tuning state
 std::mutex g_mu;
 int32_t g_variant_override = -1;
+int32_t g_smooth_override[2] = {-1, -1};  // smooth forward, adjoint
 bool g_graphs = true;
 std::map<std::vector<int64_t>, int> g_best;  // (device, batched, size buckets) -> variant
 
@@ -321,6 +322,11 @@ hipError_t choose_smooth(const std::vector<int64_t>& key, int nv, hipStream_t s,
                          bool may_tune = true) {
     {
         std::lock_guard<std::mutex> lk(g_mu);
+        const int32_t forced = g_smooth_override[key[1] == 2 ? 0 : 1];
+        if (forced >= 0) {
+            *variant = forced < nv ? forced : 0;
+            return hipSuccess;
+        }
         auto it = g_best.find(key);
         if (it != g_best.end()) {
             *variant = it->second;
@@ -405,6 +411,24 @@ int avl_set_tuning(int32_t variant, int32_t graphs) {
 }
 
 int32_t avl_tuning_variants(void) { return avl::trajectory_variants(); }
+
+int avl_set_smooth_tuning(int32_t forward_variant, int32_t backward_variant) {
+    if (forward_variant < -1 || forward_variant >= avl::smooth_forward_variants() || backward_variant < -1 ||
+        backward_variant >= avl::smooth_backward_variants())
+        return AVL_EINVAL;
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_smooth_override[0] = forward_variant;
+    g_smooth_override[1] = backward_variant;
+    return AVL_OK;
+}
+
+int avl_smooth_tuning_variants(int32_t* n_forward, int32_t* n_backward) {
+    g_last_error.clear();
+    if (!n_forward || !n_backward) return fail(AVL_EINVAL, "avl_smooth_tuning_variants: null pointer");
+    *n_forward = avl::smooth_forward_variants();
+    *n_backward = avl::smooth_backward_variants();
+    return AVL_OK;
+}
 
 int avl_tuning_variant_info(int32_t variant, int32_t* info) {
     g_last_error.clear();

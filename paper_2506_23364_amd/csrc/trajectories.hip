@@ -80,6 +80,7 @@ struct Control {
     uint32_t dry;                 // the tail probe has seen the block run out of slots
     uint32_t iters;               // wave-iterations of the epoch's budget claimed so far
     unsigned long long left;      // slots left in the partition after the window's last top-up
+    unsigned long long st[4];     // single run: the block's statistics, summed when its waves are done
 };
 
 // kAlpha: the runout-angle stop is compiled in; a single run without it takes the instantiation without.
@@ -610,7 +611,26 @@ void k_trajectories(TrajArgs a) {
         __syncthreads();
         if (ctl.busy[epoch & 1u] == 0u) break;
     }
-    flush_stats();
+    if constexpr (kBatch) {
+        flush_stats();
+    } else {
+        // every wave leaves the loop at the same boundary: the block's statistics are summed in LDS and
+        // reach the four counters with one atomic each per block, not per wave (the counters share a
+        // memory line, where device-scope atomics serialise)
+        unsigned long long* const bst = ctl.st;
+        if (threadIdx.x < 4) bst[threadIdx.x] = 0ull;
+        __syncthreads();
+        const uint64_t s0 = wave_sum64(st_steps), s1 = wave_sum64(st_exit), s2 = wave_sum64(st_stop);
+        const uint64_t s3 = wave_sum64(st_limit);
+        if (lane == 0) {
+            if (s0) atomicAdd(bst + 0, (unsigned long long)s0);
+            if (s1) atomicAdd(bst + 1, (unsigned long long)s1);
+            if (s2) atomicAdd(bst + 2, (unsigned long long)s2);
+            if (s3) atomicAdd(bst + 3, (unsigned long long)s3);
+        }
+        __syncthreads();
+        if (threadIdx.x < 4 && bst[threadIdx.x]) atomicAdd(a.stats + threadIdx.x, bst[threadIdx.x]);
+    }
     if (probe && threadIdx.x == 0) probe[2] = __builtin_amdgcn_s_memrealtime();
 }
 

@@ -355,3 +355,14 @@ def test_probe_switch_and_grid_query(L):
     assert L.lib.avl_set_probe(None, 0) == L.AVL_OK
     assert L.lib.avl_trajectory_grid(-1) == -1
     assert L.lib.avl_trajectory_grid(L.tuning_variants()) == -1
+
+
+def test_smooth_tuning_override_range(L):
+    nf, nb = L.smooth_tuning_variants()
+    assert nf >= 2 and nb >= 2
+    assert L.lib.avl_set_smooth_tuning(nf, 0) == L.AVL_EINVAL
+    assert L.lib.avl_set_smooth_tuning(0, nb) == L.AVL_EINVAL
+    assert L.lib.avl_set_smooth_tuning(-2, -1) == L.AVL_EINVAL
+    assert L.lib.avl_set_smooth_tuning(nf - 1, nb - 1) == L.AVL_OK
+    assert L.lib.avl_set_smooth_tuning(-1, -1) == L.AVL_OK
+    assert L.lib.avl_smooth_tuning_variants(None, None) == L.AVL_EINVAL

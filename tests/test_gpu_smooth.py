@@ -91,6 +91,34 @@ def test_smooth_cases(avl, name, params, P, S):
     run_both(avl, dem, mask, mass, gD, dict(synth.DEFAULT_PARAMS, **params), P, S, 11, 2, label=name)
 
 
+def test_every_smooth_variant_gives_identical_results(avl):
+    """Each grid variant of the forward (and of the adjoint, forced through avl_set_smooth_tuning) gives the
+    oracle's deposit, statistics and per-particle adjoint terms bit for bit."""
+    dem, mask, mass, gD = case(seed=8, size=80)
+    params = dict(synth.DEFAULT_PARAMS, mu=0.03, xi=INF, randomness=0.1)
+    P, S, seed, run_id = 3, 400, 11, 2
+    p_o = oracle.make_params(**params)
+    ref = oracle.smooth_forward(dem, mask, 10.0, p_o, P, S, seed, run_id, mass=mass, vel_splat=False)
+    g_ref = oracle.smooth_backward(dem, mask, 10.0, p_o, P, S, seed, gD, run_id, mass=mass)
+    n = g_ref.per_particle.shape[0]
+    nf, nb = avl.smooth_tuning_variants()
+    assert nf >= 2 and nb >= 2
+    p = avl.Params.make(**params)
+    try:
+        for v in range(max(nf, nb)):
+            vf, vb = v % nf, v % nb
+            avl.set_smooth_tuning(vf, vb)
+            run = avl.trajectories_smooth(dev(dem), dev(mask), 10.0, p, P, S, seed, run_id, mass=dev(mass))
+            assert np.array_equal(host(run.deposit_q), ref.dep_q), f"forward variant {vf}"
+            assert list(host(run.stats)) == [ref.steps, ref.n_exit, ref.n_stop, ref.n_limit], f"forward variant {vf}"
+            _, dmass, pp = avl.trajectories_backward(run, dev(dem), dev(mask), 10.0, p, P, S, seed, dev(gD), run_id,
+                                                     mass=dev(mass), per_particle=True)
+            assert np.array_equal(host(pp)[:, :n].T, g_ref.per_particle), f"adjoint variant {vb}"
+            assert np.array_equal(host(dmass), g_ref.dmass.astype(np.float32)), f"adjoint variant {vb}"
+    finally:
+        avl.set_smooth_tuning(-1, -1)
+
+
 def test_smooth_deposit_table_overflow(avl):
     """Scattered single-particle releases: a block's ~2000 particles end in more distinct cells (4 corners
     each) than its 4096-slot deposit table holds, so part of the splats take the direct raster atomics."""
