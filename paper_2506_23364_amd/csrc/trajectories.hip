@@ -68,11 +68,14 @@ __device__ __forceinline__ void global_max(uint32_t* __restrict__ p, uint32_t bi
 using namespace dev;
 
 // Workgroup-shared accumulation table: kTbl slots of (cell key, entry count, max v^2 bits) in LDS,
-// open addressing with a few linear probes. Slots are emptied only at epoch boundaries: each boundary
-// flushes a slot to the rasters and empties it, except (with retention on) a slot whose cell was entered
-// often enough in the epoch that ended, which keeps its key, count and maximum into the next epoch.
-// With retention the count word holds two 16-bit halves: the entries so far (low) and their number at
-// the last boundary (high).
+// open addressing with a few linear probes. A particle's visit to a cell (from its entry, or its release,
+// to the step that leaves the cell or ends the path) goes into the table once, when it ends: one entry
+// and the visit's largest v^2 (the counts are the same as counting each entry when it happens, and one
+// table operation per visit replaces a claim at the entry plus a max at the exit). Slots are emptied only
+// at epoch boundaries: each boundary flushes a slot to the rasters and empties it, except (with retention
+// on) a slot whose cell saw enough visits end in the epoch that ended, which keeps its key, count and
+// maximum into the next epoch. With retention the count word holds two 16-bit halves: the entries so far
+// (low) and their number at the last boundary (high).
 template <int kTbl>
 struct Table {
     uint32_t tag[kTbl], cnt[kTbl], vmx[kTbl];
@@ -95,8 +98,8 @@ struct Control {
 // kAlpha: the runout-angle stop is compiled in; a single run without it takes the instantiation without.
 // A single run with it keeps the release point and height in registers; a batch re-derives them from the
 // release cell when a run uses the stop, so its kernel carries no registers for them.
-// kKeep: table retention, 0 off; else a slot whose cell was entered at least kKeep times in the epoch
-// that ended stays in the table (its count and maximum reach the rasters at a later boundary).
+// kKeep: table retention, 0 off; else a slot whose cell saw at least kKeep visits end in the epoch that
+// ended stays in the table (its count and maximum reach the rasters at a later boundary).
 // kWpe: waves per SIMD the register budget is sized for (8: 64 VGPRs; 6: 80).
 // kRec: the recording instantiation (single run): the particles of the recorded range also write their
 // points and end records (a diagnostic; the other instantiations compile none of it).
@@ -105,8 +108,8 @@ template <bool kBatch, bool kAlpha, int kBlock, int kFlush, int kTbl, int kProbe
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWpe)))
 void k_trajectories(TrajArgs a) {
     static_assert(!(kRec && kBatch), "recording is for single runs");
-    // a lane enters a given cell at most once per iteration and a block runs at most kFlush x (waves per
-    // block) wave-iterations per epoch, so a slot gains at most kBlock * kFlush entries per epoch; a
+    // a lane ends at most one visit per iteration and a block runs at most kFlush x (waves per block)
+    // wave-iterations per epoch, so a slot gains at most kBlock * kFlush entries per epoch; a
     // retained count stays below kKeepCap, so the low half never carries
     static_assert(kKeep == 0 || kBlock * kFlush <= 32768, "retention needs 16-bit counts per epoch");
     constexpr uint32_t kKeepCap = 65536u - (uint32_t)(kBlock * kFlush);
@@ -159,18 +162,33 @@ void k_trajectories(TrajArgs a) {
     // another cell. Within an epoch slots are only filled, never emptied, so a key's first probe that is
     // empty or holds it is the same for every lane. (A retained key can find an earlier probe emptied at
     // the boundary and take that one as well: two slots of one cell, both flushed, the sums unchanged.)
+    // The probes' tags are read in groups of kGroup, one LDS round trip per group, and the group's slots
+    // are then taken in probe order: a read that shows the key is final (only the key's own claim writes
+    // it), one that shows another key stays true (slots are not emptied within an epoch), and one that shows
+    // an empty slot is settled by the compare-and-swap. So the slot taken is the first in probe order that
+    // is empty or holds the key, as with one probe at a time, but a claim no longer waits for up to kProbes
+    // dependent round trips.
     auto claim = [&](uint32_t key) -> int {
+        constexpr int kGroup = 4;
         const uint32_t h = (uint32_t)(((uint64_t)(key * 0x9E3779B1u) * (uint64_t)kTbl) >> 32);
 #pragma unroll
-        for (int q = 0; q < kProbes; ++q) {
-            uint32_t sl = h + (uint32_t)q;
-            if (sl >= (uint32_t)kTbl) sl -= (uint32_t)kTbl;
-            uint32_t t = lds_ld(tb.tag + sl);
-            if (t == kEmpty) {
-                const uint32_t old = atomicCAS(tb.tag + sl, kEmpty, key);
-                t = (old == kEmpty) ? key : old;
+        for (int g = 0; g < kProbes; g += kGroup) {
+            uint32_t sl[kGroup], t[kGroup];
+#pragma unroll
+            for (int i = 0; i < kGroup && g + i < kProbes; ++i) {
+                sl[i] = h + (uint32_t)(g + i);
+                if (sl[i] >= (uint32_t)kTbl) sl[i] -= (uint32_t)kTbl;
+                t[i] = lds_ld(tb.tag + sl[i]);
             }
-            if (t == key) return (int)sl;
+#pragma unroll
+            for (int i = 0; i < kGroup && g + i < kProbes; ++i) {
+                uint32_t ti = t[i];
+                if (ti == kEmpty) {
+                    const uint32_t old = atomicCAS(tb.tag + sl[i], kEmpty, key);
+                    ti = (old == kEmpty) ? key : old;
+                }
+                if (ti == key) return (int)sl[i];
+            }
         }
         return -1;
     };
@@ -258,7 +276,6 @@ void k_trajectories(TrajArgs a) {
     bool alive = false;
     float x = 0, y = 0, z = 0, gx = 0, gy = 0, dx = 0, dy = 0, v2 = 0, x0 = 0, y0 = 0, zr = 0, cmax2 = 0;
     uint32_t n = 0, rep = 0, cell_id = 0, spare_x = 0, spare_y = 0, cur = 0;
-    int my_slot = -1;  // table slot of the current cell in this epoch, -1 if none
     uint32_t rk = ~0u;  // recording: index of the lane's particle in the recorded range, ~0 if outside it
     auto rec_point = [&](uint32_t m, float px, float py, float pv2) {
         if constexpr (kRec) {
@@ -280,14 +297,6 @@ void k_trajectories(TrajArgs a) {
         }
     };
 
-    auto count_entry = [&](bool e) {
-        if (!e) return;
-        my_slot = claim(cur);
-        if (my_slot >= 0)
-            atomicAdd(tb.cnt + my_slot, 1u);
-        else
-            atomicAdd(counts + cur, 1u);
-    };
 
     constexpr uint32_t kBudget = (uint32_t)kFlush * (uint32_t)(kBlock / kWave);  // wave-iterations per epoch
     uint32_t wit = 0;  // the wave's iterations so far; a live particle's step count has their parity
@@ -444,13 +453,11 @@ void k_trajectories(TrajArgs a) {
                     }
                 }
             }
-            count_entry(fresh);  // entry into the release cell
 
             // ---- one step of every live particle
             const RunConst& R = rc;
-            bool leave = false, entered = false;
+            bool leave = false;  // a visit ended: its cell and largest v^2
             uint32_t leave_bits = 0;
-            int leave_slot = -1;
             uint32_t leave_key = 0;
             if (alive) {
                 bool ended = false;
@@ -533,13 +540,11 @@ void k_trajectories(TrajArgs a) {
                             const uint32_t nc =
                                 R.raster_off + (uint32_t)(int)fr1 * (uint32_t)W + (uint32_t)(int)fc1;
                             if (nc != cur) {
-                                leave = cmax2 > 0.0f;
+                                leave = true;
                                 leave_bits = __float_as_uint(cmax2);
-                                leave_slot = my_slot;
                                 leave_key = cur;
                                 cur = nc;
                                 cmax2 = v2;
-                                entered = true;
                             } else if (v2 > cmax2) {
                                 cmax2 = v2;
                             }
@@ -547,23 +552,23 @@ void k_trajectories(TrajArgs a) {
                     }
                 }
                 if (ended) {
-                    leave = cmax2 > 0.0f;
+                    leave = true;
                     leave_bits = __float_as_uint(cmax2);
-                    leave_slot = my_slot;
                     leave_key = cur;
                     alive = false;
                 }
             }
-            // ---- accumulate: max of the cell left, entry count of the cell entered
+            // ---- accumulate the visit that ended: its entry and its largest v^2 (0 bits: nothing to max)
             if (leave) {
-                int sl = leave_slot;
-                if (sl < 0) sl = claim(leave_key);
-                if (sl >= 0)
-                    atomicMax(tb.vmx + sl, leave_bits);
-                else
-                    global_max(vmax2 + leave_key, leave_bits);
+                const int sl = claim(leave_key);
+                if (sl >= 0) {
+                    atomicAdd(tb.cnt + sl, 1u);
+                    if (leave_bits) atomicMax(tb.vmx + sl, leave_bits);
+                } else {
+                    atomicAdd(counts + leave_key, 1u);
+                    if (leave_bits) global_max(vmax2 + leave_key, leave_bits);
+                }
             }
-            count_entry(entered);
         }
 
         // ---- epoch boundary: count the waves with work left, flush the table, refill the window
@@ -616,7 +621,6 @@ void k_trajectories(TrajArgs a) {
 #pragma unroll
         for (int j = 0; j < kPer; ++j)  // a stale read >= v suffices
             if (!keep[j] && ft[j] != kEmpty && fg[j] < fv[j]) atomicMax(vmax2 + ft[j], fv[j]);
-        my_slot = -1;
         __syncthreads();
         if (ctl.busy[epoch & 1u] == 0u) break;
     }
