@@ -144,6 +144,31 @@ def test_ragged_grid_param_grid(avl, name, params):
     both(avl, dem, mask, 10.0, params, 7, 600, 0xDEADBEEF12345678, 3, name)
 
 
+def test_reused_rasters_after_a_faster_pass(avl):
+    """The max check before a raster max reads the cell as the caches hold it. Rasters that a previous pass
+    left with larger speeds (low friction) are reused by a pass with smaller ones, on every trajectory
+    variant: a value cached from the earlier pass would skip maxima and leave cells too low, so each second
+    pass must still equal the oracle."""
+    dem = synth.alpine_dem(160, 900.0, seed=41)
+    nrm = oracle.normals(dem, 10.0)
+    mask = oracle.release_mask(nrm, dem, 28.0, 45.0, float(np.quantile(dem, 0.4)), INF)
+    fast = dict(synth.DEFAULT_PARAMS, mu=0.02, xi=8000.0)
+    slow = dict(synth.DEFAULT_PARAMS, mu=0.3, xi=800.0)
+    ref_slow = oracle.trajectories(dem, mask, 10.0, oracle.make_params(**slow), 8, 800, 21)
+    d, m = dev(dem), dev(mask)
+    try:
+        for v in range(avl.tuning_variants()):
+            avl.set_tuning(v, True)
+            res = avl.trajectories(d, m, 10.0, avl.Params.make(**fast), 8, 800, 21)
+            fast_vmax = host(res.vmax)
+            res = avl.trajectories(d, m, 10.0, avl.Params.make(**slow), 8, 800, 21, 0, res)
+            got = (host(res.counts), host(res.vmax), host(res.stats))
+            assert fast_vmax.max() > got[1].max()
+            assert_run_equal(got, ref_slow, f"variant {v}")
+    finally:
+        avl.set_tuning(-1, True)
+
+
 def test_bruteforce_8x8_cases(avl):
     rng = np.random.default_rng(8)
     for case in range(24):
