@@ -460,103 +460,93 @@ void k_trajectories(TrajArgs a) {
             uint32_t leave_bits = 0;
             uint32_t leave_key = 0;
             if (alive) {
-                bool ended = false;
-                if (n >= a.S) {
-                    ++st_limit;
-                    ended = true;
-                    rec_end(0u);
+                // Every live lane runs the whole step and the outcome selects what it keeps: a lane at the
+                // step limit, leaving the grid or stopping discards its target (an off-grid target's gather
+                // reads through the buffer's bounds check, so it cannot fault). Without the nested branches
+                // the compiler no longer copies the particle state at every join (5 % of the alpine pass).
+                const bool lim = n >= a.S;
+                uint32_t ux, uy;
+                if ((it & 1) == 0) {  // n is even
+                    // the key is wave-uniform: pinning it to scalar registers here makes the round keys
+                    // scalar adds inside the block instead of 20 loop-invariant values hoisted out of the
+                    // loop, spilled to vector lanes and read back by VALU instructions
+                    uint32_t k0 = __builtin_amdgcn_readfirstlane(R.key0);
+                    uint32_t k1 = __builtin_amdgcn_readfirstlane(R.key1);
+                    asm volatile("" : "+s"(k0), "+s"(k1));
+                    const uint4 o = philox4x32_10(n >> 1, rep, cell_id, R.run, k0, k1);
+                    ux = o.x;
+                    uy = o.y;
+                    spare_x = o.z;
+                    spare_y = o.w;
                 } else {
-                    ++st_steps;
-                    uint32_t ux, uy;
-                    if ((it & 1) == 0) {  // n is even
-                        // the key is wave-uniform: pinning it to scalar registers here makes the round
-                        // keys scalar adds inside the block instead of 20 loop-invariant values hoisted
-                        // out of the loop, spilled to vector lanes and read back by VALU instructions
-                        uint32_t k0 = __builtin_amdgcn_readfirstlane(R.key0);
-                        uint32_t k1 = __builtin_amdgcn_readfirstlane(R.key1);
-                        asm volatile("" : "+s"(k0), "+s"(k1));
-                        const uint4 o = philox4x32_10(n >> 1, rep, cell_id, R.run, k0, k1);
-                        ux = o.x;
-                        uy = o.y;
-                        spare_x = o.z;
-                        spare_y = o.w;
-                    } else {
-                        ux = spare_x;
-                        uy = spare_y;
+                    ux = spare_x;
+                    uy = spare_y;
+                }
+                const float rx = signed_unit(ux), ry = signed_unit(uy);
+                const float gg = gx * gx + gy * gy;
+                const float t = gg > 0.0f ? R.Q / sqrt_rn(gg) : 0.0f;
+                const float wx = (R.per * dx - t * gx) + R.rnd * rx;
+                const float wy = (R.per * dy - t * gy) + R.rnd * ry;
+                const float ww = wx * wx + wy * wy;
+                if (ww > 0.0f) {
+                    const float inv = 1.0f / sqrt_rn(ww);
+                    dx = wx * inv;
+                    dy = wy * inv;
+                }
+                const float x1 = x + R.L * dx;
+                const float y1 = y + R.L * dy;
+                const float fc1 = floorf(x1), fr1 = floorf(y1);
+                const bool inb = !lim && fc1 >= 0.0f && fc1 < fW && fr1 >= 0.0f && fr1 < fH;
+                const Sample s1 = bilinear_pad(dem_rs, Wp, row_bytes, x1, y1);
+                const float dz = z - s1.z;
+                const float ds = sqrt_rn(R.dl2 + dz * dz);
+                const float num = v2 + a.g2 * (dz - R.mdl);
+                bool stop = !(num > 0.0f);
+                const float v2n = num / (1.0f + R.cd * ds);
+                if (kAlpha && R.use_alpha) {
+                    float ax0 = x0, ay0 = y0, azr = zr;
+                    if (kBatch) {  // the release cell's centre and the height sampled there
+                        const uint32_t rr = udiv(cell_id, a.wdiv), cc = cell_id - rr * (uint32_t)W;
+                        ax0 = (float)cc + 0.5f;
+                        ay0 = (float)rr + 0.5f;
+                        azr = bilinear_pad(dem_rs, Wp, row_bytes, ax0, ay0).z;
                     }
-                    const float rx = signed_unit(ux), ry = signed_unit(uy);
-                    const float gg = gx * gx + gy * gy;
-                    const float t = gg > 0.0f ? R.Q / sqrt_rn(gg) : 0.0f;
-                    const float wx = (R.per * dx - t * gx) + R.rnd * rx;
-                    const float wy = (R.per * dy - t * gy) + R.rnd * ry;
-                    const float ww = wx * wx + wy * wy;
-                    if (ww > 0.0f) {
-                        const float inv = 1.0f / sqrt_rn(ww);
-                        dx = wx * inv;
-                        dy = wy * inv;
-                    }
-                    const float x1 = x + R.L * dx;
-                    const float y1 = y + R.L * dy;
-                    const float fc1 = floorf(x1), fr1 = floorf(y1);
-                    if (!(fc1 >= 0.0f && fc1 < fW && fr1 >= 0.0f && fr1 < fH)) {
-                        ++st_exit;
-                        ended = true;
+                    const float hx = x1 - ax0, hy = y1 - ay0;
+                    stop = stop || (azr - s1.z) < R.tca * sqrtf(hx * hx + hy * hy);
+                }
+                const bool acc = inb && !stop;
+                st_limit += lim ? 1u : 0u;
+                st_steps += lim ? 0u : 1u;
+                st_exit += (!lim && !inb) ? 1u : 0u;
+                st_stop += (inb && stop) ? 1u : 0u;
+                if constexpr (kRec) {
+                    if (lim)
+                        rec_end(0u);
+                    else if (!inb)
                         rec_end(1u);
-                    } else {
-                        const Sample s1 = bilinear_pad(dem_rs, Wp, row_bytes, x1, y1);
-                        const float dz = z - s1.z;
-                        const float ds = sqrt_rn(R.dl2 + dz * dz);
-                        const float num = v2 + a.g2 * (dz - R.mdl);
-                        bool stop = !(num > 0.0f);
-                        float v2n = 0.0f;
-                        if (!stop) {
-                            v2n = num / (1.0f + R.cd * ds);
-                            if (kAlpha && R.use_alpha) {
-                                float ax0 = x0, ay0 = y0, azr = zr;
-                                if (kBatch) {  // the release cell's centre and the height sampled there
-                                    const uint32_t rr = udiv(cell_id, a.wdiv), cc = cell_id - rr * (uint32_t)W;
-                                    ax0 = (float)cc + 0.5f;
-                                    ay0 = (float)rr + 0.5f;
-                                    azr = bilinear_pad(dem_rs, Wp, row_bytes, ax0, ay0).z;
-                                }
-                                const float hx = x1 - ax0, hy = y1 - ay0;
-                                stop = (azr - s1.z) < R.tca * sqrtf(hx * hx + hy * hy);
-                            }
-                        }
-                        if (stop) {
-                            ++st_stop;
-                            ended = true;
-                            rec_point(n + 1u, x1, y1, 0.0f);
-                            rec_end(2u);
-                        } else {
-                            x = x1;
-                            y = y1;
-                            z = s1.z;
-                            gx = s1.gx;
-                            gy = s1.gy;
-                            v2 = v2n;
-                            ++n;
-                            rec_point(n, x, y, v2);
-                            const uint32_t nc =
-                                R.raster_off + (uint32_t)(int)fr1 * (uint32_t)W + (uint32_t)(int)fc1;
-                            if (nc != cur) {
-                                leave = true;
-                                leave_bits = __float_as_uint(cmax2);
-                                leave_key = cur;
-                                cur = nc;
-                                cmax2 = v2;
-                            } else if (v2 > cmax2) {
-                                cmax2 = v2;
-                            }
-                        }
+                    else if (stop) {
+                        rec_point(n + 1u, x1, y1, 0.0f);
+                        rec_end(2u);
                     }
                 }
-                if (ended) {
-                    leave = true;
-                    leave_bits = __float_as_uint(cmax2);
-                    leave_key = cur;
-                    alive = false;
+                x = acc ? x1 : x;
+                y = acc ? y1 : y;
+                z = acc ? s1.z : z;
+                gx = acc ? s1.gx : gx;
+                gy = acc ? s1.gy : gy;
+                v2 = acc ? v2n : v2;
+                n += acc ? 1u : 0u;
+                if constexpr (kRec) {
+                    if (acc) rec_point(n, x, y, v2);
                 }
+                const uint32_t nc = R.raster_off + (uint32_t)(int)fr1 * (uint32_t)W + (uint32_t)(int)fc1;
+                const bool change = acc && nc != cur;
+                leave = change || !acc;
+                leave_bits = __float_as_uint(cmax2);
+                leave_key = cur;
+                cur = change ? nc : cur;
+                cmax2 = change ? v2 : ((acc && v2 > cmax2) ? v2 : cmax2);
+                alive = acc;
             }
             // ---- accumulate the visit that ended: its entry and its largest v^2 (0 bits: nothing to max)
             if (leave) {
