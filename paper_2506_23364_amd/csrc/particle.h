@@ -15,8 +15,11 @@ __device__ __forceinline__ uint4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_
                                                uint32_t k1) {
 #pragma unroll
     for (int round = 0; round < 10; ++round) {
-        const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
-        const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+        // each 32 x 32 -> 64-bit product as one v_mad_u64_u32 (both halves at the cost of one quarter-rate
+        // multiply; a low and a high multiply written apart are two)
+        const uint64_t p0 = (uint64_t)c0 * 0xD2511F53u, p1 = (uint64_t)c2 * 0xCD9E8D57u;
+        const uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
+        const uint32_t lo1 = (uint32_t)p1, hi1 = (uint32_t)(p1 >> 32);
         // three-way XORs as single gfx950 three-input bit operations (truth table 0x96)
         const uint32_t n0 = __builtin_amdgcn_bitop3_b32(hi1, c1, k0, 0x96);
         const uint32_t n2 = __builtin_amdgcn_bitop3_b32(hi0, c3, k1, 0x96);
@@ -52,9 +55,36 @@ __device__ __forceinline__ float sqrt_rn(float x) {
     return sqrt_rn_big(x);
 }
 
-// 24 random bits -> uniform in [-1, 1), exact in binary32
+// a / b correctly rounded, for b in [2^-40, 2^40] and a = 0 or |a| in [2^-40, 2^40]: the compiler's division
+// sequence (hardware reciprocal, one Newton step on it, two fma-corrected quotient steps) without its operand
+// scaling and its special-value fix-up. Both are identities for such operands (no operand or quotient near the
+// subnormal or overflow range, exponents less than 96 apart), so the bits are those of a / b.
+__device__ __forceinline__ float div_rn_mid(float a, float b) {
+    const float r = __builtin_amdgcn_rcpf(b);
+    const float r1 = __builtin_fmaf(__builtin_fmaf(-b, r, 1.0f), r, r);
+    const float q0 = a * r1;
+    const float q1 = __builtin_fmaf(__builtin_fmaf(-b, q0, a), r1, q0);
+    return __builtin_fmaf(__builtin_fmaf(-b, q1, a), r1, q1);
+}
+
+// x in [2^-80, 2^80] (one unsigned compare of the bits; NaN and negative x fall outside), so that
+// sqrt_rn_big(x) lies in [2^-40, 2^40]
+__device__ __forceinline__ bool mid_range(float x) {
+    return __float_as_uint(x) - 0x17800000u <= 0x67800000u - 0x17800000u;
+}
+
+// q / sqrtf(x), both correctly rounded, for x > 0 and q = 0 or |q| in [2^-40, 2^40]: sqrt_rn_big and div_rn_mid
+// when every active lane of the wave has x in [2^-80, 2^80] (a wave-uniform branch), else sqrtf and the
+// compiler's division
+__device__ __forceinline__ float div_sqrt_rn(float q, float x) {
+    if (__builtin_expect(__ballot(!mid_range(x)) != 0ull, 0)) return q / sqrtf(x);
+    return div_rn_mid(q, sqrt_rn_big(x));
+}
+
+// 24 random bits m -> 2 (m 2^-24) - 1, uniform in [-1, 1). Both products are exact and so is the difference
+// ((m - 2^23) 2^-23 needs at most 24 significant bits), so one fma gives the same bits.
 __device__ __forceinline__ float signed_unit(uint32_t u) {
-    return 2.0f * ((float)(u >> 8) * 5.9604644775390625e-8f) - 1.0f;
+    return __builtin_fmaf((float)(u >> 8), 0x1p-23f, -1.0f);
 }
 
 struct Sample {

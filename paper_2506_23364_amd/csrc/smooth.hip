@@ -82,12 +82,12 @@ __device__ __forceinline__ StepOut step(State& s, uint32_t n, uint32_t rep, uint
     }
     const float rx = signed_unit(ux), ry = signed_unit(uy);
     const float gg = s.gx * s.gx + s.gy * s.gy;
-    const float t = gg > 0.0f ? rc.Q / sqrtf(gg) : 0.0f;
+    const float t = gg > 0.0f ? div_sqrt_rn(rc.Q, gg) : 0.0f;  // Q = 1 - persistence: 0 or in [2^-24, 1]
     const float wx = (rc.per * s.dx - t * s.gx) + rc.rnd * rx;
     const float wy = (rc.per * s.dy - t * s.gy) + rc.rnd * ry;
     const float ww = wx * wx + wy * wy;
     if (ww > 0.0f) {
-        const float inv = 1.0f / sqrtf(ww);
+        const float inv = div_sqrt_rn(1.0f, ww);
         s.dx = wx * inv;
         s.dy = wy * inv;
     }
@@ -102,7 +102,12 @@ __device__ __forceinline__ StepOut step(State& s, uint32_t n, uint32_t rep, uint
     }
     const Sample s1 = sample(dem, o.x1, o.y1);
     const float dz = s.z - s1.z;
-    const float ds = sqrtf(rc.dl2 + dz * dz);
+    // dl2 + dz^2 >= dl2: with dl2 >= 2^-96 (a run constant) no lane needs the small-argument check
+    float ds;
+    if (rc.dl2 >= 0x1p-96f)
+        ds = sqrt_rn_big(rc.dl2 + dz * dz);
+    else
+        ds = sqrt_rn(rc.dl2 + dz * dz);
     o.num = s.v2 + g2 * (dz - rc.mdl);
     if (!(o.num > 0.0f)) {
         o.outcome = kStop;

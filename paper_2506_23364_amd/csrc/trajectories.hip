@@ -484,12 +484,13 @@ void k_trajectories(TrajArgs a) {
                 }
                 const float rx = signed_unit(ux), ry = signed_unit(uy);
                 const float gg = gx * gx + gy * gy;
-                const float t = gg > 0.0f ? R.Q / sqrt_rn(gg) : 0.0f;
+                // Q = 1 - persistence is 0 or in [2^-24, 1] (persistence in [0, 1])
+                const float t = gg > 0.0f ? div_sqrt_rn(R.Q, gg) : 0.0f;
                 const float wx = (R.per * dx - t * gx) + R.rnd * rx;
                 const float wy = (R.per * dy - t * gy) + R.rnd * ry;
                 const float ww = wx * wx + wy * wy;
                 if (ww > 0.0f) {
-                    const float inv = 1.0f / sqrt_rn(ww);
+                    const float inv = div_sqrt_rn(1.0f, ww);
                     dx = wx * inv;
                     dy = wy * inv;
                 }
@@ -499,7 +500,12 @@ void k_trajectories(TrajArgs a) {
                 const bool inb = !lim && fc1 >= 0.0f && fc1 < fW && fr1 >= 0.0f && fr1 < fH;
                 const Sample s1 = bilinear_pad(dem_rs, Wp, row_bytes, x1, y1);
                 const float dz = z - s1.z;
-                const float ds = sqrt_rn(R.dl2 + dz * dz);
+                // dl2 + dz^2 >= dl2: with dl2 >= 2^-96 (a run constant) no lane needs the small-argument check
+                float ds;
+                if (R.dl2 >= 0x1p-96f)
+                    ds = sqrt_rn_big(R.dl2 + dz * dz);
+                else
+                    ds = sqrt_rn(R.dl2 + dz * dz);
                 const float num = v2 + a.g2 * (dz - R.mdl);
                 bool stop = !(num > 0.0f);
                 const float v2n = num / (1.0f + R.cd * ds);
@@ -539,7 +545,9 @@ void k_trajectories(TrajArgs a) {
                 if constexpr (kRec) {
                     if (acc) rec_point(n, x, y, v2);
                 }
-                const uint32_t nc = R.raster_off + (uint32_t)(int)fr1 * (uint32_t)W + (uint32_t)(int)fc1;
+                // row x W as a 24-bit multiply (full rate; a 32-bit one is quarter rate): both factors are below
+                // 2^23 on an accepted grid and nc is used only for a step inside it
+                const uint32_t nc = R.raster_off + __umul24((uint32_t)(int)fr1, (uint32_t)W) + (uint32_t)(int)fc1;
                 const bool change = acc && nc != cur;
                 leave = change || !acc;
                 leave_bits = __float_as_uint(cmax2);
