@@ -249,12 +249,18 @@ void k_trajectories(TrajArgs a) {
     RunConst rc = uniform_run(a.runs[0]);
     __amdgpu_buffer_rsrc_t dem_rs = buffer_rsrc(a.dem_pad + rc.pad_off, a.pad_bytes);
 
-    // per-lane statistics of run wrun, added to the run's counters when the wave changes run or ends
-    uint64_t st_steps = 0;
+    // per-lane statistics of run wrun, added to the run's counters when the wave changes run or ends. A
+    // step is a move that does not hit the step limit: it is accepted, leaves the grid or stops, so the
+    // steps are the accepted ones (each particle's final n, added when its lane takes the next particle or
+    // the statistics are flushed) plus the exits and stops, and no counter moves per step for them.
+    uint64_t st_acc = 0;
     uint32_t st_exit = 0, st_stop = 0, st_limit = 0;
+    uint32_t n = 0;  // the lane's particle: accepted steps so far (not yet in st_acc)
     auto flush_stats = [&]() {
-        const uint64_t s0 = wave_sum64(st_steps), s1 = wave_sum64(st_exit), s2 = wave_sum64(st_stop);
-        const uint64_t s3 = wave_sum64(st_limit);
+        st_acc += n;
+        n = 0;
+        const uint64_t s1 = wave_sum64(st_exit), s2 = wave_sum64(st_stop);
+        const uint64_t s0 = wave_sum64(st_acc) + s1 + s2, s3 = wave_sum64(st_limit);
         if (lane == 0) {
             unsigned long long* st = a.stats + 4 * (size_t)wrun;
             if (s0) atomicAdd(st + 0, (unsigned long long)s0);
@@ -262,7 +268,7 @@ void k_trajectories(TrajArgs a) {
             if (s2) atomicAdd(st + 2, (unsigned long long)s2);
             if (s3) atomicAdd(st + 3, (unsigned long long)s3);
         }
-        st_steps = 0;
+        st_acc = 0;
         st_exit = st_stop = st_limit = 0;
     };
 
@@ -275,7 +281,7 @@ void k_trajectories(TrajArgs a) {
     // lane state
     bool alive = false;
     float x = 0, y = 0, z = 0, gx = 0, gy = 0, dx = 0, dy = 0, v2 = 0, x0 = 0, y0 = 0, zr = 0, cmax2 = 0;
-    uint32_t n = 0, rep = 0, cell_id = 0, spare_x = 0, spare_y = 0, cur = 0;
+    uint32_t rep = 0, cell_id = 0, spare_x = 0, spare_y = 0, cur = 0;
     uint32_t rk = ~0u;  // recording: index of the lane's particle in the recorded range, ~0 if outside it
     auto rec_point = [&](uint32_t m, float px, float py, float pv2) {
         if constexpr (kRec) {
@@ -439,6 +445,7 @@ void k_trajectories(TrajArgs a) {
                     }
                     v2 = 0.0f;
                     cmax2 = 0.0f;
+                    st_acc += n;  // the lane's previous particle
                     n = 0;
                     // the raster cell of the release point: the release texel's index keys the random
                     // stream, the DEM cell under its centre takes the counts (the same cell at one texel per
@@ -522,7 +529,6 @@ void k_trajectories(TrajArgs a) {
                 }
                 const bool acc = inb && !stop;
                 st_limit += lim ? 1u : 0u;
-                st_steps += lim ? 0u : 1u;
                 st_exit += (!lim && !inb) ? 1u : 0u;
                 st_stop += (inb && stop) ? 1u : 0u;
                 if constexpr (kRec) {
@@ -631,8 +637,9 @@ void k_trajectories(TrajArgs a) {
         unsigned long long* const bst = ctl.st;
         if (threadIdx.x < 4) bst[threadIdx.x] = 0ull;
         __syncthreads();
-        const uint64_t s0 = wave_sum64(st_steps), s1 = wave_sum64(st_exit), s2 = wave_sum64(st_stop);
-        const uint64_t s3 = wave_sum64(st_limit);
+        st_acc += n;
+        const uint64_t s1 = wave_sum64(st_exit), s2 = wave_sum64(st_stop);
+        const uint64_t s0 = wave_sum64(st_acc) + s1 + s2, s3 = wave_sum64(st_limit);
         if (lane == 0) {
             if (s0) atomicAdd(bst + 0, (unsigned long long)s0);
             if (s1) atomicAdd(bst + 1, (unsigned long long)s1);
