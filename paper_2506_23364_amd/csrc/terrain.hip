@@ -270,21 +270,34 @@ __device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t* total) {
     return before + inc - v;
 }
 
-__device__ inline uint32_t count16(const uint8_t* __restrict__ mask, int64_t base, int64_t n) {
-    uint32_t c = 0;
-#pragma unroll
-    for (int k = 0; k < kScanPerThread; ++k) {
-        const int64_t i = base + k;
-        if (i < n) c += mask[i] != 0;
-    }
-    return c;
+// the 16 mask bytes of a thread, [base, base + 16): one 16-byte load when all of them are in range and the
+// address is 16-byte aligned (a lane per 16 bytes, so a wave reads 1 KiB contiguously), else byte by byte with
+// the bytes past n read as 0
+__device__ inline uint4 mask16(const uint8_t* __restrict__ mask, int64_t base, int64_t n) {
+    static_assert(kScanPerThread == 16, "one 16-byte load per thread");
+    if (base + 16 <= n && (reinterpret_cast<uintptr_t>(mask + base) & 15) == 0)
+        return *reinterpret_cast<const uint4*>(mask + base);
+    uint32_t w[4] = {0u, 0u, 0u, 0u};
+    for (int k = 0; k < 16; ++k)
+        if (base + k < n) w[k >> 2] |= (uint32_t)mask[base + k] << (8 * (k & 3));
+    return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+// bit 7 of each byte of the result is set iff that byte of w is nonzero
+__device__ inline uint32_t nonzero_bytes(uint32_t w) {
+    return (((w & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | w) & 0x80808080u;
+}
+
+__device__ inline uint32_t count16(const uint4 m) {
+    return __popc(nonzero_bytes(m.x)) + __popc(nonzero_bytes(m.y)) + __popc(nonzero_bytes(m.z)) +
+           __popc(nonzero_bytes(m.w));
 }
 
 __global__ __launch_bounds__(kScanThreads) void k_compact_count(const uint8_t* __restrict__ mask, int64_t n,
                                                                 uint32_t* __restrict__ blk) {
     const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanPerThread;
     uint32_t total;
-    (void)block_excl_scan(count16(mask, base, n), &total);
+    (void)block_excl_scan(count16(mask16(mask, base, n)), &total);
     if (threadIdx.x == 0) blk[blockIdx.x] = total;
 }
 
@@ -322,12 +335,12 @@ __global__ __launch_bounds__(kScanThreads) void k_compact_write(const uint8_t* _
                                                                 int32_t* __restrict__ cells) {
     const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanPerThread;
     uint32_t total;
-    uint32_t pos = blk[blockIdx.x] + block_excl_scan(count16(mask, base, n), &total);
+    const uint4 m = mask16(mask, base, n);
+    uint32_t pos = blk[blockIdx.x] + block_excl_scan(count16(m), &total);
+    const uint32_t w[4] = {nonzero_bytes(m.x), nonzero_bytes(m.y), nonzero_bytes(m.z), nonzero_bytes(m.w)};
 #pragma unroll
-    for (int k = 0; k < kScanPerThread; ++k) {
-        const int64_t i = base + k;
-        if (i < n && mask[i] != 0) cells[pos++] = (int32_t)i;
-    }
+    for (int k = 0; k < kScanPerThread; ++k)  // bytes past n were read as 0
+        if ((w[k >> 2] >> (8 * (k & 3) + 7)) & 1u) cells[pos++] = (int32_t)(base + k);
 }
 
 hipError_t launch_compact(const uint8_t* mask, int64_t n, int32_t* cells, int32_t* n_cells, uint32_t* blk,
@@ -362,12 +375,17 @@ __global__ __launch_bounds__(256) void k_fill_u64(unsigned long long* __restrict
 // bilinear patch reads, so the padded lookup needs no clamps.
 __global__ __launch_bounds__(256) void k_pad_dem(const float* __restrict__ dem, int H, int W,
                                                  float* __restrict__ out) {
-    const int64_t Wp = (int64_t)W + 2, n = ((int64_t)H + 2) * Wp;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t rp = i / Wp, cp = i - rp * Wp;
+    // rows over blockIdx.y, columns over blockIdx.x and the threads: no division per texel
+    const int64_t Wp = (int64_t)W + 2;
+    for (int64_t rp = blockIdx.y; rp < (int64_t)H + 2; rp += gridDim.y) {
         const int64_t r = rp < 1 ? 0 : (rp > H ? H - 1 : rp - 1);
-        const int64_t c = cp < 1 ? 0 : (cp > W ? W - 1 : cp - 1);
-        out[i] = dem[r * W + c];
+        const float* __restrict__ src = dem + r * W;
+        float* __restrict__ dst = out + rp * Wp;
+        for (int64_t cp = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; cp < Wp;
+             cp += (int64_t)gridDim.x * blockDim.x) {
+            const int64_t c = cp < 1 ? 0 : (cp > W ? W - 1 : cp - 1);
+            dst[cp] = src[c];
+        }
     }
 }
 
@@ -392,9 +410,9 @@ static unsigned blocks_for(int64_t items, int per_thread) {
 }
 
 hipError_t launch_pad_dem(const float* dem, int H, int W, float* out, hipStream_t s) {
-    const int64_t n = ((int64_t)H + 2) * ((int64_t)W + 2);
-    const unsigned blocks = blocks_for(n, 4);
-    hipLaunchKernelGGL(k_pad_dem, dim3(blocks), dim3(256), 0, s, dem, H, W, out);
+    const int64_t col_blocks = std::min<int64_t>(((int64_t)W + 2 + 1023) / 1024, 1024);  // ~4 texels per thread
+    const int64_t row_blocks = std::min<int64_t>((int64_t)H + 2, 65535);
+    hipLaunchKernelGGL(k_pad_dem, dim3((unsigned)col_blocks, (unsigned)row_blocks), dim3(256), 0, s, dem, H, W, out);
     return hipGetLastError();
 }
 
