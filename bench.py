@@ -114,8 +114,8 @@ def timed_passes(avl, torch, w, dem, steps: int, warmup: int) -> dict:
     def step(timed: bool):
         if timed:
             ev[0].record(stream)
-        nrm = avl.normals(dem, w.cell_size)
-        mask = avl.release_mask(nrm, dem, w.slope_min_deg, w.slope_max_deg, w.z_min, w.z_max)
+        # normals and release map in one pass (the same bits as the two calls)
+        nrm, mask = avl.normals_release_mask(dem, w.cell_size, w.slope_min_deg, w.slope_max_deg, w.z_min, w.z_max)
         if timed:
             ev[1].record(stream)
         state["res"] = avl.trajectories(dem, mask, w.cell_size, params, w.particles_per_cell, w.step_limit, w.seed, 0,

@@ -72,6 +72,14 @@ AVL_API int avl_normals(const float* dem, int32_t H, int32_t W, float cell_size,
 AVL_API int avl_release_mask(const float* normals4, const float* dem, int32_t H, int32_t W, float slope_min_deg,
                      float slope_max_deg, float z_min, float z_max, uint8_t* mask, void* stream);
 
+/* Normals and release map in one pass (sections 5.1 and 5.2: the normals node feeding the release-point
+ * node): writes exactly what avl_normals followed by avl_release_mask on its normals writes, reading the
+ * DEM once and never reading the normals back. Arguments as for those two calls (H, W >= 2, normals4
+ * 16-byte aligned, the same slope and elevation bounds and errors); normals4 and mask are outputs. */
+AVL_API int avl_normals_release_mask(const float* dem, int32_t H, int32_t W, float cell_size, float slope_min_deg,
+                                     float slope_max_deg, float z_min, float z_max, float* normals4, uint8_t* mask,
+                                     void* stream);
+
 /* Snow cover (section 5.1: from the terrain alone, with the snow line, the maximal steepness and blend
  * factors for the transition zones as parameters; the overlay is white with the blend factor as alpha).
  * alpha[i] = a_z * a_s in binary32, where a ramp over [lo, hi] is (v - lo) / (hi - lo) clamped to [0, 1]

@@ -71,6 +71,7 @@ def _load() -> ctypes.CDLL:
                                   ctypes.c_float, ctypes.c_size_t)
     L.avl_normals.argtypes = [vp, i32, i32, f32, vp, vp]
     L.avl_release_mask.argtypes = [vp, vp, i32, i32, f32, f32, f32, f32, vp, vp]
+    L.avl_normals_release_mask.argtypes = [vp, i32, i32, f32, f32, f32, f32, f32, vp, vp, vp]
     L.avl_workspace_bytes.argtypes = [i32, i32]
     L.avl_workspace_bytes.restype = sz
     L.avl_release_cells.argtypes = [vp, i32, i32, vp, vp, vp, sz, vp]
@@ -299,6 +300,20 @@ def release_mask(nrm: torch.Tensor, dem: torch.Tensor, slope_min_deg: float, slo
         _check(lib.avl_release_mask(nrm.data_ptr(), dem.data_ptr(), h, w, slope_min_deg, slope_max_deg, z_min, z_max,
                                     out.data_ptr(), _stream(dem.device)), "avl_release_mask")
     return out
+
+
+def normals_release_mask(dem: torch.Tensor, cell_size: float, slope_min_deg: float, slope_max_deg: float,
+                         z_min: float = float("-inf"), z_max: float = float("inf")) -> tuple[torch.Tensor, torch.Tensor]:
+    """normals() and release_mask() of them in one pass: ((H, W, 4) float32 normals, (H, W) uint8 map)."""
+    _need(dem, "dem", torch.float32, 2)
+    h, w = dem.shape
+    nrm = torch.empty((h, w, 4), dtype=torch.float32, device=dem.device)
+    mask = torch.empty((h, w), dtype=torch.uint8, device=dem.device)
+    with torch.cuda.device(dem.device):
+        _check(lib.avl_normals_release_mask(dem.data_ptr(), h, w, cell_size, slope_min_deg, slope_max_deg, z_min, z_max,
+                                            nrm.data_ptr(), mask.data_ptr(), _stream(dem.device)),
+               "avl_normals_release_mask")
+    return nrm, mask
 
 
 def release_cells(mask: torch.Tensor) -> tuple[torch.Tensor, torch.Tensor]:

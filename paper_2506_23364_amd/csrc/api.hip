@@ -552,6 +552,38 @@ int avl_normals(const float* dem, int32_t H, int32_t W, float cell_size, float* 
     return e == hipSuccess ? AVL_OK : hip_fail(e, "avl_normals");
 }
 
+namespace {
+// checks of the release criteria; the cosines of the slope range, taken in binary64 and rounded once
+const char* release_bounds(float slope_min_deg, float slope_max_deg, float z_min, float z_max, float* cmin,
+                           float* cmax) {
+    if (!(slope_min_deg >= 0.0f && slope_min_deg <= slope_max_deg && slope_max_deg <= 90.0f))
+        return "need 0 <= slope_min_deg <= slope_max_deg <= 90";
+    if (std::isnan(z_min) || std::isnan(z_max)) return "NaN elevation bound";
+    const double d2r = 3.14159265358979323846 / 180.0;
+    *cmin = (float)std::cos((double)slope_max_deg * d2r);
+    *cmax = (float)std::cos((double)slope_min_deg * d2r);
+    return nullptr;
+}
+}  // namespace
+
+int avl_normals_release_mask(const float* dem, int32_t H, int32_t W, float cell_size, float slope_min_deg,
+                             float slope_max_deg, float z_min, float z_max, float* normals4, uint8_t* mask,
+                             void* stream) {
+    g_last_error.clear();
+    if (!dem || !normals4 || !mask) return fail(AVL_EINVAL, "avl_normals_release_mask: null pointer");
+    if (!grid_ok(H, W, 2)) return fail(AVL_EINVAL, "avl_normals_release_mask: need H, W >= 2 and H*W < 2^31");
+    if (!finite(cell_size) || !(cell_size > 0.0f))
+        return fail(AVL_EINVAL, "avl_normals_release_mask: cell_size must be > 0");
+    if (reinterpret_cast<uintptr_t>(normals4) & 15)
+        return fail(AVL_EINVAL, "avl_normals_release_mask: normals4 not 16-byte aligned");
+    float cmin, cmax;
+    if (const char* why = release_bounds(slope_min_deg, slope_max_deg, z_min, z_max, &cmin, &cmax))
+        return fail(AVL_EINVAL, "avl_normals_release_mask: %s", why);
+    hipError_t e = avl::launch_normals_mask(dem, H, W, cell_size, cmin, cmax, z_min, z_max, normals4, mask,
+                                            static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? AVL_OK : hip_fail(e, "avl_normals_release_mask");
+}
+
 int avl_release_mask(const float* normals4, const float* dem, int32_t H, int32_t W, float slope_min_deg,
                      float slope_max_deg, float z_min, float z_max, uint8_t* mask, void* stream) {
     g_last_error.clear();
@@ -559,12 +591,9 @@ int avl_release_mask(const float* normals4, const float* dem, int32_t H, int32_t
     if (!grid_ok(H, W, 1)) return fail(AVL_EINVAL, "avl_release_mask: need H, W >= 1 and H*W < 2^31");
     if (reinterpret_cast<uintptr_t>(normals4) & 15)
         return fail(AVL_EINVAL, "avl_release_mask: normals4 not 16-byte aligned");
-    if (!(slope_min_deg >= 0.0f && slope_min_deg <= slope_max_deg && slope_max_deg <= 90.0f))
-        return fail(AVL_EINVAL, "avl_release_mask: need 0 <= slope_min_deg <= slope_max_deg <= 90");
-    if (std::isnan(z_min) || std::isnan(z_max)) return fail(AVL_EINVAL, "avl_release_mask: NaN elevation bound");
-    const double d2r = 3.14159265358979323846 / 180.0;
-    const float cmin = (float)std::cos((double)slope_max_deg * d2r);
-    const float cmax = (float)std::cos((double)slope_min_deg * d2r);
+    float cmin, cmax;
+    if (const char* why = release_bounds(slope_min_deg, slope_max_deg, z_min, z_max, &cmin, &cmax))
+        return fail(AVL_EINVAL, "avl_release_mask: %s", why);
     hipError_t e = avl::launch_release_mask(normals4, dem, (int64_t)H * W, cmin, cmax, z_min, z_max, mask,
                                             static_cast<hipStream_t>(stream));
     return e == hipSuccess ? AVL_OK : hip_fail(e, "avl_release_mask");

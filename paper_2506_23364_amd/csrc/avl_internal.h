@@ -148,6 +148,9 @@ struct LaunchShape {
 
 // ------------------------------------------------------------------ launchers (enqueue only; return hipError_t)
 hipError_t launch_normals(const float* dem, int H, int W, float cs, float* out4, hipStream_t s);
+// normals and the release map of the same texels in one pass (cmin, cmax: the cosines of the slope range)
+hipError_t launch_normals_mask(const float* dem, int H, int W, float cs, float cmin, float cmax, float zmin,
+                               float zmax, float* out4, uint8_t* mask, hipStream_t s);
 hipError_t launch_release_mask(const float* normals4, const float* dem, int64_t n, float cmin, float cmax,
                                float zmin, float zmax, uint8_t* mask, hipStream_t s);
 hipError_t launch_snow_cover(const float* normals4, const float* dem, int64_t n, float z_lo, float z_hi, float c_lo,

@@ -17,9 +17,16 @@ namespace avl {
 // n = (-gx, -gy, 1)/sqrt(gx^2 + gy^2 + 1). Each texel takes five correctly rounded divisions, two square
 // roots and an arctangent, so the pass is bound by VALU issue; a thread's four texels are independent
 // chains the compiler interleaves.
+// kMask: the release map of the same texels as well (the release-mask pass below on the nz just computed and
+// the staged height, so the map is the one that pass writes from these normals, without reading them back).
+struct MaskArgs {
+    float cmin, cmax, zmin, zmax;
+    uint8_t* mask;
+};
 constexpr int kNTX = 64, kNTY = 16, kNRows = 4;  // tile columns, tile rows, rows of threads
+template <bool kMask>
 __global__ __launch_bounds__(kNTX * kNRows) void k_normals(const float* __restrict__ dem, int H, int W, float cs,
-                                                           float cs2, float4* __restrict__ out) {
+                                                           float cs2, float4* __restrict__ out, MaskArgs m) {
     __shared__ float tile[kNTY + 2][kNTX + 2];
     const int tx = threadIdx.x & (kNTX - 1), ty = threadIdx.x / kNTX;
     const int c0 = blockIdx.x * kNTX, r0 = blockIdx.y * kNTY;
@@ -59,14 +66,27 @@ __global__ __launch_bounds__(kNTX * kNRows) void k_normals(const float* __restri
         o.z = 1.0f / l;
         o.w = atanf(sqrtf(gg)) * 57.295779513082320876798f;
         out[(size_t)r * W + c] = o;
+        if constexpr (kMask) {
+            const float z = tile[lr][lc];  // dem[r][c]: an in-grid texel is staged unclamped
+            m.mask[(size_t)r * W + c] = (m.cmin <= o.z && o.z <= m.cmax && m.zmin <= z && z <= m.zmax) ? 1 : 0;
+        }
     }
 }
 
 hipError_t launch_normals(const float* dem, int H, int W, float cs, float* out4, hipStream_t s) {
     dim3 grid((W + kNTX - 1) / kNTX, (H + kNTY - 1) / kNTY);
     const float cs2 = 2.0f * cs;
-    hipLaunchKernelGGL(k_normals, grid, dim3(kNTX * kNRows), 0, s, dem, H, W, cs, cs2,
-                       reinterpret_cast<float4*>(out4));
+    hipLaunchKernelGGL(k_normals<false>, grid, dim3(kNTX * kNRows), 0, s, dem, H, W, cs, cs2,
+                       reinterpret_cast<float4*>(out4), MaskArgs{});
+    return hipGetLastError();
+}
+
+hipError_t launch_normals_mask(const float* dem, int H, int W, float cs, float cmin, float cmax, float zmin,
+                               float zmax, float* out4, uint8_t* mask, hipStream_t s) {
+    dim3 grid((W + kNTX - 1) / kNTX, (H + kNTY - 1) / kNTY);
+    const float cs2 = 2.0f * cs;
+    hipLaunchKernelGGL(k_normals<true>, grid, dim3(kNTX * kNRows), 0, s, dem, H, W, cs, cs2,
+                       reinterpret_cast<float4*>(out4), MaskArgs{cmin, cmax, zmin, zmax, mask});
     return hipGetLastError();
 }
 

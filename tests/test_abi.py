@@ -98,6 +98,15 @@ def test_terrain_calls_reject_bad_arguments(L):
     assert lib.avl_release_mask(FAKE, FAKE, 4, 4, 30.0, 91.0, 0.0, 1.0, FAKE, None) == L.AVL_EINVAL
     assert lib.avl_release_mask(FAKE, FAKE, 4, 4, 30.0, 45.0, float("nan"), 1.0, FAKE, None) == L.AVL_EINVAL
     assert lib.avl_release_mask(None, FAKE, 4, 4, 30.0, 45.0, 0.0, 1.0, FAKE, None) == L.AVL_EINVAL
+    nrm = lib.avl_normals_release_mask
+    assert nrm(None, 4, 4, 10.0, 30.0, 45.0, 0.0, 1.0, FAKE, FAKE, None) == L.AVL_EINVAL
+    assert nrm(FAKE, 4, 4, 10.0, 30.0, 45.0, 0.0, 1.0, FAKE, None, None) == L.AVL_EINVAL
+    assert nrm(FAKE, 1, 4, 10.0, 30.0, 45.0, 0.0, 1.0, FAKE, FAKE, None) == L.AVL_EINVAL
+    assert nrm(FAKE, 4, 4, 0.0, 30.0, 45.0, 0.0, 1.0, FAKE, FAKE, None) == L.AVL_EINVAL
+    assert nrm(FAKE, 4, 4, 10.0, 30.0, 45.0, 0.0, 1.0, FAKE + 4, FAKE, None) == L.AVL_EINVAL
+    assert nrm(FAKE, 4, 4, 10.0, 40.0, 30.0, 0.0, 1.0, FAKE, FAKE, None) == L.AVL_EINVAL
+    assert nrm(FAKE, 4, 4, 10.0, 30.0, 91.0, 0.0, 1.0, FAKE, FAKE, None) == L.AVL_EINVAL
+    assert nrm(FAKE, 4, 4, 10.0, 30.0, 45.0, 0.0, float("nan"), FAKE, FAKE, None) == L.AVL_EINVAL
     assert lib.avl_release_cells(FAKE, 4, 4, FAKE, FAKE, FAKE, 10, None) == L.AVL_ENOMEM
     assert lib.avl_release_cells(None, 4, 4, FAKE, FAKE, FAKE, 1 << 20, None) == L.AVL_EINVAL
 

@@ -85,11 +85,31 @@ def test_normals_mask_cells_bitexact(avl, case):
         ref_m = oracle.release_mask(ref_n, dem, smin, smax, zmin, zmax)
         got_m = host(avl.release_mask(dev(got_n), dev(dem), smin, smax, zmin, zmax))
         assert np.array_equal(got_m, ref_m), (name, smin, smax)
+        # the one-pass call writes exactly what the two calls write
+        fn, fm = avl.normals_release_mask(dev(dem), cs, smin, smax, zmin, zmax)
+        assert np.array_equal(host(fn).view(np.uint32), got_n.view(np.uint32)), (name, "fused normals")
+        assert np.array_equal(host(fm), ref_m), (name, smin, smax, "fused mask")
         cells, n = avl.release_cells(dev(ref_m))
         n = int(host(n)[0])
         ref_c = oracle.compact(ref_m)
         assert n == len(ref_c)
         assert np.array_equal(host(cells)[:n], ref_c)
+
+
+@pytest.mark.parametrize("offset", [1, 3, 8])
+def test_release_cells_unaligned_mask(avl, offset):
+    # a mask that starts off a 16-byte boundary takes the byte-wise reads
+    rng = np.random.default_rng(offset)
+    m = (rng.random((97, 131)) < 0.3).astype(np.uint8)
+    buf = torch.zeros(m.size + offset, dtype=torch.uint8, device="cuda")
+    view = buf[offset:].view(m.shape)
+    view.copy_(torch.from_numpy(m))
+    assert view.data_ptr() % 16 != 0
+    cells, n = avl.release_cells(view)
+    n = int(host(n)[0])
+    ref = oracle.compact(m)
+    assert n == len(ref)
+    assert np.array_equal(host(cells)[:n], ref)
 
 
 @pytest.mark.parametrize("p", [0.0, 0.001, 0.5, 1.0])
