@@ -985,11 +985,17 @@ avl::SmoothArgs smooth_args(const float* dem, const float* mass, int32_t H, int3
 
 }  // namespace
 
-int avl_trajectories_smooth(const float* dem, const uint8_t* mask, const float* mass, int32_t H, int32_t W,
-                            float cell_size, const avl_params* params, uint32_t particles_per_cell,
-                            uint32_t step_limit, uint64_t seed, uint32_t run_id, int32_t max_release_cells,
-                            uint32_t flags, int64_t* deposit_q, float* deposit, int64_t* velocity_q, float* velocity,
-                            uint64_t* stats, int32_t* status, void* workspace, size_t workspace_bytes, void* stream) {
+namespace {
+// The smooth forward pass. `prepared`: the workspace already holds this mask's release cells, padded DEM,
+// start records and per-particle masses from an earlier pass with the same DEM, mask, mass and particles per
+// cell (a calibration loop, where only the friction parameters change between passes), so only the run
+// constants are set up again.
+int smooth_forward(const float* dem, const uint8_t* mask, const float* mass, int32_t H, int32_t W,
+                   float cell_size, const avl_params* params, uint32_t particles_per_cell,
+                   uint32_t step_limit, uint64_t seed, uint32_t run_id, int32_t max_release_cells,
+                   uint32_t flags, int64_t* deposit_q, float* deposit, int64_t* velocity_q, float* velocity,
+                   uint64_t* stats, int32_t* status, void* workspace, size_t workspace_bytes, void* stream,
+                   bool prepared) {
     g_last_error.clear();
     int rc = smooth_checks("avl_trajectories_smooth", dem, mask, H, W, cell_size, params, particles_per_cell,
                            step_limit, max_release_cells, workspace, workspace_bytes);
@@ -1008,7 +1014,7 @@ int avl_trajectories_smooth(const float* dem, const uint8_t* mask, const float* 
     a.vel_q = vel ? reinterpret_cast<unsigned long long*>(velocity_q) : nullptr;
     a.stats = stats ? reinterpret_cast<unsigned long long*>(stats) : sw.w.stats;
     hipError_t e;
-    if ((e = avl::launch_compact(mask, n, sw.w.cells, sw.w.n_cells, sw.w.blk, s)) != hipSuccess)
+    if (!prepared && (e = avl::launch_compact(mask, n, sw.w.cells, sw.w.n_cells, sw.w.blk, s)) != hipSuccess)
         return hip_fail(e, "avl_trajectories_smooth: compaction");
     const avl::RunSpec spec{0u, 0u, 0u, run_id, (unsigned long long)seed};
     if ((e = avl::launch_setup_runs(nullptr, nullptr, 0, spec, *params, sw.w.n_cells, 1, 1, 1, H, W, cell_size,
@@ -1023,12 +1029,13 @@ int avl_trajectories_smooth(const float* dem, const uint8_t* mask, const float* 
         if ((z = avl::launch_fill_u64(sw.w.queues, 0ull, avl::kXcds * avl::kQueueStride, s)) != hipSuccess) return z;
         return avl::launch_fill_u64(a.stats, 0ull, 4, s);
     };
-    if ((e = avl::launch_pad_dem(dem, H, W, sw.dem_pad, s)) != hipSuccess)
+    if (!prepared && (e = avl::launch_pad_dem(dem, H, W, sw.dem_pad, s)) != hipSuccess)
         return hip_fail(e, "avl_trajectories_smooth: padded DEM");
-    if ((e = avl::launch_start_records(dem, H, W, 1, sw.w.cells, sw.w.n_cells, max_release_cells, sw.starts, s)) !=
-            hipSuccess ||
-        (e = avl::launch_particle_mass(mass, sw.w.cells, sw.w.n_cells, max_release_cells, particles_per_cell, sw.mpc,
-                                       s)) != hipSuccess)
+    if (!prepared &&
+        ((e = avl::launch_start_records(dem, H, W, 1, sw.w.cells, sw.w.n_cells, max_release_cells, sw.starts, s)) !=
+             hipSuccess ||
+         (e = avl::launch_particle_mass(mass, sw.w.cells, sw.w.n_cells, max_release_cells, particles_per_cell,
+                                        sw.mpc, s)) != hipSuccess))
         return hip_fail(e, "avl_trajectories_smooth: start records");
     int variant = 0;
     if ((e = choose_smooth(smooth_key(2, n, max_release_cells, particles_per_cell, step_limit),
@@ -1043,6 +1050,17 @@ int avl_trajectories_smooth(const float* dem, const uint8_t* mask, const float* 
     if (vel && velocity && (e = avl::launch_q_to_float(a.vel_q, n, velocity, s)) != hipSuccess)
         return hip_fail(e, "avl_trajectories_smooth: velocity");
     return AVL_OK;
+}
+}  // namespace
+
+int avl_trajectories_smooth(const float* dem, const uint8_t* mask, const float* mass, int32_t H, int32_t W,
+                            float cell_size, const avl_params* params, uint32_t particles_per_cell,
+                            uint32_t step_limit, uint64_t seed, uint32_t run_id, int32_t max_release_cells,
+                            uint32_t flags, int64_t* deposit_q, float* deposit, int64_t* velocity_q, float* velocity,
+                            uint64_t* stats, int32_t* status, void* workspace, size_t workspace_bytes, void* stream) {
+    return smooth_forward(dem, mask, mass, H, W, cell_size, params, particles_per_cell, step_limit, seed, run_id,
+                          max_release_cells, flags, deposit_q, deposit, velocity_q, velocity, stats, status, workspace,
+                          workspace_bytes, stream, false);
 }
 
 int avl_trajectories_backward(const float* dem, const uint8_t* mask, const float* mass, int32_t H, int32_t W,
@@ -1333,9 +1351,10 @@ int avl_calibrate(const float* dem, const uint8_t* mask, const float* mass, int3
         avl_params p = *start;
         p.mu = (float)th[0];
         p.xi = (float)th[1];
-        if ((rc = avl_trajectories_smooth(dem, mask, mass, H, W, cell_size, &p, particles_per_cell, step_limit, seed,
-                                          run_id, max_release_cells, 0u, c.dep_q, c.dep, nullptr, nullptr, nullptr,
-                                          c.status, c.smooth, c.smooth_bytes, stream)) != AVL_OK)
+        // after the first pass the release cells, padded DEM, start records and masses are in the workspace
+        if ((rc = smooth_forward(dem, mask, mass, H, W, cell_size, &p, particles_per_cell, step_limit, seed, run_id,
+                                 max_release_cells, 0u, c.dep_q, c.dep, nullptr, nullptr, nullptr, c.status, c.smooth,
+                                 c.smooth_bytes, stream, t > 0)) != AVL_OK)
             return rc;
         hipError_t e = avl::launch_mse_grad(c.dep, target, n, cgrad, c.gD, c.part, c.scal, s);
         if (e != hipSuccess) return hip_fail(e, "avl_calibrate: loss");
