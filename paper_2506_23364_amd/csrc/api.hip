@@ -989,13 +989,15 @@ namespace {
 // The smooth forward pass. `prepared`: the workspace already holds this mask's release cells, padded DEM,
 // start records and per-particle masses from an earlier pass with the same DEM, mask, mass and particles per
 // cell (a calibration loop, where only the friction parameters change between passes), so only the run
-// constants are set up again.
+// constants are set up again. `p_dev`, `spec_dev` (nullable, together): the run constants are set up from
+// these device copies of the parameters and the run (a loop that updates the parameters on the device);
+// `params` then serves only for the host checks of the parameters the loop does not change.
 int smooth_forward(const float* dem, const uint8_t* mask, const float* mass, int32_t H, int32_t W,
                    float cell_size, const avl_params* params, uint32_t particles_per_cell,
                    uint32_t step_limit, uint64_t seed, uint32_t run_id, int32_t max_release_cells,
                    uint32_t flags, int64_t* deposit_q, float* deposit, int64_t* velocity_q, float* velocity,
                    uint64_t* stats, int32_t* status, void* workspace, size_t workspace_bytes, void* stream,
-                   bool prepared) {
+                   bool prepared, const avl_params* p_dev = nullptr, const avl::RunSpec* spec_dev = nullptr) {
     g_last_error.clear();
     int rc = smooth_checks("avl_trajectories_smooth", dem, mask, H, W, cell_size, params, particles_per_cell,
                            step_limit, max_release_cells, workspace, workspace_bytes);
@@ -1017,9 +1019,9 @@ int smooth_forward(const float* dem, const uint8_t* mask, const float* mass, int
     if (!prepared && (e = avl::launch_compact(mask, n, sw.w.cells, sw.w.n_cells, sw.w.blk, s)) != hipSuccess)
         return hip_fail(e, "avl_trajectories_smooth: compaction");
     const avl::RunSpec spec{0u, 0u, 0u, run_id, (unsigned long long)seed};
-    if ((e = avl::launch_setup_runs(nullptr, nullptr, 0, spec, *params, sw.w.n_cells, 1, 1, 1, H, W, cell_size,
-                                    particles_per_cell, false, sw.w.runs, sw.w.run_off, status, s,
-                                    max_release_cells)) != hipSuccess)
+    if ((e = avl::launch_setup_runs(p_dev ? spec_dev : nullptr, p_dev, p_dev ? 1u : 0u, spec, *params, sw.w.n_cells,
+                                    1, 1, 1, H, W, cell_size, particles_per_cell, false, sw.w.runs, sw.w.run_off,
+                                    status, s, max_release_cells)) != hipSuccess)
         return hip_fail(e, "avl_trajectories_smooth: run setup");
     auto zero = [&]() -> hipError_t {
         hipError_t z;
@@ -1063,14 +1065,15 @@ int avl_trajectories_smooth(const float* dem, const uint8_t* mask, const float* 
                           workspace_bytes, stream, false);
 }
 
-int avl_trajectories_backward(const float* dem, const uint8_t* mask, const float* mass, int32_t H, int32_t W,
-                              float cell_size, const avl_params* params, uint32_t particles_per_cell,
-                              uint32_t step_limit, uint64_t seed, uint32_t run_id, int32_t max_release_cells,
-                              const float* grad_deposit, double* dparams, float* dmass, float* per_particle,
-                              void* workspace, size_t workspace_bytes, void* stream) {
+namespace {
+// The adjoint of the pass smooth_forward left in the workspace; p_dev (nullable): xi is read from this device
+// copy of the parameters (the loop that keeps them on the device).
+int smooth_backward(const float* dem, const uint8_t* mask, const float* mass, int32_t H, int32_t W,
+                    float cell_size, const avl_params* params, uint32_t particles_per_cell,
+                    uint32_t step_limit, int32_t max_release_cells,
+                    const float* grad_deposit, double* dparams, float* dmass, float* per_particle,
+                    void* workspace, size_t workspace_bytes, void* stream, const avl_params* p_dev) {
     g_last_error.clear();
-    (void)seed;
-    (void)run_id;
     int rc = smooth_checks("avl_trajectories_backward", dem, mask, H, W, cell_size, params, particles_per_cell,
                            step_limit, max_release_cells, workspace, workspace_bytes);
     if (rc != AVL_OK) return rc;
@@ -1082,6 +1085,7 @@ int avl_trajectories_backward(const float* dem, const uint8_t* mask, const float
     avl::SmoothArgs a = smooth_args(dem, mass, H, W, cell_size, params, particles_per_cell, step_limit,
                                     max_release_cells, sw);
     a.gD = grad_deposit;
+    a.pdev = p_dev;
     hipError_t e;
     auto zero = [&]() -> hipError_t {
         hipError_t z;
@@ -1104,6 +1108,19 @@ int avl_trajectories_backward(const float* dem, const uint8_t* mask, const float
             hipSuccess)
         return hip_fail(e, "avl_trajectories_backward: copy");
     return AVL_OK;
+}
+}  // namespace
+
+int avl_trajectories_backward(const float* dem, const uint8_t* mask, const float* mass, int32_t H, int32_t W,
+                              float cell_size, const avl_params* params, uint32_t particles_per_cell,
+                              uint32_t step_limit, uint64_t seed, uint32_t run_id, int32_t max_release_cells,
+                              const float* grad_deposit, double* dparams, float* dmass, float* per_particle,
+                              void* workspace, size_t workspace_bytes, void* stream) {
+    (void)seed;
+    (void)run_id;
+    return smooth_backward(dem, mask, mass, H, W, cell_size, params, particles_per_cell, step_limit,
+                           max_release_cells, grad_deposit, dparams, dmass, per_particle, workspace, workspace_bytes,
+                           stream, nullptr);
 }
 
 int avl_trajectories_batched(const float* dems, int32_t n_tiles, const uint8_t* masks, int32_t n_masks, int32_t H,
@@ -1274,7 +1291,13 @@ struct CalibWs {
     double* part;      // loss partial sums
     double* scal;      // [loss, dL/dmu, dL/dxi, dL/dh]
     int32_t* status;   // smooth pass status
+    avl::RunSpec* spec;  // the run, on the device
+    avl_params* p;       // the current parameters, on the device
+    double* state;       // Adam's state (avl::kCalibState)
+    double* hist;        // kCalibRows history rows of 5, copied to the caller's history as they fill
+    int32_t* err;        // (first nonzero status, its iteration)
 };
+constexpr int32_t kCalibRows = 64;
 
 size_t calib_layout(int32_t H, int32_t W, int32_t max_cells, uint32_t P, uint32_t S, char* base, CalibWs* c) {
     const int64_t n = (int64_t)H * W;
@@ -1291,6 +1314,11 @@ size_t calib_layout(int32_t H, int32_t W, int32_t max_cells, uint32_t P, uint32_
     char* dm = take((size_t)n * 4);
     char* pt = take(avl::mse_partials() * sizeof(double));
     char* sc = take(4 * sizeof(double) + sizeof(int32_t));
+    char* spc = take(sizeof(avl::RunSpec));
+    char* pp = take(sizeof(avl_params));
+    char* stt = take(avl::kCalibState * sizeof(double));
+    char* hs = take((size_t)kCalibRows * 5 * sizeof(double));
+    char* er = take(2 * sizeof(int32_t));
     if (c) {
         c->smooth = base;
         c->smooth_bytes = sm;
@@ -1301,6 +1329,11 @@ size_t calib_layout(int32_t H, int32_t W, int32_t max_cells, uint32_t P, uint32_
         c->part = reinterpret_cast<double*>(pt);
         c->scal = reinterpret_cast<double*>(sc);
         c->status = reinterpret_cast<int32_t*>(sc + 4 * sizeof(double));
+        c->spec = reinterpret_cast<avl::RunSpec*>(spc);
+        c->p = reinterpret_cast<avl_params*>(pp);
+        c->state = reinterpret_cast<double*>(stt);
+        c->hist = reinterpret_cast<double*>(hs);
+        c->err = reinterpret_cast<int32_t*>(er);
     }
     return off;
 }
@@ -1341,56 +1374,61 @@ int avl_calibrate(const float* dem, const uint8_t* mask, const float* mass, int3
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int64_t n = (int64_t)H * W;
     const float cgrad = 2.0f / (float)n;
-    const double lr[2] = {(double)adam->lr_mu, (double)adam->lr_xi};
-    const double b1 = adam->beta1, b2 = adam->beta2, eps = adam->eps;
-    const double lo[2] = {(double)adam->mu_min, (double)adam->xi_min};
-    double th[2] = {(double)start->mu, (double)start->xi};
-    double m[2] = {0.0, 0.0}, v[2] = {0.0, 0.0};
-    double b1t = 1.0, b2t = 1.0;
+    // The loop stays on the device: the run constants are set up from a device copy of the parameters, the
+    // adjoint reads xi from it, and a one-thread kernel takes the Adam step in binary64 (the same arithmetic
+    // in the same order as a host loop would) and writes the history row. The host only enqueues; rows come
+    // back in blocks of kCalibRows, and a nonzero status of any pass is reported after the loop.
+    avl::AdamConsts ac;
+    ac.lr[0] = (double)adam->lr_mu;
+    ac.lr[1] = (double)adam->lr_xi;
+    ac.b1 = adam->beta1;
+    ac.b2 = adam->beta2;
+    ac.eps = adam->eps;
+    ac.lo[0] = (double)adam->mu_min;
+    ac.lo[1] = (double)adam->xi_min;
+    const avl::RunSpec spec{0u, 0u, 0u, run_id, (unsigned long long)seed};
+    hipError_t e = avl::launch_calib_init(spec, *start, c.spec, c.p, c.state, c.err, s);
+    if (e != hipSuccess) return hip_fail(e, "avl_calibrate: init");
     for (int32_t t = 0; t < n_iters; ++t) {
-        avl_params p = *start;
-        p.mu = (float)th[0];
-        p.xi = (float)th[1];
         // after the first pass the release cells, padded DEM, start records and masses are in the workspace
-        if ((rc = smooth_forward(dem, mask, mass, H, W, cell_size, &p, particles_per_cell, step_limit, seed, run_id,
-                                 max_release_cells, 0u, c.dep_q, c.dep, nullptr, nullptr, nullptr, c.status, c.smooth,
-                                 c.smooth_bytes, stream, t > 0)) != AVL_OK)
+        if ((rc = smooth_forward(dem, mask, mass, H, W, cell_size, start, particles_per_cell, step_limit, seed,
+                                 run_id, max_release_cells, 0u, c.dep_q, c.dep, nullptr, nullptr, nullptr, c.status,
+                                 c.smooth, c.smooth_bytes, stream, t > 0, c.p, c.spec)) != AVL_OK)
             return rc;
-        hipError_t e = avl::launch_mse_grad(c.dep, target, n, cgrad, c.gD, c.part, c.scal, s);
-        if (e != hipSuccess) return hip_fail(e, "avl_calibrate: loss");
-        if ((rc = avl_trajectories_backward(dem, mask, mass, H, W, cell_size, &p, particles_per_cell, step_limit, seed,
-                                            run_id, max_release_cells, c.gD, c.scal + 1, c.dmass, nullptr, c.smooth,
-                                            c.smooth_bytes, stream)) != AVL_OK)
+        if ((e = avl::launch_mse_grad(c.dep, target, n, cgrad, c.gD, c.part, c.scal, s)) != hipSuccess)
+            return hip_fail(e, "avl_calibrate: loss");
+        if ((rc = smooth_backward(dem, mask, mass, H, W, cell_size, start, particles_per_cell, step_limit,
+                                  max_release_cells, c.gD, c.scal + 1, c.dmass, nullptr, c.smooth, c.smooth_bytes,
+                                  stream, c.p)) != AVL_OK)
             return rc;
-        struct {
-            double v[4];
-            int32_t status;
-        } h{};
-        if ((e = hipMemcpyAsync(&h, c.scal, 4 * sizeof(double) + sizeof(int32_t), hipMemcpyDeviceToHost, s)) !=
-                hipSuccess ||
-            (e = hipStreamSynchronize(s)) != hipSuccess)
-            return hip_fail(e, "avl_calibrate: read back");
-        if (h.status != 0)
-            return fail(AVL_EINVAL, "%s: the mask has more release cells than max_release_cells", where);
-        double* row = history + 5 * (int64_t)t;
-        row[0] = h.v[0];
-        row[1] = th[0];
-        row[2] = th[1];
-        row[3] = h.v[1];
-        row[4] = h.v[2];
-        // Adam (Kingma and Ba 2015, algorithm 1), bias corrections from running products of the rates
-        b1t *= b1;
-        b2t *= b2;
-        for (int k = 0; k < 2; ++k) {
-            const double g = h.v[1 + k];
-            m[k] = b1 * m[k] + (1.0 - b1) * g;
-            v[k] = b2 * v[k] + (1.0 - b2) * (g * g);
-            const double mh = m[k] / (1.0 - b1t);
-            const double vh = v[k] / (1.0 - b2t);
-            th[k] = th[k] - lr[k] * mh / (std::sqrt(vh) + eps);
-            if (th[k] < lo[k]) th[k] = lo[k];
+        const int32_t slot = t % kCalibRows;
+        if ((e = avl::launch_adam_step(c.scal, c.status, c.state, c.p, c.hist + 5 * slot, ac, t, c.err, s)) !=
+            hipSuccess)
+            return hip_fail(e, "avl_calibrate: step");
+        if (slot == kCalibRows - 1 || t == n_iters - 1) {
+            // stream-ordered before the next step overwrites the rows
+            if ((e = hipMemcpyAsync(history + 5 * (int64_t)(t - slot), c.hist, (size_t)(slot + 1) * 5 * sizeof(double),
+                                    hipMemcpyDeviceToHost, s)) != hipSuccess)
+                return hip_fail(e, "avl_calibrate: history");
         }
     }
+    struct {
+        double st[avl::kCalibState];
+        int32_t err[2];
+    } h{};
+    h.st[0] = (double)start->mu;
+    h.st[1] = (double)start->xi;
+    if (n_iters > 0 &&
+        ((e = hipMemcpyAsync(h.st, c.state, sizeof(h.st), hipMemcpyDeviceToHost, s)) != hipSuccess ||
+         (e = hipMemcpyAsync(h.err, c.err, sizeof(h.err), hipMemcpyDeviceToHost, s)) != hipSuccess ||
+         (e = hipStreamSynchronize(s)) != hipSuccess))
+        return hip_fail(e, "avl_calibrate: read back");
+    if (h.err[0] == 3)
+        return fail(AVL_EINVAL, "%s: the mask has more release cells than max_release_cells", where);
+    if (h.err[0] != 0)
+        return fail(AVL_EINVAL, "%s: the parameters of iteration %d are invalid (status %d)", where, h.err[1],
+                    h.err[0]);
+    const double th[2] = {h.st[0], h.st[1]};
     *result = *start;
     result->mu = (float)th[0];
     result->xi = (float)th[1];

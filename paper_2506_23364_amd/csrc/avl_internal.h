@@ -236,6 +236,7 @@ struct SmoothArgs {
     const StartRec* starts;                 // per release cell: the start state of its particles
     const float* mpc;                       // per release cell: the mass of each of its particles
     DivU32 pdiv;                            // slot -> release cell (division by the particles per cell)
+    const ::avl_params* pdev;               // nullable: the adjoint reads xi here (a device-side loop) not from .xi
 };
 
 
@@ -259,6 +260,20 @@ hipError_t launch_particle_mass(const float* mass, const int32_t* cells, const i
 hipError_t launch_mse_grad(const float* dep, const float* target, int64_t n, float c, float* gD, double* part,
                            double* loss, hipStream_t s);
 size_t mse_partials();
+
+// Device side of the calibration loop. State: th_mu, th_xi, m_mu, m_xi, v_mu, v_xi, beta1^t, beta2^t (binary64).
+struct AdamConsts {
+    double lr[2], b1, b2, eps, lo[2];
+};
+constexpr int kCalibState = 8;
+// writes the run spec, the parameters and the initial state (th = the start's mu, xi; m = v = 0; products 1)
+hipError_t launch_calib_init(RunSpec spec, ::avl_params start, RunSpec* spec_dev, ::avl_params* p_dev, double* state,
+                             int32_t* err, hipStream_t s);
+// one Adam step from scal = [loss, dL/dmu, dL/dxi, dL/dh]: writes the history row (loss, mu, xi, dL/dmu, dL/dxi,
+// before the step), updates the state and the parameters; the first iteration whose pass reported a nonzero
+// status is kept in err = (status, iteration)
+hipError_t launch_adam_step(const double* scal, const int32_t* status, double* state, ::avl_params* p_dev,
+                            double* row, AdamConsts c, int32_t t, int32_t* err, hipStream_t s);
 hipError_t launch_finalize_vmax(uint32_t* vmax_bits, int64_t n, hipStream_t s);
 
 // Persistent-grid shape of kernel variant `variant` on the current device; number of variants.

@@ -386,6 +386,7 @@ __global__ __launch_bounds__(kSmoothBlock) void k_smooth_backward(SmoothArgs a) 
     const size_t gtid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     const size_t cplane = (size_t)a.C * a.cap;
     const float g2dl = a.g2dl;
+    const float xi = a.pdev ? a.pdev->xi : a.xi;  // a device-side loop keeps the parameters on the device
     Dispenser disp;
     {
         const uint64_t total = wave_bcast64(a.run_off[1]);
@@ -498,7 +499,7 @@ __global__ __launch_bounds__(kSmoothBlock) void k_smooth_backward(SmoothArgs a) 
                         const float aa = e.x, v2n = e.y;
                         const float op = 1.0f + aa;
                         dmu = dmu - lam * (g2dl / op);
-                        dxi = dxi + lam * ((v2n * aa) / (a.xi * op));
+                        dxi = dxi + lam * ((v2n * aa) / (xi * op));
                         dh = dh + lam * ((v2n * aa) / (a.h * op));
                         lam = lam / op;
                     }
@@ -626,6 +627,61 @@ hipError_t launch_mse_grad(const float* dep, const float* target, int64_t n, flo
 }
 
 size_t mse_partials() { return kMseBlocks; }
+
+// ------------------------------------------------------------------------------------------ calibration loop
+// Adam (Kingma and Ba 2015, algorithm 1) on (mu, xi) in binary64, one thread: the host loop's arithmetic in
+// its order (bias corrections from running products of the rates, the step clamped at the lower bounds), so
+// a loop that stays on the device takes the same steps.
+__global__ void k_calib_init(RunSpec spec, ::avl_params start, RunSpec* __restrict__ spec_dev,
+                             ::avl_params* __restrict__ p_dev, double* __restrict__ st, int32_t* __restrict__ err) {
+    *spec_dev = spec;
+    *p_dev = start;
+    st[0] = (double)start.mu;
+    st[1] = (double)start.xi;
+    st[2] = st[3] = st[4] = st[5] = 0.0;
+    st[6] = st[7] = 1.0;
+    err[0] = err[1] = 0;
+}
+
+__global__ void k_adam_step(const double* __restrict__ scal, const int32_t* __restrict__ status,
+                            double* __restrict__ st, ::avl_params* __restrict__ p, double* __restrict__ row,
+                            AdamConsts c, int32_t t, int32_t* __restrict__ err) {
+    if (*status != 0 && err[0] == 0) {
+        err[0] = *status;
+        err[1] = t;
+    }
+    row[0] = scal[0];
+    row[1] = st[0];
+    row[2] = st[1];
+    row[3] = scal[1];
+    row[4] = scal[2];
+    st[6] *= c.b1;
+    st[7] *= c.b2;
+    for (int k = 0; k < 2; ++k) {
+        const double g = scal[1 + k];
+        st[2 + k] = c.b1 * st[2 + k] + (1.0 - c.b1) * g;
+        st[4 + k] = c.b2 * st[4 + k] + (1.0 - c.b2) * (g * g);
+        const double mh = st[2 + k] / (1.0 - st[6]);
+        const double vh = st[4 + k] / (1.0 - st[7]);
+        double th = st[k] - c.lr[k] * mh / (sqrt(vh) + c.eps);
+        if (th < c.lo[k]) th = c.lo[k];
+        st[k] = th;
+    }
+    p->mu = (float)st[0];
+    p->xi = (float)st[1];
+}
+
+hipError_t launch_calib_init(RunSpec spec, ::avl_params start, RunSpec* spec_dev, ::avl_params* p_dev, double* state,
+                             int32_t* err, hipStream_t s) {
+    hipLaunchKernelGGL(k_calib_init, dim3(1), dim3(1), 0, s, spec, start, spec_dev, p_dev, state, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam_step(const double* scal, const int32_t* status, double* state, ::avl_params* p_dev,
+                            double* row, AdamConsts c, int32_t t, int32_t* err, hipStream_t s) {
+    hipLaunchKernelGGL(k_adam_step, dim3(1), dim3(1), 0, s, scal, status, state, p_dev, row, c, t, err);
+    return hipGetLastError();
+}
 
 // ------------------------------------------------------------------------------------------ launchers
 

@@ -9,6 +9,8 @@
 * runout angle: one batched call sweeping tan(alpha) (off, 0.3 ... 0.6) over one release scenario equals
   the oracle run by run, and a larger angle never lengthens the runout (fewer visited cells and steps).
 """
+import math
+
 import numpy as np
 import pytest
 import torch
@@ -67,6 +69,41 @@ def test_calibration_history_matches_oracle(avl, scene):
     compare(hist, ref, "calibration P=4")
     assert res.mu == f32(mu_r) and res.xi == f32(xi_r)
     assert res.persistence == f32(0.9) and res.flow_height == f32(c.flow_height)
+
+
+def test_calibration_history_over_several_row_blocks(avl, scene):
+    # 150 iterations: the loop keeps its history in blocks of 64 rows on the device; every row must land at
+    # its place and the Adam state must carry over the block boundaries. Each row's (mu, xi) is the Adam step
+    # (binary64, the library's order of operations) from the rows before it, and the first rows equal those
+    # of a shorter run.
+    c, base = scene
+    P, S, iters = 2, 200, 150
+    target = target_for(c, base, P)
+    start = avl.Params.make(**dict(base, mu=f32(c.mu0), xi=f32(c.xi0)))
+    adam = avl.Adam.make(lr_mu=0.003, lr_xi=30.0)
+    hist, res = avl.calibrate(dev(c.dem), dev(c.mask), c.cell_size, start, P, S, c.seed, dev(target), iters, adam,
+                              mass=dev(c.mass))
+    short, _ = avl.calibrate(dev(c.dem), dev(c.mask), c.cell_size, start, P, S, c.seed, dev(target), 8, adam,
+                             mass=dev(c.mass))
+    assert hist.shape == (iters, 5) and np.isfinite(hist).all()
+    assert np.array_equal(hist[:8], short)
+    lr = (float(np.float32(adam.lr_mu)), float(np.float32(adam.lr_xi)))
+    b1, b2, eps = float(np.float32(adam.beta1)), float(np.float32(adam.beta2)), float(np.float32(adam.eps))
+    lo = (float(np.float32(adam.mu_min)), float(np.float32(adam.xi_min)))
+    th = [float(np.float32(start.mu)), float(np.float32(start.xi))]
+    m, v, b1t, b2t = [0.0, 0.0], [0.0, 0.0], 1.0, 1.0
+    for t in range(iters):
+        assert hist[t, 1] == th[0] and hist[t, 2] == th[1], t
+        b1t *= b1
+        b2t *= b2
+        for k in range(2):
+            g = float(hist[t, 3 + k])
+            m[k] = b1 * m[k] + (1.0 - b1) * g
+            v[k] = b2 * v[k] + (1.0 - b2) * (g * g)
+            mh = m[k] / (1.0 - b1t)
+            vh = v[k] / (1.0 - b2t)
+            th[k] = max(th[k] - lr[k] * mh / (math.sqrt(vh) + eps), lo[k])
+    assert res.mu == f32(th[0]) and res.xi == f32(th[1])
 
 
 def test_calibration_zero_iterations(avl, scene):
