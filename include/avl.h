@@ -305,7 +305,8 @@ AVL_API int avl_trajectories_backward(const float* dem, const uint8_t* mask, con
  * the use the smooth variant and its adjoint exist for. Each iteration runs avl_trajectories_smooth at the
  * current (mu, xi) rounded to binary32, the loss L = sum (D - T)^2 / N over the H*W deposit D (the fixed
  * point raster as float) and its gradient dL/dD = c (D - T) with c = 2/N in binary32 (L summed in binary64
- * in a fixed order), then avl_trajectories_backward, and updates (mu, xi) in binary64 on the host:
+ * in a fixed order), then avl_trajectories_backward, and updates (mu, xi) in binary64 (on the device, one
+ * thread, in this order of operations):
  *   m <- b1 m + (1 - b1) g;  v <- b2 v + (1 - b2) g^2;  theta <- theta - lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps),
  * then clamps mu >= mu_min and xi >= xi_min. The other parameters stay those of *start. */
 typedef struct avl_adam {
@@ -316,16 +317,17 @@ typedef struct avl_adam {
 } avl_adam;
 
 /* Workspace bytes avl_calibrate needs (0 if an argument is out of range): the smooth pass's workspace plus
- * the deposit, its gradient and the reductions. */
+ * the deposit, its gradient, the reductions, the parameters, the optimiser state and 64 history rows. */
 AVL_API size_t avl_calibrate_workspace_bytes(int32_t H, int32_t W, int32_t max_release_cells,
                                              uint32_t particles_per_cell, uint32_t step_limit);
 
 /* n_iters Adam iterations from (start->mu, start->xi) (start->xi finite). target: H*W float deposit on the
  * device. history (host, nullable when n_iters = 0): n_iters rows of 5 doubles, (L, mu, xi, dL/dmu, dL/dxi)
  * at each iterate before its update. result (host): *start with the final mu and xi (binary32). The other
- * arguments are those of avl_trajectories_smooth. The call waits for the stream once per iteration (the
- * update needs the gradient on the host). A mask with more release cells than max_release_cells returns
- * AVL_EINVAL after the first iteration. */
+ * arguments are those of avl_trajectories_smooth. The parameters, the optimiser state and the rows stay on
+ * the device: the host enqueues the iterations without waiting, the rows are copied back 64 at a time, and
+ * the call waits for the stream once at the end. A mask with more release cells than max_release_cells, or
+ * an iterate the run setup rejects, returns AVL_EINVAL after the loop (history then unspecified). */
 AVL_API int avl_calibrate(const float* dem, const uint8_t* mask, const float* mass, int32_t H, int32_t W,
                           float cell_size, const avl_params* start, uint32_t particles_per_cell, uint32_t step_limit,
                           uint64_t seed, uint32_t run_id, int32_t max_release_cells, const float* target,
