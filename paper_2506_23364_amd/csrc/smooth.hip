@@ -93,13 +93,11 @@ __device__ __forceinline__ StepOut step(State& s, uint32_t n, uint32_t rep, uint
     }
     o.x1 = s.x + rc.L * s.dx;
     o.y1 = s.y + rc.L * s.dy;
-    o.num = 0.0f;
-    o.a = 0.0f;
+    // Every lane runs the whole step and the outcome selects what it keeps (no branch per outcome, so the
+    // compiler copies no state at their joins): a target off the grid is read through the buffer's bounds
+    // check, which cannot fault; its values are discarded.
     const float fc1 = floorf(o.x1), fr1 = floorf(o.y1);
-    if (!(fc1 >= 0.0f && fc1 < (float)W && fr1 >= 0.0f && fr1 < (float)H)) {
-        o.outcome = kExit;
-        return o;
-    }
+    const bool inb = fc1 >= 0.0f && fc1 < (float)W && fr1 >= 0.0f && fr1 < (float)H;
     const Sample s1 = sample(dem, o.x1, o.y1);
     const float dz = s.z - s1.z;
     // dl2 + dz^2 >= dl2: with dl2 >= 2^-96 (a run constant) no lane needs the small-argument check
@@ -108,27 +106,25 @@ __device__ __forceinline__ StepOut step(State& s, uint32_t n, uint32_t rep, uint
         ds = sqrt_rn_big(rc.dl2 + dz * dz);
     else
         ds = sqrt_rn(rc.dl2 + dz * dz);
-    o.num = s.v2 + g2 * (dz - rc.mdl);
-    if (!(o.num > 0.0f)) {
-        o.outcome = kStop;
-        return o;
-    }
-    o.a = rc.cd * ds;
-    const float v2n = o.num / (1.0f + o.a);
+    const float num = s.v2 + g2 * (dz - rc.mdl);
+    const bool pos = num > 0.0f;
+    const float aa = rc.cd * ds;
+    const float v2n = num / (1.0f + aa);
+    bool angle = false;
     if (rc.use_alpha) {
         const float hx = o.x1 - s.x0, hy = o.y1 - s.y0;
-        if ((s.zr - s1.z) < rc.tca * sqrtf(hx * hx + hy * hy)) {
-            o.outcome = kAngle;
-            return o;
-        }
+        angle = (s.zr - s1.z) < rc.tca * sqrtf(hx * hx + hy * hy);
     }
-    s.x = o.x1;
-    s.y = o.y1;
-    s.z = s1.z;
-    s.gx = s1.gx;
-    s.gy = s1.gy;
-    s.v2 = v2n;
-    o.outcome = kAccept;
+    o.num = inb ? num : 0.0f;
+    o.a = (inb && pos) ? aa : 0.0f;
+    o.outcome = !inb ? kExit : (!pos ? kStop : (angle ? kAngle : kAccept));
+    const bool acc = inb && pos && !angle;
+    s.x = acc ? o.x1 : s.x;
+    s.y = acc ? o.y1 : s.y;
+    s.z = acc ? s1.z : s.z;
+    s.gx = acc ? s1.gx : s.gx;
+    s.gy = acc ? s1.gy : s.gy;
+    s.v2 = acc ? v2n : s.v2;
     return o;
 }
 
