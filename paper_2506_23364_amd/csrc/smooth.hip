@@ -26,7 +26,8 @@ namespace {
 
 constexpr uint32_t kCkpt = 64;        // steps between checkpoints (even: segments start on even steps)
 constexpr int kSmoothBlock = 256;
-constexpr int kBackwardGrid = 1024;   // blocks of the adjoint kernel (its scratch is sized for this)
+constexpr int kBackwardGrid = 1536;   // blocks of the adjoint kernel (its scratch is sized for this): six waves
+                                      // per SIMD; 1024 (four) left the long paths' recompute short of waves
 constexpr int kReduceChunk = 4096;    // particles per block of the gradient reduction
 static_assert(kCkpt % 2 == 0, "segments must start on even steps (one Philox block serves two steps)");
 
