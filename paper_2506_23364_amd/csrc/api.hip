@@ -1389,27 +1389,33 @@ int avl_calibrate(const float* dem, const uint8_t* mask, const float* mass, int3
     const avl::RunSpec spec{0u, 0u, 0u, run_id, (unsigned long long)seed};
     hipError_t e = avl::launch_calib_init(spec, *start, c.spec, c.p, c.state, c.err, s);
     if (e != hipSuccess) return hip_fail(e, "avl_calibrate: init");
+    // an error inside the loop returns only after the stream has drained: history rows copied earlier in
+    // the loop may still be on their way into the caller's buffer
+    auto drained = [&](int code) {
+        (void)hipStreamSynchronize(s);
+        return code;
+    };
     for (int32_t t = 0; t < n_iters; ++t) {
         // after the first pass the release cells, padded DEM, start records and masses are in the workspace
         if ((rc = smooth_forward(dem, mask, mass, H, W, cell_size, start, particles_per_cell, step_limit, seed,
                                  run_id, max_release_cells, 0u, c.dep_q, c.dep, nullptr, nullptr, nullptr, c.status,
                                  c.smooth, c.smooth_bytes, stream, t > 0, c.p, c.spec)) != AVL_OK)
-            return rc;
+            return drained(rc);
         if ((e = avl::launch_mse_grad(c.dep, target, n, cgrad, c.gD, c.part, c.scal, s)) != hipSuccess)
-            return hip_fail(e, "avl_calibrate: loss");
+            return drained(hip_fail(e, "avl_calibrate: loss"));
         if ((rc = smooth_backward(dem, mask, mass, H, W, cell_size, start, particles_per_cell, step_limit,
                                   max_release_cells, c.gD, c.scal + 1, c.dmass, nullptr, c.smooth, c.smooth_bytes,
                                   stream, c.p)) != AVL_OK)
-            return rc;
+            return drained(rc);
         const int32_t slot = t % kCalibRows;
         if ((e = avl::launch_adam_step(c.scal, c.status, c.state, c.p, c.hist + 5 * slot, ac, t, c.err, s)) !=
             hipSuccess)
-            return hip_fail(e, "avl_calibrate: step");
+            return drained(hip_fail(e, "avl_calibrate: step"));
         if (slot == kCalibRows - 1 || t == n_iters - 1) {
             // stream-ordered before the next step overwrites the rows
             if ((e = hipMemcpyAsync(history + 5 * (int64_t)(t - slot), c.hist, (size_t)(slot + 1) * 5 * sizeof(double),
                                     hipMemcpyDeviceToHost, s)) != hipSuccess)
-                return hip_fail(e, "avl_calibrate: history");
+                return drained(hip_fail(e, "avl_calibrate: history"));
         }
     }
     struct {
@@ -1422,7 +1428,7 @@ int avl_calibrate(const float* dem, const uint8_t* mask, const float* mass, int3
         ((e = hipMemcpyAsync(h.st, c.state, sizeof(h.st), hipMemcpyDeviceToHost, s)) != hipSuccess ||
          (e = hipMemcpyAsync(h.err, c.err, sizeof(h.err), hipMemcpyDeviceToHost, s)) != hipSuccess ||
          (e = hipStreamSynchronize(s)) != hipSuccess))
-        return hip_fail(e, "avl_calibrate: read back");
+        return drained(hip_fail(e, "avl_calibrate: read back"));
     if (h.err[0] == 3)
         return fail(AVL_EINVAL, "%s: the mask has more release cells than max_release_cells", where);
     if (h.err[0] != 0)
