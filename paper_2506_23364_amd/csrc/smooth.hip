@@ -322,7 +322,7 @@ __global__ __launch_bounds__(kBlk) void k_smooth_forward(SmoothArgs a) {
             end_particle(kEndLimit);
             continue;
         }
-        if (n % kCkpt == 0) {
+        if (n != 0 && n % kCkpt == 0) {  // checkpoint 0 is the release cell's start record
             const size_t at = (size_t)(n / kCkpt) * a.cap + slot_id;
             a.ck[at] = s.x;
             a.ck[cplane + at] = s.y;
@@ -415,7 +415,7 @@ __global__ __launch_bounds__(kSmoothBlock) void k_smooth_backward(SmoothArgs a) 
                 s.x0 = st.x;
                 s.y0 = st.y;
                 s.zr = st.z;
-                if (c < 0) {
+                if (c <= 0) {  // the release (checkpoint 0 is the start record, v^2 = 0)
                     s.x = st.x;
                     s.y = st.y;
                     s.z = st.z;
